@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark: pair-interaction throughput of the 2D self-gravitating model.
+
+Workload: N = 262,144 particles, eps = 1e-3, positions uniform in the unit disk,
+momenta Gaussian (sigma = 0.5) with zero total momentum (seed 3), dt = 0.01.
+A step is one fourth-order Yoshida step (three all-pairs force evaluations);
+the timed region is `--steps` consecutive steps in one md_step call, with the
+state resident in HBM.  Throughput = 3 N^2 pair interactions per step (self
+pairs included, as in the paper's tiles) / elapsed time.
+
+The headline line is the mixed form (FP32 pair arithmetic, FP32 partials folded
+into FP64 per j-tile).  The FP64 form is timed beside it on the same steps, and
+the relative energy error |E - E0| / |E0| (and the better conditioned
+|E - E0| / (K0 + |V0|)) is reported for both; the mixed figure counts only if
+its error is <= 1e-5.
+
+Also reported: the pair kernel's fraction of the FP32 VALU peak (roofline), and
+the FP64 CPU oracle's pair throughput on a bounded sample of force rows of the
+same configuration (cpu_baseline).
+
+Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-fp64] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gpair-interactions/s (2D gravity N=262144), mixed vs FP64 at dE/E<=1e-5"
+N = 262_144
+EPS = 1e-3
+DT = 0.01
+SEED = 3
+SIGMA = 0.5
+FLOPS_PER_PAIR = 10          # 2 sub, 2 FMA (r^2 + eps), 2 FMA (accumulate); plus one reciprocal
+PEAK_FP32_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32 (packed FP32 is not used)
+PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PAIR_KERNEL_SRC = os.path.join(ROOT, "paper_1212_0262_amd", "csrc", "pair.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "grav2d_pair_mixed_n262144_pmc.txt")
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pair_kernel_hash() -> str:
+    with open(PAIR_KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per pair-kernel launch from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != pair_kernel_hash():
+        return None
+    return float(b.group(1))
+
+
+def run_variant(md, torch, prec, q0, p0, steps, warmup):
+    """Time `steps` Yoshida steps of one precision form; returns a result dict."""
+    stream = torch.cuda.current_stream()
+    ctx = md.md_init(md.GRAV2D, prec, N, EPS, stream=stream)
+    q = torch.from_numpy(q0).cuda()
+    p = torch.from_numpy(p0).cuda()
+    f = torch.empty_like(q)
+    e0 = md.md_energy(ctx, q, p).cpu().numpy()
+    md.md_force(ctx, q, f)
+    if warmup > 0:  # warm up on a copy so the timed run starts from the initial state
+        qw, pw, fw = q.clone(), p.clone(), f.clone()
+        md.md_step(ctx, qw, pw, fw, DT, warmup)
+        del qw, pw, fw
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    md.md_step(ctx, q, p, f, DT, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    e1 = md.md_energy(ctx, q, p).cpu().numpy()
+    tiles = md.md_get_tiles(ctx)
+    ctx.close()
+    pairs = 3.0 * N * N * steps
+    return {
+        "ms_total": ms, "wall_s": wall, "ms_per_step": ms / steps,
+        "gpairs_per_s": pairs / (ms * 1e-3) / 1e9,
+        "pair_launches": 3 * steps,
+        "pair_ms_avg": ms / (3 * steps),  # upper bound: includes the O(N) update kernels and gaps
+        "E0": e0.tolist(), "E1": e1.tolist(),
+        "dE_E": abs(e1[2] - e0[2]) / abs(e0[2]),
+        "dE_KV": abs(e1[2] - e0[2]) / (abs(e0[0]) + abs(e0[1])),
+        "tiles": list(tiles), "final_q": q, "final_p": p,
+    }
+
+
+def cpu_baseline(q0, target_s: float = 10.0):
+    """FP64 oracle pair throughput on sampled force rows of the same configuration."""
+    import numpy as np
+
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    used = oracle.get_threads()
+    rng = np.random.default_rng(0)
+    rows = rng.choice(N, size=32, replace=False)
+    t0 = time.perf_counter()
+    oracle.force_rows(oracle.GRAV2D, q0, rows, EPS)
+    dt = time.perf_counter() - t0
+    nrows = int(min(N, max(32, 32 * target_s / max(dt, 1e-6))))
+    rows = rng.choice(N, size=nrows, replace=False)
+    t0 = time.perf_counter()
+    oracle.force_rows(oracle.GRAV2D, q0, rows, EPS)
+    dt = time.perf_counter() - t0
+    return {
+        "value": nrows * N / dt / 1e9, "unit": "Gpair-interactions/s", "cores": used, "kind": "oracle",
+        "sample": f"one FP64 force evaluation on {nrows} sampled rows x {N} particles "
+                  f"({nrows * N:.3e} pairs, {dt:.1f} s, {used} threads)",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1212_0262_amd import inputs, md
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    md.load()
+    q0, p0 = inputs.grav2d_disk(N, seed=SEED, sigma=SIGMA)
+
+    log(f"bench: mixed N={N} steps={args.steps} warmup={args.warmup}")
+    mixed = run_variant(md, torch, md.MIXED, q0, p0, args.steps, args.warmup)
+    log(f"bench: mixed {mixed['gpairs_per_s']:.1f} Gpairs/s, {mixed['ms_per_step']:.2f} ms/step, "
+        f"dE/E={mixed['dE_E']:.2e}")
+    fp64 = None
+    if not args.no_fp64:
+        log("bench: fp64")
+        fp64 = run_variant(md, torch, md.FP64, q0, p0, args.steps, args.warmup)
+        log(f"bench: fp64 {fp64['gpairs_per_s']:.1f} Gpairs/s, {fp64['ms_per_step']:.2f} ms/step, "
+            f"dE/E={fp64['dE_E']:.2e}")
+    cpu = None
+    if not args.no_cpu:
+        log("bench: cpu baseline (oracle)")
+        cpu = cpu_baseline(q0)
+        log(f"bench: cpu {cpu['value']:.3f} Gpairs/s on {cpu['cores']} threads")
+
+    achieved = FLOPS_PER_PAIR * N * N / (mixed["pair_ms_avg"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(mixed["gpairs_per_s"], 3),
+        "unit": "Gpair-interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": "grav2d uniform disk N=262144 eps=1e-3 dt=0.01 sigma=0.5 seed=3 (mixed: FP32 pairs, "
+                        "FP64 fold per j-tile)",
+            "model": "grav2d", "n": N, "eps": EPS, "dt": DT, "precision": "mixed",
+            "tiles_ipl_waves_jsplit_jtile": mixed["tiles"],
+        },
+        "roofline": {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_from_profile(),
+            "kernel": "k_pair_2d<float, AccTile, ipl>",
+            "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": N * N,
+            "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
+        },
+        "energy": {
+            "mixed_dE_E": mixed["dE_E"], "mixed_dE_over_K0_plus_absV0": mixed["dE_KV"],
+            "E0": mixed["E0"], "gate_dE_E_le_1e-5": bool(mixed["dE_E"] <= 1e-5),
+        },
+        "cpu_baseline": cpu,
+    }
+    if fp64 is not None:
+        dq = (mixed["final_q"] - fp64["final_q"]).abs().max().item()
+        dp = (mixed["final_p"] - fp64["final_p"]).abs().max().item()
+        out["fp64"] = {
+            "value": round(fp64["gpairs_per_s"], 3), "ms_per_step": round(fp64["ms_per_step"], 4),
+            "dE_E": fp64["dE_E"], "dE_over_K0_plus_absV0": fp64["dE_KV"],
+            "pair_tflops": round(FLOPS_PER_PAIR * N * N / (fp64["pair_ms_avg"] * 1e-3) / 1e12, 3),
+            "frac_fp64_peak": round(FLOPS_PER_PAIR * N * N / (fp64["pair_ms_avg"] * 1e-3) / 1e12
+                                    / PEAK_FP64_TFLOPS, 4),
+        }
+        out["mixed_vs_fp64"] = {
+            "speedup": round(mixed["gpairs_per_s"] / fp64["gpairs_per_s"], 3),
+            "energy_diff_over_K0_plus_absV0": abs(mixed["E1"][2] - fp64["E1"][2])
+            / (abs(fp64["E0"][0]) + abs(fp64["E0"][1])),
+            "max_abs_dq": dq, "max_abs_dp": dp,
+        }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

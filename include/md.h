@@ -1,0 +1,184 @@
+/*
+ * md.h -- C ABI of libmd, the MI355X (gfx950) force engine for long-range
+ * molecular dynamics (T. M. Rocha Filho, "Molecular dynamics for long-range
+ * interacting systems on Graphic Processing Units").
+ *
+ * What the library computes
+ *   The force evaluation inside the fourth-order Yoshida symplectic integrator
+ *   (Sec. 3, eq. 4) for the three models of Sec. 2, unit masses, 1/N coupling:
+ *     MD_RING    eq. 1: V = -(1/N) sum_{i<j} 1/(sqrt2 sqrt(1 - cos(ti - tj) + eps))
+ *                force: the all-pairs sum of eqs. 8-9 (Sec. 3.2), taken as
+ *                -dV/dtheta_i (the sign printed in eqs. 8-9 is +dV/dtheta_i).
+ *     MD_HMF     eq. 2: V = (1/N) sum_{i<j} [1 - cos(ti - tj)], evaluated in O(N)
+ *                through the magnetization (Sec. 3.1, eqs. 5-7).
+ *     MD_GRAV2D  eq. 3: V = (1/N) sum_{i<j} log(|r_i - r_j|^2 + eps); force
+ *                -(2/N) sum_j (r_i - r_j)/(|r_i - r_j|^2 + eps), the all-pairs
+ *                sum of Sec. 3.2 (natural logarithm).
+ *
+ * Data layout (every array argument)
+ *   Device pointers to contiguous FP64 structure-of-arrays [d][n]: d = 1 for
+ *   MD_RING and MD_HMF (angle theta, momentum p_theta), d = 2 for MD_GRAV2D
+ *   (x row of n values, then y row; px then py).  f has the shape of q.
+ *   Pointers must be 8-byte aligned (torch allocations are 256-byte aligned).
+ *
+ * Ownership
+ *   The caller owns q, p, f, the energy output and the workspace (sized by
+ *   md_workspace_bytes).  The library owns only the host-side context; it never
+ *   allocates device memory.  The workspace must stay alive and untouched by the
+ *   caller for the life of the context.
+ *
+ * Streams and synchronisation
+ *   Every call only enqueues kernels on the HIP stream given to md_init (NULL =
+ *   the legacy default stream) and returns without waiting; results are ready
+ *   once that stream has reached them.  No call allocates or synchronises the
+ *   host, so calls may be captured into a HIP graph.
+ *
+ * Errors
+ *   Every function returns an md_status; nothing is thrown across the ABI.
+ *   Arguments are validated before anything is enqueued, so a call that returns
+ *   MD_EINVAL, MD_ESTATE or MD_EUNSUPPORTED has changed nothing.  A launch failure
+ *   returns MD_EDEVICE; md_last_error gives the detail.  A context is not
+ *   thread-safe; distinct contexts are independent.
+ *
+ * Determinism
+ *   Same device, same inputs, same tile configuration: bitwise-identical
+ *   outputs (fixed reduction trees, no floating-point atomics).
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_ctx md_ctx; /* opaque, host-side */
+
+/* Models of Sec. 2 (eqs. 1-3). */
+enum md_model { MD_HMF = 0, MD_RING = 1, MD_GRAV2D = 2 };
+
+/*
+ * Arithmetic of the force evaluation.  State (q, p, f), energies and the HMF
+ * magnetization are FP64 in every mode except MD_MIXED_F32STATE.
+ *   MD_FP64            all FP64.
+ *   MD_MIXED           FP32 copies of the positions (Sec. 3.2, 2D scheme), FP32
+ *                      pair arithmetic, FP32 partial sums over a j-tile folded
+ *                      into an FP64 per-particle accumulator once per tile.
+ *   MD_MIXED_KAHAN     FP32 pair arithmetic, Kahan-compensated FP32 accumulation
+ *                      of every pair term (no FP64 in the pair loop).
+ *   MD_MIXED_PAIRF64   FP32 pair arithmetic, each pair term added into an FP64
+ *                      accumulator (the literal scheme of Sec. 3.2 for 2D).
+ *   MD_MIXED_F32STATE  HMF only: FP32 angles (wrapped to [-pi, pi)), momenta,
+ *                      sines/cosines and kicks inside md_step; FP64 reduction of
+ *                      the magnetization (eq. 7).  q, p, f stay FP64 at the ABI.
+ * MD_RING and MD_GRAV2D accept the first four; MD_HMF accepts MD_FP64 and
+ * MD_MIXED_F32STATE.
+ */
+enum md_prec {
+    MD_FP64 = 0,
+    MD_MIXED = 1,
+    MD_MIXED_KAHAN = 2,
+    MD_MIXED_PAIRF64 = 3,
+    MD_MIXED_F32STATE = 4
+};
+
+enum md_status {
+    MD_OK = 0,
+    MD_EINVAL = -1,       /* bad argument (null/misaligned pointer, n < 1, eps <= 0, ...) */
+    MD_EDEVICE = -2,      /* a HIP call or kernel launch failed */
+    MD_ENOMEM = -3,       /* workspace smaller than md_workspace_bytes, or host alloc failed */
+    MD_ESTATE = -4,       /* call out of order (e.g. md_step on HMF before any md_force) */
+    MD_ENONFINITE = -5,   /* reserved: a host-read energy was not finite */
+    MD_EUNSUPPORTED = -6  /* model/precision combination or tile configuration not built */
+};
+
+/*
+ * Workspace bytes a context for (model, prec, n) needs; 0 for an invalid
+ * combination.  The figure covers every tile configuration md_set_tiles
+ * accepts for this n.
+ */
+size_t md_workspace_bytes(int model, int prec, int64_t n);
+
+/*
+ * Create a context for n particles of `model` (eqs. 1-3) with softening eps
+ * (eqs. 1 and 3; ignored for MD_HMF, must be > 0 otherwise), computing in
+ * `prec`.  hip_stream: a hipStream_t, or NULL for the default stream.
+ * workspace: device memory of at least md_workspace_bytes(model, prec, n)
+ * bytes, 256-byte aligned.  On success *out holds the new context.
+ * The context records the current HIP device.
+ */
+int md_init(md_ctx **out, int model, int prec, int64_t n, double eps,
+            void *hip_stream, void *workspace, size_t workspace_bytes);
+
+/* Change the stream later calls enqueue on. */
+int md_set_stream(md_ctx *c, void *hip_stream);
+
+/*
+ * Tile configuration of the O(N^2) pair kernels (Sec. 3.2: i-tiles over blocks,
+ * j-tiles streamed through the whole j range).  Results are the same sums in a
+ * different order, so they agree to rounding across configurations.
+ *   i_per_lane   particles i held in registers by each lane: 1, 2 or 4
+ *   waves        wavefronts (64 lanes) per block: 1, 2 or 4
+ *   j_split      number of j ranges computed by separate blocks and combined
+ *                in a fixed order: 1 .. md_max_j_split(n)
+ *   j_tile       j per FP32 partial sum before the FP64 fold (MD_MIXED):
+ *                a multiple of 16 in [16, 4096]
+ * 0 in any field keeps the built-in choice for this n.  MD_HMF ignores it.
+ */
+int md_set_tiles(md_ctx *c, int i_per_lane, int waves, int j_split, int j_tile);
+
+/* Current tile configuration (after defaults were resolved): out[4] host ints. */
+int md_get_tiles(const md_ctx *c, int *out4);
+
+/* Largest j_split md_set_tiles accepts for n particles (>= 1). */
+int md_max_j_split(int64_t n);
+
+/*
+ * f = -dV/dq at positions q (eqs. 6-9 and the 2D gradient of eq. 3).
+ * q: device [d][n] FP64, read only.  f: device [d][n] FP64, written.
+ * For MD_HMF this also caches the magnetization of q in the workspace.
+ */
+int md_force(md_ctx *c, const double *q, double *f);
+
+/*
+ * nsteps Yoshida steps of size dt (eq. 4), in place.  On entry f must equal
+ * force(q) (from md_force or the previous md_step); on exit q, p hold the state
+ * at t + nsteps*dt and f = force(q).  Three force evaluations per step; the
+ * force at the end of a step is reused at the start of the next.  dt may be
+ * negative (reverse integration).  nsteps = 0 is a no-op.
+ */
+int md_step(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps);
+
+/*
+ * Energies of the state (q, p): out_dev3[0] = K = (1/2) sum p^2,
+ * out_dev3[1] = V of eqs. 1-3 (HMF through eq. 5), out_dev3[2] = K + V.
+ * Always FP64 arithmetic and FP64 accumulation, whatever `prec` is.
+ * out_dev3: device pointer to 3 doubles.
+ */
+int md_energy(md_ctx *c, const double *q, const double *p, double *out_dev3);
+
+/*
+ * HMF magnetization of eq. 7 at positions q: out_dev2[0] = Mx, out_dev2[1] = My
+ * (FP64 reduction).  MD_HMF contexts only.
+ */
+int md_magnetization(md_ctx *c, const double *q, double *out_dev2);
+
+/* Destroy a context (does not touch the workspace).  NULL is accepted. */
+int md_destroy(md_ctx *c);
+
+/* Static text for a status code. */
+const char *md_strerror(int status);
+
+/* Detail of the last failure on this context ("" if none); valid until the next call. */
+const char *md_last_error(const md_ctx *c);
+
+/* Library version string. */
+const char *md_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MD_H */

@@ -1,0 +1,381 @@
+// api.hip -- the C ABI of libmd (md.h): argument validation, workspace carve-up,
+// tile configuration, and the driver of the fourth-order Yoshida composition
+// (Sec. 3, eq. 4) that sequences the kernels of pair.hip and hmf.hip.
+//
+// The Yoshida step (eq. 4 and the step list after it) as a kick-drift sequence,
+// with the force at the new positions used for the final kick and carried into
+// the next step (three force evaluations per step):
+//     p += B0 dt f;  q += D0 dt p;  f = F(q)
+//     p += B1 dt f;  q += D1 dt p;  f = F(q)
+//     p += B1 dt f;  q += D0 dt p;  f = F(q)
+//     p += B0 dt f
+// The coefficients are not printed in the paper; they are those of Yoshida's
+// triple-jump composition of the second-order leapfrog: with w1 = 1/(2 - 2^{1/3})
+// and w0 = -2^{1/3}/(2 - 2^{1/3}), D0 = w1, D1 = w0, B0 = w1/2, B1 = (w0 + w1)/2.
+// Inside one call the end kick of a step and the start kick of the next are
+// applied by the same kernel (two separate adds, same result as two stages).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "md_internal.h"
+
+namespace md {
+namespace {
+
+constexpr int64_t kMaxPairN = int64_t(1) << 23;  // O(N^2) models
+constexpr int64_t kMaxHmfN = int64_t(1) << 30;   // O(N) model
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool prec_ok(int model, int prec)
+{
+    if (model == MD_HMF) return prec == MD_FP64 || prec == MD_MIXED_F32STATE;
+    if (model == MD_RING || model == MD_GRAV2D) return prec >= MD_FP64 && prec <= MD_MIXED_PAIRF64;
+    return false;
+}
+
+bool model_ok(int model) { return model == MD_HMF || model == MD_RING || model == MD_GRAV2D; }
+
+struct Layout {
+    size_t red, scal, ops, part, th32, p32, total;
+};
+
+Layout layout(int model, int prec, int64_t n)
+{
+    Layout L{};
+    const size_t npad = (size_t)pad_n(n);
+    size_t off = 0;
+    L.red = off;
+    off = align_up(off + sizeof(double) * kRedSlots);
+    L.scal = off;
+    off = align_up(off + sizeof(double) * 32);
+    L.ops = off;
+    if (model == MD_RING) off = align_up(off + 2 * npad * (prec == MD_FP64 ? sizeof(double) : sizeof(float)));
+    else if (model == MD_GRAV2D && prec != MD_FP64) off = align_up(off + 2 * npad * sizeof(float));
+    L.part = off;
+    if (model != MD_HMF) off = align_up(off + (size_t)max_j_split(n) * dims(model) * npad * sizeof(double));
+    L.th32 = off;
+    if (model == MD_HMF && prec == MD_MIXED_F32STATE) off = align_up(off + npad * sizeof(float));
+    L.p32 = off;
+    if (model == MD_HMF && prec == MD_MIXED_F32STATE) off = align_up(off + npad * sizeof(float));
+    L.total = off;
+    return L;
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+int fail(md_ctx *c, int status, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(md_ctx *c, int status, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return status;
+}
+
+int dev_fail(md_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, MD_EDEVICE, "%s: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
+}
+
+// Makes the context's device current for the scope of one call.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void yoshida(double *b0, double *b1, double *d0, double *d1)
+{
+    const double cb = cbrt(2.0);
+    const double w1 = 1.0 / (2.0 - cb);
+    const double w0 = -cb / (2.0 - cb);
+    *d0 = w1;
+    *d1 = w0;
+    *b0 = 0.5 * w1;
+    *b1 = 0.5 * (w0 + w1);
+}
+
+#define MD_TRY(expr, what)                        \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return dev_fail(c, e_, what); \
+    } while (0)
+
+int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps)
+{
+    double B0, B1, D0, D1;
+    yoshida(&B0, &B1, &D0, &D1);
+    const int stage = UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1 | UPD_DRIFT | UPD_PREP;
+    MD_TRY(launch_update(c, UPD_KICK1 | UPD_DRIFT | UPD_PREP, B0 * dt, 0.0, D0 * dt, q, p, f), "step: first kick");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        MD_TRY(launch_pair(c, q), "step: pair kernel");
+        MD_TRY(launch_update(c, stage, B1 * dt, 0.0, D1 * dt, q, p, f), "step: update");
+        MD_TRY(launch_pair(c, q), "step: pair kernel");
+        MD_TRY(launch_update(c, stage, B1 * dt, 0.0, D0 * dt, q, p, f), "step: update");
+        MD_TRY(launch_pair(c, q), "step: pair kernel");
+        if (s + 1 < nsteps)
+            MD_TRY(launch_update(c, stage | UPD_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, f), "step: update");
+        else
+            MD_TRY(launch_update(c, UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1, B0 * dt, 0.0, 0.0, q, p, f),
+                   "step: last kick");
+    }
+    return MD_OK;
+}
+
+int step_hmf(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps)
+{
+    double B0, B1, D0, D1;
+    yoshida(&B0, &B1, &D0, &D1);
+    const bool f32 = c->prec == MD_MIXED_F32STATE;
+    const int stage = HMF_KICK_M | HMF_DRIFT | HMF_WRITE | HMF_REDUCE;
+    if (f32) MD_TRY(launch_hmf_convert(c, q, p, true), "step: convert in");
+    MD_TRY(launch_hmf_pass(c, HMF_KICK_F | HMF_DRIFT | HMF_WRITE | HMF_REDUCE, B0 * dt, 0.0, D0 * dt, q, p, f,
+                           nullptr, f32),
+           "step: first pass");
+    MD_TRY(launch_hmf_finalize(c), "step: finalize");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D1 * dt, q, p, nullptr, nullptr, f32), "step: pass");
+        MD_TRY(launch_hmf_finalize(c), "step: finalize");
+        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32), "step: pass");
+        MD_TRY(launch_hmf_finalize(c), "step: finalize");
+        if (s + 1 < nsteps) {
+            MD_TRY(launch_hmf_pass(c, stage | HMF_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, nullptr, nullptr, f32),
+                   "step: pass");
+            MD_TRY(launch_hmf_finalize(c), "step: finalize");
+        } else {
+            MD_TRY(launch_hmf_pass(c, HMF_KICK_M | HMF_STORE_F | HMF_WRITE, B0 * dt, 0.0, 0.0, q, p, nullptr, f,
+                                   f32),
+                   "step: last pass");
+        }
+    }
+    if (f32) MD_TRY(launch_hmf_convert(c, q, p, false), "step: convert out");
+    return MD_OK;
+}
+
+}  // namespace
+
+int64_t pad_n(int64_t n) { return (n + 255) / 256 * 256; }
+
+int dims(int model) { return model == MD_GRAV2D ? 2 : 1; }
+
+int max_j_split(int64_t n)
+{
+    if (n < 1) return 1;
+    int64_t s = (int64_t(1) << 22) / n;
+    if (s > kMaxJSplit) s = kMaxJSplit;
+    return s < 1 ? 1 : (int)s;
+}
+
+Tiles default_tiles(int model, int prec, int64_t n)
+{
+    (void)model;
+    (void)prec;
+    Tiles t;
+    t.waves = 4;
+    t.ipl = n >= 16384 ? 2 : 1;
+    t.jtile = 128;
+    const int64_t wi = (n + kWave * t.ipl - 1) / (kWave * t.ipl);
+    int64_t s = (8192 + wi - 1) / wi;
+    const int64_t by_len = n / 64 > 0 ? n / 64 : 1;
+    if (s > by_len) s = by_len;
+    if (s > max_j_split(n)) s = max_j_split(n);
+    t.jsplit = s < 1 ? 1 : (int)s;
+    return t;
+}
+
+}  // namespace md
+
+using namespace md;
+
+extern "C" {
+
+size_t md_workspace_bytes(int model, int prec, int64_t n)
+{
+    if (!model_ok(model) || !prec_ok(model, prec) || n < 1) return 0;
+    if (n > (model == MD_HMF ? kMaxHmfN : kMaxPairN)) return 0;
+    return layout(model, prec, n).total;
+}
+
+int md_max_j_split(int64_t n) { return max_j_split(n); }
+
+int md_init(md_ctx **out, int model, int prec, int64_t n, double eps, void *hip_stream, void *workspace,
+            size_t workspace_bytes)
+{
+    if (!out) return MD_EINVAL;
+    *out = nullptr;
+    if (!model_ok(model) || n < 1 || n > (model == MD_HMF ? kMaxHmfN : kMaxPairN)) return MD_EINVAL;
+    if (!prec_ok(model, prec)) return MD_EUNSUPPORTED;
+    if (model != MD_HMF && !(eps > 0.0 && isfinite(eps))) return MD_EINVAL;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return MD_EINVAL;
+    const Layout L = layout(model, prec, n);
+    if (workspace_bytes < L.total) return MD_ENOMEM;
+
+    md_ctx *c = new (std::nothrow) md_ctx();
+    if (!c) return MD_ENOMEM;
+    c->model = model;
+    c->prec = prec;
+    c->n = n;
+    c->npad = pad_n(n);
+    c->eps = model == MD_HMF ? 0.0 : eps;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ws = static_cast<char *>(workspace);
+    c->ws_bytes = workspace_bytes;
+    c->red = reinterpret_cast<double *>(c->ws + L.red);
+    c->scal = reinterpret_cast<double *>(c->ws + L.scal);
+    c->ops = (L.part > L.ops) ? static_cast<void *>(c->ws + L.ops) : nullptr;
+    c->part = (L.th32 > L.part) ? reinterpret_cast<double *>(c->ws + L.part) : nullptr;
+    c->th32 = (L.p32 > L.th32) ? reinterpret_cast<float *>(c->ws + L.th32) : nullptr;
+    c->p32 = (L.total > L.p32) ? reinterpret_cast<float *>(c->ws + L.p32) : nullptr;
+    c->tiles = default_tiles(model, prec, n);
+    hipError_t e = hipGetDevice(&c->dev);
+    if (e != hipSuccess) {
+        delete c;
+        return MD_EDEVICE;
+    }
+    *out = c;
+    return MD_OK;
+}
+
+int md_set_stream(md_ctx *c, void *hip_stream)
+{
+    if (!c) return MD_EINVAL;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return MD_OK;
+}
+
+int md_set_tiles(md_ctx *c, int i_per_lane, int waves, int j_split, int j_tile)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    const Tiles d = default_tiles(c->model, c->prec, c->n);
+    Tiles t;
+    t.ipl = i_per_lane ? i_per_lane : d.ipl;
+    t.waves = waves ? waves : d.waves;
+    t.jsplit = j_split ? j_split : d.jsplit;
+    t.jtile = j_tile ? j_tile : d.jtile;
+    if (t.ipl != 1 && t.ipl != 2 && t.ipl != 4)
+        return fail(c, MD_EUNSUPPORTED, "i_per_lane must be 1, 2 or 4 (got %d)", t.ipl);
+    if (t.waves != 1 && t.waves != 2 && t.waves != 4)
+        return fail(c, MD_EUNSUPPORTED, "waves must be 1, 2 or 4 (got %d)", t.waves);
+    if (t.jsplit < 1 || t.jsplit > max_j_split(c->n))
+        return fail(c, MD_EINVAL, "j_split must be in [1, %d] (got %d)", max_j_split(c->n), t.jsplit);
+    if (t.jtile < 16 || t.jtile > 4096 || t.jtile % 16)
+        return fail(c, MD_EINVAL, "j_tile must be a multiple of 16 in [16, 4096] (got %d)", t.jtile);
+    c->tiles = t;
+    return MD_OK;
+}
+
+int md_get_tiles(const md_ctx *c, int *out4)
+{
+    if (!c || !out4) return MD_EINVAL;
+    out4[0] = c->tiles.ipl;
+    out4[1] = c->tiles.waves;
+    out4[2] = c->tiles.jsplit;
+    out4[3] = c->tiles.jtile;
+    return MD_OK;
+}
+
+int md_force(md_ctx *c, const double *q, double *f)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (!q || !f || !aligned8(q) || !aligned8(f)) return fail(c, MD_EINVAL, "md_force: null or misaligned pointer");
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_force: set device");
+    double *qm = const_cast<double *>(q);
+    if (c->model == MD_HMF) {
+        MD_TRY(launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, qm, nullptr, nullptr, nullptr, false), "force: reduce");
+        MD_TRY(launch_hmf_finalize(c), "force: finalize");
+        MD_TRY(launch_hmf_pass(c, HMF_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, nullptr, f, false), "force: store");
+        return MD_OK;
+    }
+    MD_TRY(launch_prep(c, q), "force: operands");
+    MD_TRY(launch_pair(c, q), "force: pair kernel");
+    MD_TRY(launch_update(c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, f), "force: combine");
+    return MD_OK;
+}
+
+int md_step(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (!q || !p || !f || !aligned8(q) || !aligned8(p) || !aligned8(f))
+        return fail(c, MD_EINVAL, "md_step: null or misaligned pointer");
+    if (!isfinite(dt)) return fail(c, MD_EINVAL, "md_step: dt must be finite");
+    if (nsteps < 0) return fail(c, MD_EINVAL, "md_step: nsteps must be >= 0");
+    if (nsteps == 0) return MD_OK;
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_step: set device");
+    return c->model == MD_HMF ? step_hmf(c, q, p, f, dt, nsteps) : step_pairs(c, q, p, f, dt, nsteps);
+}
+
+int md_energy(md_ctx *c, const double *q, const double *p, double *out_dev3)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (!q || !p || !out_dev3 || !aligned8(q) || !aligned8(p) || !aligned8(out_dev3))
+        return fail(c, MD_EINVAL, "md_energy: null or misaligned pointer");
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_energy: set device");
+    MD_TRY(launch_energy(c, q, p, out_dev3), "energy");
+    return MD_OK;
+}
+
+int md_magnetization(md_ctx *c, const double *q, double *out_dev2)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (c->model != MD_HMF) return fail(c, MD_EUNSUPPORTED, "md_magnetization: HMF contexts only");
+    if (!q || !out_dev2 || !aligned8(q) || !aligned8(out_dev2))
+        return fail(c, MD_EINVAL, "md_magnetization: null or misaligned pointer");
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_magnetization: set device");
+    MD_TRY(launch_magnetization(c, q, out_dev2), "magnetization");
+    return MD_OK;
+}
+
+int md_destroy(md_ctx *c)
+{
+    delete c;
+    return MD_OK;
+}
+
+const char *md_strerror(int status)
+{
+    switch (status) {
+    case MD_OK: return "success";
+    case MD_EINVAL: return "invalid argument";
+    case MD_EDEVICE: return "HIP device or launch error";
+    case MD_ENOMEM: return "workspace too small or host allocation failed";
+    case MD_ESTATE: return "call out of order";
+    case MD_ENONFINITE: return "non-finite result";
+    case MD_EUNSUPPORTED: return "unsupported model, precision or tile configuration";
+    default: return "unknown status";
+    }
+}
+
+const char *md_last_error(const md_ctx *c) { return c ? c->err.c_str() : ""; }
+
+const char *md_version(void) { return "libmd 0.1 (gfx950)"; }
+
+}  // extern "C"

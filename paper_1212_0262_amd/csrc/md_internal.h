@@ -1,0 +1,93 @@
+// md_internal.h -- host-side context of libmd and the kernel launchers each
+// translation unit provides.  Not installed; the public interface is md.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "md.h"
+
+namespace md {
+
+// Update-kernel flags (one kick-drift stage of the Yoshida composition, eq. 4).
+enum : int {
+    UPD_F_FROM_PART = 1 << 0,  // f = prefactor * (sum of the pair-kernel partials), else read f
+    UPD_STORE_F = 1 << 1,      // write f
+    UPD_KICK1 = 1 << 2,        // p += kick1 * f
+    UPD_KICK2 = 1 << 3,        // p += kick2 * f (end kick of a step merged with the next start)
+    UPD_DRIFT = 1 << 4,        // q += drift * p
+    UPD_PREP = 1 << 5,         // refresh the pair-kernel operands from q (FP32 copy / sincos)
+};
+
+// HMF pass flags.
+enum : int {
+    HMF_KICK_F = 1 << 0,    // p += kick1 * f_in[i]
+    HMF_KICK_M = 1 << 1,    // p += (kick1 [+ kick2]) * (cos(t) My - sin(t) Mx)
+    HMF_KICK2 = 1 << 2,     // second kick of the same force
+    HMF_DRIFT = 1 << 3,     // t += drift * p
+    HMF_REDUCE = 1 << 4,    // block partials of sum cos(t'), sum sin(t')
+    HMF_STORE_F = 1 << 5,   // f_out = cos(t) My - sin(t) Mx  (no drift in the same pass)
+    HMF_WRITE = 1 << 6,     // write t, p back
+};
+
+constexpr int kWave = 64;           // lanes per wavefront (CDNA)
+constexpr int kMaxJSplit = 64;
+constexpr int kRedSlots = 1 << 16;   // doubles of reduction scratch
+constexpr int kHmfGrid = 2048;       // blocks of the HMF grid-stride passes
+constexpr int kEnergyBlock = 256;
+
+struct Tiles {
+    int ipl = 0;     // i per lane
+    int waves = 0;   // wavefronts per block
+    int jsplit = 0;  // j ranges per i block
+    int jtile = 0;   // j per FP32 partial
+};
+
+}  // namespace md
+
+struct md_ctx {
+    int model = 0, prec = 0, dev = 0;
+    int64_t n = 0, npad = 0;
+    double eps = 0.0;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    // workspace carve-up
+    void *ops = nullptr;      // pair operands: 2D [2][npad] FP32 copy; Ring [2][npad] cos,sin (FP32 or FP64)
+    double *part = nullptr;   // pair partials [jsplit][d][npad]
+    double *red = nullptr;    // reduction partials [kRedSlots]
+    double *scal = nullptr;   // small device scalars (HMF magnetization, ...)
+    float *th32 = nullptr;    // HMF FP32 state
+    float *p32 = nullptr;
+    md::Tiles tiles;
+    std::string err;
+};
+
+namespace md {
+
+int64_t pad_n(int64_t n);
+int dims(int model);
+int max_j_split(int64_t n);
+Tiles default_tiles(int model, int prec, int64_t n);
+int hmf_grid(int64_t n);  // blocks of the HMF passes (fixed per n: reproducible sums)
+
+// Launchers return hipSuccess or the launch error.  All enqueue on c->stream.
+// pair.hip
+hipError_t launch_prep(md_ctx *c, const double *q);
+hipError_t launch_pair(md_ctx *c, const double *q);
+hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift,
+                         double *q, double *p, double *f);
+// hmf.hip
+hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, double drift,
+                           double *th, double *p, const double *f_in, double *f_out,
+                           bool f32state);
+hipError_t launch_hmf_finalize(md_ctx *c);
+hipError_t launch_hmf_convert(md_ctx *c, double *th, double *p, bool to_f32);
+// energy.hip
+hipError_t launch_energy(md_ctx *c, const double *q, const double *p, double *out3);
+hipError_t launch_magnetization(md_ctx *c, const double *q, double *out2);
+
+}  // namespace md

@@ -1,0 +1,361 @@
+// pair.hip -- the O(N^2) all-pairs forces of the Ring model (eqs. 8-9) and the
+// 2D self-gravitating model (gradient of eq. 3), and the O(N) kick/drift stages
+// of the Yoshida composition (eq. 4) that surround them.
+//
+// Pair kernel design (gfx950, wave64):
+//   * i-tile in registers: each lane owns i_per_lane particles i, 64 apart.
+//   * j-stream broadcast: every lane of a wavefront walks the same j, so the j
+//     operands are wave-uniform loads that the compiler places in scalar
+//     registers (s_load through the scalar cache); they feed the VALU directly as
+//     the one scalar operand an instruction may take.  No LDS, no barriers.
+//   * j-split: the j range is cut into j_split pieces computed by different
+//     blocks (grid.y) so that small N still fills 256 CUs; the partial sums are
+//     added in a fixed order by the update kernel (deterministic).
+//   * self pair: contributes exactly zero (2D: dx = dy = 0; Ring: the numerator
+//     sin(ti)cos(tj) - cos(ti)sin(tj) is formed from rounded products, without
+//     fused multiply-add, so it is exactly 0 at j = i), so no mask is needed.
+//   * ragged N: the j loop bound is uniform; lanes with i >= N load particle
+//     N-1 and do not store.
+// Accumulation policies (md_prec): FP32 partial per j-tile folded into FP64;
+// Kahan-compensated FP32 per pair; FP64 add per pair; plain FP64.
+#include "device.h"
+#include "md_internal.h"
+
+namespace md {
+namespace {
+
+// ---------------------------------------------------------------- accumulators --
+
+// FP32 partial over a j tile, folded into an FP64 total once per tile.
+struct AccTile {
+    float s = 0.f;
+    double t = 0.0;
+    __device__ __forceinline__ void add(float a, float b) { s = __builtin_fmaf(a, b, s); }
+    __device__ __forceinline__ void fold() { t += (double)s; s = 0.f; }
+    __device__ __forceinline__ double get() const { return t; }
+};
+
+// Kahan-compensated FP32 sum of every pair term; -c holds the lost low part.
+struct AccKahan {
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float a, float b)
+    {
+        const float y = a * b - c;
+        const float u = s + y;
+        c = (u - s) - y;
+        s = u;
+    }
+    __device__ __forceinline__ void fold() {}
+    __device__ __forceinline__ double get() const { return (double)s - (double)c; }
+};
+
+// Each FP32 pair term added into an FP64 accumulator.
+struct AccPair64 {
+    double t = 0.0;
+    __device__ __forceinline__ void add(float a, float b) { t += (double)(a * b); }
+    __device__ __forceinline__ void fold() {}
+    __device__ __forceinline__ double get() const { return t; }
+};
+
+// Plain FP64.
+struct AccF64 {
+    double t = 0.0;
+    __device__ __forceinline__ void add(double a, double b) { t = __builtin_fma(a, b, t); }
+    __device__ __forceinline__ void fold() {}
+    __device__ __forceinline__ double get() const { return t; }
+};
+
+__device__ __forceinline__ float rcp_(float x) { return rcp32(x); }
+__device__ __forceinline__ double rcp_(double x) { return rcp64(x); }
+__device__ __forceinline__ float rsq_(float x) { return rsq32(x); }
+__device__ __forceinline__ double rsq_(double x) { return rsq64(x); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ------------------------------------------------------------------ pair terms --
+
+// 2D: adds (r_i - r_j) / (|r_i - r_j|^2 + eps) to (ax, ay).
+template <typename T, typename A>
+__device__ __forceinline__ void pair_2d(T xi, T yi, T xj, T yj, T eps, A &ax, A &ay)
+{
+    const T dx = xi - xj;
+    const T dy = yi - yj;
+    const T w = rcp_(fma_(dx, dx, fma_(dy, dy, eps)));
+    ax.add(dx, w);
+    ay.add(dy, w);
+}
+
+// Ring (eq. 9): adds sin(ti - tj) / (1 - cos(ti - tj) + eps)^{3/2} to a, from the
+// cosines and sines of both angles.  one_eps = 1 + eps.
+template <typename T, typename A>
+__device__ __forceinline__ void pair_ring(T ci, T si, T cj, T sj, T one_eps, A &a)
+{
+    T num;
+    {
+#pragma clang fp contract(off)
+        num = si * cj - ci * sj;
+    }
+    const T u = fma_(-ci, cj, fma_(-si, sj, one_eps));
+    const T r = rsq_(u);
+    a.add(num, r * r * r);
+}
+
+// ---------------------------------------------------------------- pair kernels --
+
+// part[(s*2 + c)*npad + i] = sum over j in the s-th j range of the 2D pair term.
+template <typename T, typename A, int IPL>
+__global__ __launch_bounds__(256) void k_pair_2d(const T *__restrict__ xs, const T *__restrict__ ys,
+                                                 int n, int npad, int jlen, int jtile, T eps,
+                                                 double *__restrict__ part)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int ibase = (blockIdx.x * (blockDim.x / kWave) + wave) * (kWave * IPL) + lane;
+    const int s = blockIdx.y;
+    const int j0 = s * jlen;
+    const int j1 = min(n, j0 + jlen);
+
+    T xi[IPL], yi[IPL];
+    A ax[IPL], ay[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = min(ibase + kWave * k, n - 1);
+        xi[k] = xs[i];
+        yi[k] = ys[i];
+    }
+    for (int jt = j0; jt < j1; jt += jtile) {
+        const int je = min(j1, jt + jtile);
+        int j = jt;
+        for (; j + 8 <= je; j += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T xj = xs[j + u];
+                const T yj = ys[j + u];
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) pair_2d(xi[k], yi[k], xj, yj, eps, ax[k], ay[k]);
+            }
+        }
+        for (; j < je; ++j) {
+            const T xj = xs[j];
+            const T yj = ys[j];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) pair_2d(xi[k], yi[k], xj, yj, eps, ax[k], ay[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            ax[k].fold();
+            ay[k].fold();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = ibase + kWave * k;
+        if (i < n) {
+            part[(size_t)(2 * s) * npad + i] = ax[k].get();
+            part[(size_t)(2 * s + 1) * npad + i] = ay[k].get();
+        }
+    }
+}
+
+// part[s*npad + i] = sum over j in the s-th j range of the Ring pair term.
+// cs = [cos row | sin row], each npad long.
+template <typename T, typename A, int IPL>
+__global__ __launch_bounds__(256) void k_pair_ring(const T *__restrict__ cs, int n, int npad, int jlen,
+                                                   int jtile, T one_eps, double *__restrict__ part)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int ibase = (blockIdx.x * (blockDim.x / kWave) + wave) * (kWave * IPL) + lane;
+    const int s = blockIdx.y;
+    const int j0 = s * jlen;
+    const int j1 = min(n, j0 + jlen);
+    const T *__restrict__ cc = cs;
+    const T *__restrict__ ss = cs + npad;
+
+    T ci[IPL], si[IPL];
+    A a[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = min(ibase + kWave * k, n - 1);
+        ci[k] = cc[i];
+        si[k] = ss[i];
+    }
+    for (int jt = j0; jt < j1; jt += jtile) {
+        const int je = min(j1, jt + jtile);
+        int j = jt;
+        for (; j + 8 <= je; j += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T cj = cc[j + u];
+                const T sj = ss[j + u];
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) pair_ring(ci[k], si[k], cj, sj, one_eps, a[k]);
+            }
+        }
+        for (; j < je; ++j) {
+            const T cj = cc[j];
+            const T sj = ss[j];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) pair_ring(ci[k], si[k], cj, sj, one_eps, a[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) a[k].fold();
+    }
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = ibase + kWave * k;
+        if (i < n) part[(size_t)s * npad + i] = a[k].get();
+    }
+}
+
+// --------------------------------------------------------------- update kernel --
+
+// Operand refresh after a drift.
+enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_SINCOS32 = 2, PREP_SINCOS64 = 3 };
+
+// One kick-drift stage, elementwise over particles (eq. 4 and the step list of
+// Sec. 3): f from the pair partials (times the model prefactor), p += kick * f,
+// q += drift * p, then the pair operands of the new q.
+template <int D, int PREP>
+__global__ __launch_bounds__(256) void k_update(const double *__restrict__ part, int S, int n, int npad,
+                                                double pref, double *__restrict__ f,
+                                                double *__restrict__ p, double *__restrict__ q,
+                                                void *__restrict__ ops, double kick1, double kick2,
+                                                double drift, int flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool need_p = flags & (UPD_KICK1 | UPD_KICK2 | UPD_DRIFT);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const size_t k = (size_t)d * n + i;
+        double fd = 0.0;
+        if (flags & UPD_F_FROM_PART) {
+            double s = 0.0;
+            for (int b = 0; b < S; ++b) s += part[(size_t)(b * D + d) * npad + i];
+            fd = pref * s;
+        } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
+            fd = f[k];
+        }
+        if (flags & UPD_STORE_F) f[k] = fd;
+        double qd = 0.0;
+        if (flags & (UPD_DRIFT | UPD_PREP)) qd = q[k];
+        if (need_p) {
+            double pd = p[k];
+            if (flags & UPD_KICK1) pd += kick1 * fd;
+            if (flags & UPD_KICK2) pd += kick2 * fd;
+            if (flags & (UPD_KICK1 | UPD_KICK2)) p[k] = pd;
+            if (flags & UPD_DRIFT) {
+                qd += drift * pd;
+                q[k] = qd;
+            }
+        }
+        if (flags & UPD_PREP) {
+            if (PREP == PREP_CAST32) {
+                static_cast<float *>(ops)[(size_t)d * npad + i] = (float)qd;
+            } else if (PREP == PREP_SINCOS32 || PREP == PREP_SINCOS64) {
+                double sn, cn;
+                sincos(qd, &sn, &cn);
+                if (PREP == PREP_SINCOS32) {
+                    static_cast<float *>(ops)[i] = (float)cn;
+                    static_cast<float *>(ops)[npad + i] = (float)sn;
+                } else {
+                    static_cast<double *>(ops)[i] = cn;
+                    static_cast<double *>(ops)[npad + i] = sn;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers --
+
+int prep_kind(const md_ctx *c)
+{
+    if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? PREP_NONE : PREP_CAST32;
+    return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_SINCOS32;
+}
+
+hipError_t update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
+                  double *f)
+{
+    const int n = (int)c->n;
+    const dim3 block(256), grid((unsigned)((n + 255) / 256));
+    const double pref = c->model == MD_GRAV2D ? -2.0 / (double)n : -1.0 / (2.0 * sqrt(2.0) * (double)n);
+    const int S = c->tiles.jsplit;
+    const int npad = (int)c->npad;
+    const int pk = prep_kind(c);
+    if (pk == PREP_NONE) flags &= ~UPD_PREP;
+#define MD_UPD(D_, P_)                                                                                    \
+    hipLaunchKernelGGL((k_update<D_, P_>), grid, block, 0, c->stream, c->part, S, n, npad, pref, f, p, q, \
+                       c->ops, kick1, kick2, drift, flags)
+    if (c->model == MD_GRAV2D) {
+        if (pk == PREP_CAST32) MD_UPD(2, PREP_CAST32);
+        else MD_UPD(2, PREP_NONE);
+    } else {
+        if (pk == PREP_SINCOS32) MD_UPD(1, PREP_SINCOS32);
+        else MD_UPD(1, PREP_SINCOS64);
+    }
+#undef MD_UPD
+    return hipGetLastError();
+}
+
+template <typename T, typename A>
+hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
+{
+    const int n = (int)c->n, npad = (int)c->npad, jt = c->tiles.jtile;
+    if (c->model == MD_GRAV2D) {
+        const T *x = static_cast<const T *>(src);
+        const T *y = x + (src == c->ops ? npad : n);
+        const T eps = (T)c->eps;
+        switch (c->tiles.ipl) {
+        case 1: hipLaunchKernelGGL((k_pair_2d<T, A, 1>), grid, block, 0, c->stream, x, y, n, npad, jlen, jt, eps, c->part); break;
+        case 2: hipLaunchKernelGGL((k_pair_2d<T, A, 2>), grid, block, 0, c->stream, x, y, n, npad, jlen, jt, eps, c->part); break;
+        default: hipLaunchKernelGGL((k_pair_2d<T, A, 4>), grid, block, 0, c->stream, x, y, n, npad, jlen, jt, eps, c->part); break;
+        }
+    } else {
+        const T *cs = static_cast<const T *>(src);
+        const T one_eps = (T)(1.0 + c->eps);
+        switch (c->tiles.ipl) {
+        case 1: hipLaunchKernelGGL((k_pair_ring<T, A, 1>), grid, block, 0, c->stream, cs, n, npad, jlen, jt, one_eps, c->part); break;
+        case 2: hipLaunchKernelGGL((k_pair_ring<T, A, 2>), grid, block, 0, c->stream, cs, n, npad, jlen, jt, one_eps, c->part); break;
+        default: hipLaunchKernelGGL((k_pair_ring<T, A, 4>), grid, block, 0, c->stream, cs, n, npad, jlen, jt, one_eps, c->part); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_prep(md_ctx *c, const double *q)
+{
+    if (prep_kind(c) == PREP_NONE) return hipSuccess;
+    return update(c, UPD_PREP, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr);
+}
+
+hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
+                         double *f)
+{
+    return update(c, flags, kick1, kick2, drift, q, p, f);
+}
+
+// Pair partials of the current operands.  For FP64 2D the operands are q itself.
+hipError_t launch_pair(md_ctx *c, const double *q)
+{
+    const Tiles &t = c->tiles;
+    const int n = (int)c->n;
+    const int per_block = kWave * t.ipl * t.waves;
+    const dim3 block((unsigned)(kWave * t.waves));
+    const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)t.jsplit);
+    int jlen = (n + t.jsplit - 1) / t.jsplit;
+    jlen = (jlen + 15) / 16 * 16;
+    const void *src = (c->model == MD_GRAV2D && c->prec == MD_FP64) ? (const void *)q : (const void *)c->ops;
+    switch (c->prec) {
+    case MD_FP64: return pair_ipl<double, AccF64>(c, src, grid, block, jlen);
+    case MD_MIXED: return pair_ipl<float, AccTile>(c, src, grid, block, jlen);
+    case MD_MIXED_KAHAN: return pair_ipl<float, AccKahan>(c, src, grid, block, jlen);
+    default: return pair_ipl<float, AccPair64>(c, src, grid, block, jlen);
+    }
+}
+
+}  // namespace md

@@ -1,0 +1,202 @@
+"""Thin Python binding of libmd (include/md.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libmd.so``; this module checks
+tensor shapes, dtypes and devices, passes raw device pointers and the current
+HIP stream across the C ABI, and turns status codes into exceptions.  PyTorch
+provides device memory and streams, nothing else.
+
+The function names mirror the C entry points.  Arrays are FP64 CUDA(HIP)
+tensors of shape ``[d, n]`` (``d = 2`` for 2D gravity, else 1), contiguous.
+
+torch is imported before the library is loaded, so that libmd binds to the
+HIP runtime torch already holds (both carry the SONAME ``libamdhip64.so.7``)
+and the process has one runtime.  There is no fallback: if ``libmd.so`` has
+not been built, :func:`load` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch  # noqa: F401  (must precede loading libmd: shared HIP runtime)
+
+HMF, RING, GRAV2D = 0, 1, 2
+FP64, MIXED, MIXED_KAHAN, MIXED_PAIRF64, MIXED_F32STATE = 0, 1, 2, 3, 4
+OK, EINVAL, EDEVICE, ENOMEM, ESTATE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+MODEL_NAMES = {HMF: "hmf", RING: "ring", GRAV2D: "grav2d"}
+PREC_NAMES = {FP64: "fp64", MIXED: "mixed", MIXED_KAHAN: "mixed_kahan",
+              MIXED_PAIRF64: "mixed_pairf64", MIXED_F32STATE: "mixed_f32state"}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmd.so")
+
+# name -> (restype, argtypes); every symbol declared in include/md.h
+_V, _I, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "md_workspace_bytes": (_SZ, [_I, _I, _I64]),
+    "md_init": (_I, [ctypes.POINTER(_V), _I, _I, _I64, _D, _V, _V, _SZ]),
+    "md_set_stream": (_I, [_V, _V]),
+    "md_set_tiles": (_I, [_V, _I, _I, _I, _I]),
+    "md_get_tiles": (_I, [_V, ctypes.POINTER(_I)]),
+    "md_max_j_split": (_I, [_I64]),
+    "md_force": (_I, [_V, _V, _V]),
+    "md_step": (_I, [_V, _V, _V, _V, _D, _I64]),
+    "md_energy": (_I, [_V, _V, _V, _V]),
+    "md_magnetization": (_I, [_V, _V, _V]),
+    "md_destroy": (_I, [_V]),
+    "md_strerror": (ctypes.c_char_p, [_I]),
+    "md_last_error": (ctypes.c_char_p, [_V]),
+    "md_version": (ctypes.c_char_p, []),
+}
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+class MDError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {strerror(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+def load() -> ctypes.CDLL:
+    """The loaded libmd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1212_0262_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return load().md_strerror(int(status)).decode()
+
+
+def md_version() -> str:
+    return load().md_version().decode()
+
+
+def dims(model: int) -> int:
+    return 2 if model == GRAV2D else 1
+
+
+def md_workspace_bytes(model: int, prec: int, n: int) -> int:
+    return int(load().md_workspace_bytes(int(model), int(prec), int(n)))
+
+
+def md_max_j_split(n: int) -> int:
+    return int(load().md_max_j_split(int(n)))
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Context:
+    """A libmd context plus the workspace tensor it lives in."""
+
+    def __init__(self, handle: int, model: int, prec: int, n: int, eps: float, workspace: torch.Tensor):
+        self.handle = handle
+        self.model, self.prec, self.n, self.eps = model, prec, n, eps
+        self.d = dims(model)
+        self.workspace = workspace
+
+    def _check(self, status: int, where: str) -> None:
+        if status != OK:
+            detail = load().md_last_error(self.handle).decode() if self.handle else ""
+            raise MDError(status, where, detail)
+
+    def _arr(self, t: torch.Tensor, name: str) -> int:
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name}: expected a device tensor")
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name}: expected float64, got {t.dtype}")
+        if tuple(t.shape) != (self.d, self.n) or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous [{self.d}, {self.n}] tensor, got {tuple(t.shape)}")
+        return t.data_ptr()
+
+    def close(self) -> None:
+        if self.handle:
+            load().md_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def md_init(model: int, prec: int, n: int, eps: float = 0.0, stream=None,
+            workspace: Optional[torch.Tensor] = None) -> Context:
+    """Create a context on the current device; allocates the workspace with torch if not given."""
+    need = md_workspace_bytes(model, prec, n)
+    if workspace is None:
+        if need == 0:
+            raise MDError(EINVAL, "md_init", f"invalid model/prec/n ({model}, {prec}, {n})")
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    st = load().md_init(ctypes.byref(h), int(model), int(prec), int(n), float(eps), _stream_handle(stream),
+                        workspace.data_ptr(), workspace.numel() * workspace.element_size())
+    if st != OK:
+        raise MDError(st, "md_init")
+    return Context(h.value, int(model), int(prec), int(n), float(eps), workspace)
+
+
+def md_set_stream(ctx: Context, stream=None) -> None:
+    ctx._check(load().md_set_stream(ctx.handle, _stream_handle(stream)), "md_set_stream")
+
+
+def md_set_tiles(ctx: Context, i_per_lane: int = 0, waves: int = 0, j_split: int = 0, j_tile: int = 0) -> None:
+    ctx._check(load().md_set_tiles(ctx.handle, int(i_per_lane), int(waves), int(j_split), int(j_tile)),
+               "md_set_tiles")
+
+
+def md_get_tiles(ctx: Context) -> tuple:
+    out = (ctypes.c_int * 4)()
+    ctx._check(load().md_get_tiles(ctx.handle, out), "md_get_tiles")
+    return tuple(int(v) for v in out)
+
+
+def md_force(ctx: Context, q: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
+    ctx._check(load().md_force(ctx.handle, ctx._arr(q, "q"), ctx._arr(f, "f")), "md_force")
+    return f
+
+
+def md_step(ctx: Context, q: torch.Tensor, p: torch.Tensor, f: torch.Tensor, dt: float, nsteps: int) -> None:
+    ctx._check(load().md_step(ctx.handle, ctx._arr(q, "q"), ctx._arr(p, "p"), ctx._arr(f, "f"),
+                              float(dt), int(nsteps)), "md_step")
+
+
+def md_energy(ctx: Context, q: torch.Tensor, p: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """{K, V, E} as a device float64 tensor of 3 (read it on the host to synchronise)."""
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=q.device)
+    if out.dtype != torch.float64 or out.numel() < 3 or out.device.type != "cuda":
+        raise ValueError("out: expected a device float64 tensor of at least 3 elements")
+    ctx._check(load().md_energy(ctx.handle, ctx._arr(q, "q"), ctx._arr(p, "p"), out.data_ptr()), "md_energy")
+    return out
+
+
+def md_magnetization(ctx: Context, q: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=q.device)
+    ctx._check(load().md_magnetization(ctx.handle, ctx._arr(q, "q"), out.data_ptr()), "md_magnetization")
+    return out
+
+
+def md_destroy(ctx: Context) -> None:
+    ctx.close()
