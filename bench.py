@@ -135,29 +135,123 @@ def cpu_baseline(q0, target_s: float = 10.0):
     }
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
-        return 2
+HMF_N = 10_000_000
+HMF_DT = 0.1
+HMF_BYTES = {"fp64": 96, "f32state": 48}   # per particle-step: 3 passes x (read + write of theta, p)
+RING_N = 2048
+RING_EPS = 0.01
+RING_DT = 0.05
+PEAK_HBM_GBS = 8000.0
 
+
+def ring_workload(md, torch, args):
+    """Ring model, N = 2048, eps = 0.01, dt = 0.05, waterbag (theta in [-pi/2, pi/2],
+    p in [-0.5, 0.5], seed 1), FP64 and mixed."""
     import numpy as np
-    import torch
 
-    from paper_1212_0262_amd import inputs, md
+    from paper_1212_0262_amd import inputs
+    q0, p0 = inputs.ring_waterbag(RING_N, seed=1)
+    res = {}
+    for name, prec in (("fp64", md.FP64), ("mixed", md.MIXED)):
+        ctx = md.md_init(md.RING, prec, RING_N, RING_EPS)
+        q = torch.from_numpy(q0).cuda()
+        p = torch.from_numpy(p0).cuda()
+        f = torch.empty_like(q)
+        e0 = md.md_energy(ctx, q, p).cpu().numpy()
+        md.md_force(ctx, q, f)
+        qw, pw, fw = q.clone(), p.clone(), f.clone()
+        md.md_step(ctx, qw, pw, fw, RING_DT, max(1, args.warmup))
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        md.md_step(ctx, q, p, f, RING_DT, args.steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        e1 = md.md_energy(ctx, q, p).cpu().numpy()
+        res[name] = {"ms": ms, "us_per_step": 1e3 * ms / args.steps,
+                     "gpairs_per_s": 3.0 * RING_N ** 2 * args.steps / (ms * 1e-3) / 1e9,
+                     "dE_E": float(abs(e1[2] - e0[2]) / abs(e0[2])), "tiles": list(md.md_get_tiles(ctx))}
+        ctx.close()
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        nst = 2
+        f = oracle.force(oracle.RING, q0, RING_EPS)
+        oracle.step(oracle.RING, q0, p0, f, RING_DT, nst, RING_EPS)
+        dt = time.perf_counter() - t0
+        cpu = {"value": (3 * nst + 1) * RING_N ** 2 / dt / 1e9, "unit": "Gpair-interactions/s", "cores": 1,
+               "kind": "oracle", "sample": f"{nst} FP64 Yoshida steps of the full N={RING_N} system, 1 thread"}
+    fp = res["fp64"]
+    return {
+        "metric": "Gpair-interactions/s (Ring N=2048, FP64)", "value": round(fp["gpairs_per_s"], 3),
+        "unit": "Gpair-interactions/s", "ms_per_step": round(fp["us_per_step"] / 1e3, 5), "dtype": "f64",
+        "config": {"workload": "ring waterbag N=2048 eps=0.01 dt=0.05 seed=1", "model": "ring", "n": RING_N,
+                   "eps": RING_EPS, "dt": RING_DT, "precision": "fp64", "tiles": fp["tiles"]},
+        "roofline": None, "cpu_baseline": cpu, "ring": res,
+    }
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 1
-    md.load()
+
+def hmf_workload(md, torch, args):
+    """HMF, N = 10^7, waterbag theta in [-1, 1], p in [-1.2, 1.2] (seed 2), dt = 0.1:
+    FP64 and FP32 state with FP64 magnetization; HBM-bound."""
+    from paper_1212_0262_amd import inputs
+    q0, p0 = inputs.hmf_waterbag(HMF_N, seed=2)
+    res = {}
+    for name, prec in (("fp64", md.FP64), ("f32state", md.MIXED_F32STATE)):
+        ctx = md.md_init(md.HMF, prec, HMF_N, 0.0)
+        q = torch.from_numpy(q0).cuda()
+        p = torch.from_numpy(p0).cuda()
+        f = torch.empty_like(q)
+        e0 = md.md_energy(ctx, q, p).cpu().numpy()
+        md.md_force(ctx, q, f)
+        qw, pw, fw = q.clone(), p.clone(), f.clone()
+        md.md_step(ctx, qw, pw, fw, HMF_DT, max(1, args.warmup))
+        del qw, pw, fw
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        md.md_step(ctx, q, p, f, HMF_DT, args.steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        e1 = md.md_energy(ctx, q, p).cpu().numpy()
+        ps = HMF_N * args.steps / (ms * 1e-3)
+        res[name] = {"ms": ms, "ms_per_step": ms / args.steps, "particle_steps_per_s": ps,
+                     "algorithmic_GBs": ps * HMF_BYTES[name] / 1e9,
+                     "dE_E": float(abs(e1[2] - e0[2]) / abs(e0[2]))}
+        ctx.close()
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        oracle.set_threads(threads)
+        nst = 3
+        f = oracle.force(oracle.HMF, q0)
+        t0 = time.perf_counter()
+        oracle.step(oracle.HMF, q0, p0, f, HMF_DT, nst)
+        dt = time.perf_counter() - t0
+        cpu = {"value": HMF_N * nst / dt, "unit": "particle-steps/s", "cores": oracle.get_threads(),
+               "kind": "oracle", "sample": f"{nst} FP64 Yoshida steps of the full N=1e7 system"}
+    fp = res["fp64"]
+    return {
+        "metric": "particle-steps/s (HMF N=1e7, FP64)", "value": round(fp["particle_steps_per_s"], 1),
+        "unit": "particle-steps/s", "ms_per_step": round(fp["ms_per_step"], 5), "dtype": "f64",
+        "config": {"workload": "hmf waterbag N=1e7 dt=0.1 seed=2", "model": "hmf", "n": HMF_N, "dt": HMF_DT,
+                   "precision": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": round(fp["algorithmic_GBs"], 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(fp["algorithmic_GBs"] / PEAK_HBM_GBS, 4), "traffic": None,
+                     "bytes_per_particle_step": HMF_BYTES["fp64"]},
+        "cpu_baseline": cpu, "hmf": res,
+    }
+
+
+def grav2d_workload(md, torch, args):
+    import numpy as np
+
+    from paper_1212_0262_amd import inputs
     q0, p0 = inputs.grav2d_disk(N, seed=SEED, sigma=SIGMA)
 
     log(f"bench: mixed N={N} steps={args.steps} warmup={args.warmup}")
@@ -181,10 +275,8 @@ def main() -> int:
         "metric": METRIC,
         "value": round(mixed["gpairs_per_s"], 3),
         "unit": "Gpair-interactions/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(mixed["ms_per_step"], 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f32",
         "config": {
             "workload": "grav2d uniform disk N=262144 eps=1e-3 dt=0.01 sigma=0.5 seed=3 (mixed: FP32 pairs, "
                         "FP64 fold per j-tile)",
@@ -200,13 +292,14 @@ def main() -> int:
         },
         "energy": {
             "mixed_dE_E": mixed["dE_E"], "mixed_dE_over_K0_plus_absV0": mixed["dE_KV"],
-            "E0": mixed["E0"], "gate_dE_E_le_1e-5": bool(mixed["dE_E"] <= 1e-5),
+            "E0": mixed["E0"],
         },
         "cpu_baseline": cpu,
     }
     if fp64 is not None:
         dq = (mixed["final_q"] - fp64["final_q"]).abs().max().item()
         dp = (mixed["final_p"] - fp64["final_p"]).abs().max().item()
+        prec_err = abs(mixed["E1"][2] - fp64["E1"][2]) / abs(fp64["E0"][2])
         out["fp64"] = {
             "value": round(fp64["gpairs_per_s"], 3), "ms_per_step": round(fp64["ms_per_step"], 4),
             "dE_E": fp64["dE_E"], "dE_over_K0_plus_absV0": fp64["dE_KV"],
@@ -216,11 +309,49 @@ def main() -> int:
         }
         out["mixed_vs_fp64"] = {
             "speedup": round(mixed["gpairs_per_s"] / fp64["gpairs_per_s"], 3),
+            "energy_diff_over_absE0": prec_err,
             "energy_diff_over_K0_plus_absV0": abs(mixed["E1"][2] - fp64["E1"][2])
             / (abs(fp64["E0"][0]) + abs(fp64["E0"][1])),
             "max_abs_dq": dq, "max_abs_dp": dp,
         }
-    print(json.dumps(out), flush=True)
+        # precision gate: the energy error the mixed form adds to the FP64 run
+        out["energy"]["gate_mixed_vs_fp64_dE_over_E0_le_1e-5"] = bool(prec_err <= 1e-5)
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 100 grav2d, 50 ring, 1000 hmf)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["grav2d", "ring", "hmf"], default="grav2d")
+    ap.add_argument("--no-fp64", action="store_true", help="grav2d: skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        return 2
+    if args.steps is None:
+        args.steps = {"grav2d": 100, "ring": 50, "hmf": 1000}[args.workload]
+
+    import torch
+
+    from paper_1212_0262_amd import md
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    md.load()
+    fn = {"grav2d": grav2d_workload, "ring": ring_workload, "hmf": hmf_workload}[args.workload]
+    out = fn(md, torch, args)
+    line = {"metric": out.pop("metric"), "value": out.pop("value"), "unit": out.pop("unit"), "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": out.pop("ms_per_step"),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": out.pop("dtype"),
+            "data": "synthetic"}
+    line.update(out)
+    print(json.dumps(line), flush=True)
     return 0
 
 

@@ -119,6 +119,10 @@ def test_energy_matches_oracle(model, eps, n):
     eo = oracle.energy(model, q, p, eps)
     eg = gpu_energy(model, q, p, eps)
     scale = abs(eo[0]) + abs(eo[1])
+    if model == HMF:
+        # V = (N/2)(1 - Mx^2 - My^2) is formed by cancellation against 1: its
+        # rounding scale is N/2, whatever the size of V itself
+        scale += n / 2
     assert np.abs(eg - eo).max() <= 1e-12 * max(scale, 1e-300), (eg, eo)
 
 
@@ -204,13 +208,20 @@ def test_time_reversal_fp64():
     assert np.abs(host(pd) - p).max() < 1e-11
 
 
-def test_momentum_conserved():
+@pytest.mark.parametrize("prec,tol", [(md.FP64, 1e-12), (md.MIXED, 1e-6)])
+def test_momentum_conserved(prec, tol):
+    """The pair terms are antisymmetric (f_ij = -f_ji, bitwise, in either precision)
+    and central, so total and angular momentum change only through the rounding
+    of the per-particle sums.  FP64: roundoff.  Mixed: each FP32 j-tile partial
+    (128 terms of size O(1), running sums up to ~50) carries ~1e-7 relative
+    rounding, so sum_i f_i ~ sqrt(N) * 1e-7 = 6e-6 per evaluation; times a kick
+    of ~0.007 over 30 stages, a random walk of ~2.5e-7 (linear worst case 1.3e-6)."""
     q, p = _state(GRAV2D, 4096, seed=61)
-    qg, pg, fg, _ = gpu_run(GRAV2D, md.MIXED, q, p, 1e-3, 0.01, 10)
-    assert np.abs(pg.sum(axis=1) - p.sum(axis=1)).max() < 1e-9
+    qg, pg, fg, _ = gpu_run(GRAV2D, prec, q, p, 1e-3, 0.01, 10)
+    assert np.abs(pg.sum(axis=1) - p.sum(axis=1)).max() < tol
     L0 = np.sum(q[0] * p[1] - q[1] * p[0])
     L1 = np.sum(qg[0] * pg[1] - qg[1] * pg[0])
-    assert abs(L1 - L0) < 1e-9
+    assert abs(L1 - L0) < tol
 
 
 def test_zero_steps_and_argument_errors():
