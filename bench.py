@@ -44,7 +44,7 @@ FLOPS_PER_PAIR = 10          # 2 sub, 2 FMA (r^2 + eps), 2 FMA (accumulate); plu
 PEAK_FP32_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32 (packed FP32 is not used)
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
-PAIR_KERNEL_SRC = os.path.join(ROOT, "paper_1212_0262_amd", "csrc", "pair.hip")
+PAIR_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("pair.hip", "device.h")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "grav2d_pair_mixed_n262144_pmc.txt")
 
 
@@ -53,20 +53,27 @@ def log(msg: str) -> None:
 
 
 def pair_kernel_hash() -> str:
-    with open(PAIR_KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sources the pair kernel is compiled from."""
+    h = hashlib.sha256()
+    for fn in PAIR_KERNEL_SRCS:
+        with open(fn, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
+def traffic_from_profile(tiles):
     """HBM bytes per pair-kernel launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source with the same tiles; else None."""
     try:
         txt = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    t = re.search(r"tiles_ipl_waves_jsplit_jtile:\s*([0-9, ]+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != pair_kernel_hash():
+    if not (m and t and b) or m.group(1) != pair_kernel_hash():
+        return None
+    if [int(x) for x in t.group(1).replace(" ", "").split(",") if x] != list(tiles):
         return None
     return float(b.group(1))
 
@@ -285,7 +292,7 @@ def grav2d_workload(md, torch, args):
         },
         "roofline": {
             "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_from_profile(),
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_from_profile(mixed["tiles"]),
             "kernel": "k_pair_2d<float, AccTile, ipl>",
             "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": N * N,
             "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),

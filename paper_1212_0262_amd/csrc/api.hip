@@ -186,20 +186,27 @@ int max_j_split(int64_t n)
     return s < 1 ? 1 : (int)s;
 }
 
+// Built-in tile choice (measured on MI355X, md_force at N = 2048 .. 262144): the
+// pair kernels are VALU-issue bound, so the aim is enough independent wavefronts
+// (several rounds of 8 per SIMD over 1024 SIMDs, which evens out the tail) while
+// each block keeps a j range long enough to amortise its i loads and its output.
 Tiles default_tiles(int model, int prec, int64_t n)
 {
     (void)model;
     (void)prec;
     Tiles t;
     t.waves = 4;
-    t.ipl = n >= 16384 ? 2 : 1;
+    t.ipl = n >= 65536 ? 2 : 1;
     t.jtile = 128;
     const int64_t wi = (n + kWave * t.ipl - 1) / (kWave * t.ipl);
-    int64_t s = (8192 + wi - 1) / wi;
-    const int64_t by_len = n / 64 > 0 ? n / 64 : 1;
-    if (s > by_len) s = by_len;
-    if (s > max_j_split(n)) s = max_j_split(n);
-    t.jsplit = s < 1 ? 1 : (int)s;
+    const int64_t target = n >= 65536 ? 32768 : 16384;
+    int64_t s = target / wi;
+    int64_t cap = n > 2048 ? n / 128 : n / 64;
+    if (cap > max_j_split(n)) cap = max_j_split(n);
+    if (s > cap) s = cap;
+    int64_t p2 = 1;
+    while (p2 * 2 <= s) p2 *= 2;
+    t.jsplit = (int)p2;
     return t;
 }
 
