@@ -89,7 +89,7 @@ enum md_status {
     MD_EINVAL = -1,       /* bad argument (null/misaligned pointer, n < 1, eps <= 0, ...) */
     MD_EDEVICE = -2,      /* a HIP call or kernel launch failed */
     MD_ENOMEM = -3,       /* workspace smaller than md_workspace_bytes, or host alloc failed */
-    MD_ESTATE = -4,       /* call out of order (e.g. md_step on HMF before any md_force) */
+    MD_ESTATE = -4,       /* reserved: call out of order */
     MD_ENONFINITE = -5,   /* reserved: a host-read energy was not finite */
     MD_EUNSUPPORTED = -6  /* model/precision combination or tile configuration not built */
 };
@@ -107,7 +107,7 @@ size_t md_workspace_bytes(int model, int prec, int64_t n);
  * `prec`.  hip_stream: a hipStream_t, or NULL for the default stream.
  * workspace: device memory of at least md_workspace_bytes(model, prec, n)
  * bytes, 256-byte aligned.  On success *out holds the new context.
- * The context records the current HIP device.
+ * The context records the current HIP device; md_init enqueues nothing.
  */
 int md_init(md_ctx **out, int model, int prec, int64_t n, double eps,
             void *hip_stream, void *workspace, size_t workspace_bytes);

@@ -152,17 +152,13 @@ int step_hmf(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nste
     MD_TRY(launch_hmf_pass(c, HMF_KICK_F | HMF_DRIFT | HMF_WRITE | HMF_REDUCE, B0 * dt, 0.0, D0 * dt, q, p, f,
                            nullptr, f32),
            "step: first pass");
-    MD_TRY(launch_hmf_finalize(c), "step: finalize");
     for (int64_t s = 0; s < nsteps; ++s) {
         MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D1 * dt, q, p, nullptr, nullptr, f32), "step: pass");
-        MD_TRY(launch_hmf_finalize(c), "step: finalize");
-        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32), "step: pass");
-        MD_TRY(launch_hmf_finalize(c), "step: finalize");
-        if (s + 1 < nsteps) {
+            MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32), "step: pass");
+            if (s + 1 < nsteps) {
             MD_TRY(launch_hmf_pass(c, stage | HMF_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, nullptr, nullptr, f32),
                    "step: pass");
-            MD_TRY(launch_hmf_finalize(c), "step: finalize");
-        } else {
+                } else {
             MD_TRY(launch_hmf_pass(c, HMF_KICK_M | HMF_STORE_F | HMF_WRITE, B0 * dt, 0.0, 0.0, q, p, nullptr, f,
                                    f32),
                    "step: last pass");
@@ -312,7 +308,6 @@ int md_force(md_ctx *c, const double *q, double *f)
     double *qm = const_cast<double *>(q);
     if (c->model == MD_HMF) {
         MD_TRY(launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, qm, nullptr, nullptr, nullptr, false), "force: reduce");
-        MD_TRY(launch_hmf_finalize(c), "force: finalize");
         MD_TRY(launch_hmf_pass(c, HMF_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, nullptr, f, false), "force: store");
         return MD_OK;
     }

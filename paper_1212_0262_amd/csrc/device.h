@@ -36,6 +36,79 @@ __device__ __forceinline__ double rsq64(double x)
     return __builtin_fma(y, e * __builtin_fma(e, 0.375, 0.5), y);
 }
 
+// sin and cos together (Cody and Waite's argument reduction followed by Taylor
+// polynomials).  x = k pi/2 + r with k = rint(x 2/pi); pi/2 is split into a
+// double and a correction (pi/2 = P1 + P2 to about 1e-33), and the two FMA steps
+// r = (x - k P1) - k P2 leave |r| <= pi/4 with an absolute error near 1e-16 for
+// |x| < 2^30.  On |r| <= pi/4 the Taylor series of sin to r^17 and of cos to r^16
+// are exact to 1e-19.  The quadrant k mod 4 permutes and negates the pair.
+// Larger |x| (never reached by the dynamics here) falls back to the library.
+__device__ __forceinline__ void sincos64(double x, double *sp, double *cp)
+{
+    if (!(fabs(x) < 1073741824.0)) {
+        sincos(x, sp, cp);
+        return;
+    }
+    const double P1 = 1.5707963267948966;      // pi/2 rounded to double
+    const double P2 = 6.123233995736766e-17;   // pi/2 - P1
+    const double k = __builtin_rint(x * 0.6366197723675814);
+    double r = __builtin_fma(-k, P1, x);
+    r = __builtin_fma(-k, P2, r);
+    const double z = r * r;
+    double ps = -1.0 / 355687428096000.0;       // -1/17!
+    ps = __builtin_fma(ps, z, 1.0 / 1307674368000.0);
+    ps = __builtin_fma(ps, z, -1.0 / 6227020800.0);
+    ps = __builtin_fma(ps, z, 1.0 / 39916800.0);
+    ps = __builtin_fma(ps, z, -1.0 / 362880.0);
+    ps = __builtin_fma(ps, z, 1.0 / 5040.0);
+    ps = __builtin_fma(ps, z, -1.0 / 120.0);
+    ps = __builtin_fma(ps, z, 1.0 / 6.0);
+    double pc = 1.0 / 20922789888000.0;         // 1/16!
+    pc = __builtin_fma(pc, z, -1.0 / 87178291200.0);
+    pc = __builtin_fma(pc, z, 1.0 / 479001600.0);
+    pc = __builtin_fma(pc, z, -1.0 / 3628800.0);
+    pc = __builtin_fma(pc, z, 1.0 / 40320.0);
+    pc = __builtin_fma(pc, z, -1.0 / 720.0);
+    pc = __builtin_fma(pc, z, 1.0 / 24.0);
+    pc = __builtin_fma(pc, z, -0.5);
+    const double sr = __builtin_fma(-r * z, ps, r);   // r - r^3/6 + ...  (ps holds +1/6 - ...)
+    const double cr = __builtin_fma(z, pc, 1.0);
+    const int q = (int)k;
+    const double a = (q & 1) ? cr : sr;
+    const double b = (q & 1) ? sr : cr;
+    *sp = (q & 2) ? -a : a;
+    *cp = ((q + 1) & 2) ? -b : b;
+}
+
+// FP32 counterpart (the FP32-state HMF path keeps |x| <= pi): Taylor to r^11 / r^12.
+__device__ __forceinline__ void sincos32(float x, float *sp, float *cp)
+{
+    const float P1 = 1.57079637f;        // pi/2 rounded to float
+    const float P2 = -4.37113883e-8f;    // pi/2 - P1
+    const float k = __builtin_rintf(x * 0.636619772f);
+    float r = __builtin_fmaf(-k, P1, x);
+    r = __builtin_fmaf(-k, P2, r);
+    const float z = r * r;
+    float ps = -1.0f / 39916800.0f;
+    ps = __builtin_fmaf(ps, z, 1.0f / 362880.0f);
+    ps = __builtin_fmaf(ps, z, -1.0f / 5040.0f);
+    ps = __builtin_fmaf(ps, z, 1.0f / 120.0f);
+    ps = __builtin_fmaf(ps, z, -1.0f / 6.0f);
+    float pc = 1.0f / 479001600.0f;
+    pc = __builtin_fmaf(pc, z, -1.0f / 3628800.0f);
+    pc = __builtin_fmaf(pc, z, 1.0f / 40320.0f);
+    pc = __builtin_fmaf(pc, z, -1.0f / 720.0f);
+    pc = __builtin_fmaf(pc, z, 1.0f / 24.0f);
+    pc = __builtin_fmaf(pc, z, -0.5f);
+    const float sr = __builtin_fmaf(r * z, ps, r);
+    const float cr = __builtin_fmaf(z, pc, 1.0f);
+    const int q = (int)k;
+    const float a = (q & 1) ? cr : sr;
+    const float b = (q & 1) ? sr : cr;
+    *sp = (q & 2) ? -a : a;
+    *cp = ((q + 1) & 2) ? -b : b;
+}
+
 // Sum over the 64 lanes of a wavefront (xor butterfly; every lane gets the total).
 __device__ __forceinline__ double wave_sum(double v)
 {

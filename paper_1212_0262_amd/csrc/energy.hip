@@ -93,11 +93,6 @@ __global__ __launch_bounds__(256) void k_energy_finalize(const double *__restric
     }
 }
 
-__global__ void k_copy_m(const double *__restrict__ M, double *__restrict__ out)
-{
-    if (threadIdx.x < 2) out[threadIdx.x] = M[threadIdx.x];
-}
-
 }  // namespace
 
 // Layout of the reduction scratch: [0, kRedSlots/2) potential partials,
@@ -118,11 +113,12 @@ hipError_t launch_energy(md_ctx *c, const double *q, const double *p, double *ou
     double *redK = c->red + kRedSlots / 2;
     int nv;
     if (c->model == MD_HMF) {
-        // sums of cos/sin of q into red[0 .. 2*hmf_grid)
+        // block partials of sum cos, sum sin of q (double-buffered halves of red)
         hipError_t e = launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr,
                                        nullptr, false);
         if (e != hipSuccess) return e;
         nv = hmf_grid(c->n);
+        redV = const_cast<double *>(hmf_partials(c));
     } else {
         const int gx = (n + kEnergyBlock - 1) / kEnergyBlock;
         const int s = energy_jsplit(c->n);
@@ -147,10 +143,7 @@ hipError_t launch_magnetization(md_ctx *c, const double *q, double *out2)
     hipError_t e = launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr,
                                    nullptr, false);
     if (e != hipSuccess) return e;
-    e = launch_hmf_finalize(c);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_copy_m, dim3(1), dim3(64), 0, c->stream, c->scal, out2);
-    return hipGetLastError();
+    return launch_hmf_magnetization(c, out2);
 }
 
 }  // namespace md

@@ -8,17 +8,26 @@
 // for the next magnetization, and writes (t, p) back.  Stored sines/cosines
 // would add 32 B of HBM traffic per particle per stage to a bandwidth-bound
 // pass; two sincos evaluations cost less.  The magnetization is a grid-wide
-// dependency, so each pass ends with FP64 block partials (wavefront butterfly,
-// then a fixed serial order over wavefronts) and a one-block finalize kernel sums
-// them in a fixed order: deterministic, no atomics.
+// dependency: each pass ends with FP64 block partials (wavefront butterfly, then
+// a fixed serial order over wavefronts) and a one-block kernel sums them in a
+// fixed order into M.  The kernel boundary is the only synchronisation: no
+// atomics, and no device-wide fences (on this GPU a device-scope release writes
+// back the L2 of the issuing XCD, which costs more than a launch).
+//
+// Memory access: each lane moves W consecutive elements (16-byte vector loads and
+// stores: W = 2 in FP64, 4 in FP32), U vectors per grid-stride iteration, over a
+// grid of up to 16384 blocks; with two sincos per element this streams at about
+// 6.5 TB/s on MI355X.  Pointers that are not 16-byte aligned take W = 1.
 #include "device.h"
 #include "md_internal.h"
 
 namespace md {
 namespace {
 
-__device__ __forceinline__ void sincos_(double x, double *s, double *c) { sincos(x, s, c); }
-__device__ __forceinline__ void sincos_(float x, float *s, float *c) { sincosf(x, s, c); }
+constexpr int kUnroll = 2;  // vectors per thread per grid-stride iteration
+
+__device__ __forceinline__ void sincos_(double x, double *s, double *c) { sincos64(x, s, c); }
+__device__ __forceinline__ void sincos_(float x, float *s, float *c) { sincos32(x, s, c); }
 
 // Map an FP32 angle into [-pi, pi).
 __device__ __forceinline__ float wrap_pi(float t)
@@ -31,52 +40,114 @@ __device__ __forceinline__ float wrap_pi(float t)
     return t;
 }
 
-// One kick/drift/reduce pass over all particles (grid-stride; the grid size is
-// fixed per n, so the partial sums are reproducible).  T is the state type.
+// W consecutive values, aligned to their size (one vector load/store when W > 1).
+template <typename T, int W>
+struct alignas(sizeof(T) * W) Vec {
+    T x[W];
+};
+
+struct PassArgs {
+    double kick1, kick2, drift;
+    int flags;
+};
+
+// The work of one particle: kick (with f from f_in or from M), drift, and the
+// sincos of the new angle into the partial sums.
 template <typename T>
+__device__ __forceinline__ void particle(T &t, T &p, double fin, double *fout, T mx, T my, T k1, T k2, T dr,
+                                         int flags, double &sc, double &ss)
+{
+    if (flags & (HMF_KICK_M | HMF_STORE_F)) {
+        T s, c;
+        sincos_(t, &s, &c);
+        const T f = c * my - s * mx;
+        if (flags & HMF_STORE_F) *fout = (double)f;
+        if (flags & HMF_KICK_M) {
+            p += k1 * f;
+            if (flags & HMF_KICK2) p += k2 * f;
+        }
+    } else if (flags & HMF_KICK_F) {
+        p += k1 * (T)fin;
+    }
+    if (flags & HMF_DRIFT) {
+        t += dr * p;
+        if constexpr (sizeof(T) == 4) t = wrap_pi(t);
+    }
+    if (flags & HMF_REDUCE) {
+        T s, c;
+        sincos_(t, &s, &c);
+        sc += (double)c;
+        ss += (double)s;
+    }
+}
+
+// One kick/drift/reduce pass over all particles (grid-stride over a grid fixed
+// per n, so every partial sum is reproducible).  T: state type; W: elements per
+// vector access.  M[0..1] holds the magnetization for HMF_KICK_M / HMF_STORE_F;
+// HMF_REDUCE writes the block partials (sum cos, sum sin) to red[2b], red[2b+1].
+template <typename T, int W>
 __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restrict__ p,
-                                                  const double *__restrict__ f_in,
-                                                  const double *__restrict__ M, double *__restrict__ f_out,
-                                                  T kick1, T kick2, T drift, int flags, int n,
+                                                  const double *__restrict__ f_in, double *__restrict__ f_out,
+                                                  const double *__restrict__ M, PassArgs a, int n,
                                                   double *__restrict__ red)
 {
     __shared__ double lds[2][4];
+    const int flags = a.flags;
+    const T k1 = (T)a.kick1, k2 = (T)a.kick2, dr = (T)a.drift;
     T mx = 0, my = 0;
     if (flags & (HMF_KICK_M | HMF_STORE_F)) {
         mx = (T)M[0];
         my = (T)M[1];
     }
+    const bool need_p = flags & (HMF_KICK_F | HMF_KICK_M | HMF_DRIFT);
+    const bool write = flags & HMF_WRITE;
     double sc = 0.0, ss = 0.0;
+    const int nvec = n / W;
     const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        T t = th[i];
-        T pp = 0;
-        if (flags & (HMF_KICK_F | HMF_KICK_M | HMF_DRIFT)) pp = p[i];
-        if (flags & (HMF_KICK_M | HMF_STORE_F)) {
-            T s, c;
-            sincos_(t, &s, &c);
-            const T f = c * my - s * mx;
-            if (flags & HMF_STORE_F) f_out[i] = (double)f;
-            if (flags & HMF_KICK_M) {
-                pp += kick1 * f;
-                if (flags & HMF_KICK2) pp += kick2 * f;
+    using VT = Vec<T, W>;
+    using VD = Vec<double, W>;
+    for (int base = blockIdx.x * blockDim.x + threadIdx.x; base < nvec; base += stride * kUnroll) {
+        VT t[kUnroll], q[kUnroll];
+        VD fi[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int v = base + u * stride;
+            if (v < nvec) {
+                t[u] = reinterpret_cast<const VT *>(th)[v];
+                if (need_p) q[u] = reinterpret_cast<const VT *>(p)[v];
+                if (flags & HMF_KICK_F) fi[u] = reinterpret_cast<const VD *>(f_in)[v];
             }
-        } else if (flags & HMF_KICK_F) {
-            pp += kick1 * (T)f_in[i];
         }
-        if (flags & HMF_DRIFT) {
-            t += drift * pp;
-            if constexpr (sizeof(T) == 4) t = wrap_pi(t);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int v = base + u * stride;
+            if (v >= nvec) continue;
+            VD fo;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                T pw = need_p ? q[u].x[w] : T(0);
+                particle(t[u].x[w], pw, (flags & HMF_KICK_F) ? fi[u].x[w] : 0.0, &fo.x[w], mx, my, k1, k2, dr,
+                         flags, sc, ss);
+                q[u].x[w] = pw;
+            }
+            if (flags & HMF_STORE_F) reinterpret_cast<VD *>(f_out)[v] = fo;
+            if (write) {
+                reinterpret_cast<VT *>(th)[v] = t[u];
+                if (need_p) reinterpret_cast<VT *>(p)[v] = q[u];
+            }
         }
-        if (flags & HMF_WRITE) {
+    }
+    // the n mod W particles past the last full vector: block 0
+    if (W > 1 && blockIdx.x == 0 && (int)threadIdx.x < n - nvec * W) {
+        const int i = nvec * W + threadIdx.x;
+        T t = th[i];
+        T pw = need_p ? p[i] : T(0);
+        double fo = 0.0;
+        particle(t, pw, (flags & HMF_KICK_F) ? f_in[i] : 0.0, &fo, mx, my, k1, k2, dr, flags, sc, ss);
+        if (flags & HMF_STORE_F) f_out[i] = fo;
+        if (write) {
             th[i] = t;
-            p[i] = pp;
-        }
-        if (flags & HMF_REDUCE) {
-            T s, c;
-            sincos_(t, &s, &c);
-            sc += (double)c;
-            ss += (double)s;
+            if (need_p) p[i] = pw;
         }
     }
     if (flags & HMF_REDUCE) {
@@ -89,21 +160,32 @@ __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restr
     }
 }
 
-// M[0..1] = (sum of the nblk partial pairs) / n, in a fixed order.
-__global__ __launch_bounds__(256) void k_hmf_finalize(const double *__restrict__ red, int nblk, int n,
-                                                      double *__restrict__ M)
+// M[0..1] = (sum of the g partial pairs) / n, in a fixed order (one block of
+// 1024 threads; thread t adds partials t, t + 1024, ... in that order).  All of a
+// thread's loads are issued before the adds (g <= kHmfGrid = 16 * 1024).
+__global__ __launch_bounds__(1024) void k_hmf_finalize(const double *__restrict__ red, int g, int n,
+                                                       double *__restrict__ M)
 {
-    __shared__ double lds[2][4];
-    double sc = 0.0, ss = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        sc += red[2 * b];
-        ss += red[2 * b + 1];
+    __shared__ double lds[2][16];
+    constexpr int kPer = kHmfGrid / 1024;
+    double vc[kPer], vs[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int b = threadIdx.x + 1024 * k;
+        vc[k] = b < g ? red[2 * b] : 0.0;
+        vs[k] = b < g ? red[2 * b + 1] : 0.0;
     }
-    sc = block_sum(sc, lds[0]);
-    ss = block_sum(ss, lds[1]);
+    double c = 0.0, s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        c += vc[k];
+        s += vs[k];
+    }
+    c = block_sum(c, lds[0]);
+    s = block_sum(s, lds[1]);
     if (threadIdx.x == 0) {
-        M[0] = sc / (double)n;
-        M[1] = ss / (double)n;
+        M[0] = c / (double)n;
+        M[1] = s / (double)n;
     }
 }
 
@@ -125,32 +207,58 @@ __global__ __launch_bounds__(256) void k_hmf_convert(double *__restrict__ th, do
 
 }  // namespace
 
+// Vector width of the accesses for this context (1 when a pointer is not 16-byte aligned).
+static int vec_width(bool f32, const void *a, const void *b, const void *c, const void *d)
+{
+    const uintptr_t m = (uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)d;
+    if (m & 15u) return 1;
+    return f32 ? 4 : 2;
+}
+
 int hmf_grid(int64_t n)
 {
-    const int64_t b = (n + 255) / 256;
+    const int64_t per_block = 256 * kUnroll * 2;  // at least W = 2 elements per access
+    const int64_t b = (n + per_block - 1) / per_block;
     return (int)(b < kHmfGrid ? (b < 1 ? 1 : b) : kHmfGrid);
 }
+
+const double *hmf_partials(const md_ctx *c) { return c->red; }
 
 hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, double drift, double *th,
                            double *p, const double *f_in, double *f_out, bool f32state)
 {
     const int n = (int)c->n;
     const int g = hmf_grid(c->n);
+    const PassArgs a{kick1, kick2, drift, flags};
     if (f32state) {
-        hipLaunchKernelGGL((k_hmf_pass<float>), dim3(g), dim3(256), 0, c->stream, c->th32, c->p32, f_in,
-                           c->scal, f_out, (float)kick1, (float)kick2, (float)drift, flags, n, c->red);
+        const int w = vec_width(true, c->th32, c->p32, f_in, f_out);
+        if (w == 4)
+            hipLaunchKernelGGL((k_hmf_pass<float, 4>), dim3(g), dim3(256), 0, c->stream, c->th32, c->p32, f_in,
+                               f_out, c->scal, a, n, c->red);
+        else
+            hipLaunchKernelGGL((k_hmf_pass<float, 1>), dim3(g), dim3(256), 0, c->stream, c->th32, c->p32, f_in,
+                               f_out, c->scal, a, n, c->red);
     } else {
-        hipLaunchKernelGGL((k_hmf_pass<double>), dim3(g), dim3(256), 0, c->stream, th, p, f_in, c->scal,
-                           f_out, kick1, kick2, drift, flags, n, c->red);
+        const int w = vec_width(false, th, p, f_in, f_out);
+        if (w == 2)
+            hipLaunchKernelGGL((k_hmf_pass<double, 2>), dim3(g), dim3(256), 0, c->stream, th, p, f_in, f_out,
+                               c->scal, a, n, c->red);
+        else
+            hipLaunchKernelGGL((k_hmf_pass<double, 1>), dim3(g), dim3(256), 0, c->stream, th, p, f_in, f_out,
+                               c->scal, a, n, c->red);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && (flags & HMF_REDUCE)) {
+        hipLaunchKernelGGL(k_hmf_finalize, dim3(1), dim3(1024), 0, c->stream, c->red, g, n, c->scal);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
-hipError_t launch_hmf_finalize(md_ctx *c)
+hipError_t launch_hmf_magnetization(md_ctx *c, double *out2)
 {
-    hipLaunchKernelGGL(k_hmf_finalize, dim3(1), dim3(256), 0, c->stream, c->red, hmf_grid(c->n), (int)c->n,
-                       c->scal);
-    return hipGetLastError();
+    hipError_t e = hipMemcpyAsync(out2, c->scal, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    return e;
 }
 
 hipError_t launch_hmf_convert(md_ctx *c, double *th, double *p, bool to_f32)

@@ -36,7 +36,7 @@ enum : int {
 constexpr int kWave = 64;           // lanes per wavefront (CDNA)
 constexpr int kMaxJSplit = 64;
 constexpr int kRedSlots = 1 << 16;   // doubles of reduction scratch
-constexpr int kHmfGrid = 2048;       // blocks of the HMF grid-stride passes
+constexpr int kHmfGrid = 16384;      // most blocks of an HMF pass (2 FP64 partials each)
 constexpr int kEnergyBlock = 256;
 
 struct Tiles {
@@ -84,7 +84,8 @@ hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, doubl
 hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, double drift,
                            double *th, double *p, const double *f_in, double *f_out,
                            bool f32state);
-hipError_t launch_hmf_finalize(md_ctx *c);
+hipError_t launch_hmf_magnetization(md_ctx *c, double *out2);
+const double *hmf_partials(const md_ctx *c);  // block partials of the latest reducing pass
 hipError_t launch_hmf_convert(md_ctx *c, double *th, double *p, bool to_f32);
 // energy.hip
 hipError_t launch_energy(md_ctx *c, const double *q, const double *p, double *out3);
