@@ -19,6 +19,7 @@ the FP64 CPU oracle's pair throughput on a bounded sample of force rows of the
 same configuration (cpu_baseline).
 
 Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-fp64] [--no-cpu]
+       python bench.py --workload ring|hmf|ensemble   (the other workloads)
 """
 from __future__ import annotations
 
@@ -255,6 +256,96 @@ def hmf_workload(md, torch, args):
     }
 
 
+ENS_NB = 256
+ENS_EPS = 0.01
+ENS_DT = 0.05
+
+
+def ensemble_workload(md, torch, args):
+    """Ring ensemble: 256 realizations, N_b = round(exp(U(ln 1000, ln 16384))) (seed 4),
+    waterbag ICs per realization (seeded [4, b]), eps = 0.01, dt = 0.05, FP32 pairs
+    with Kahan-compensated accumulation; tiles autotuned; the whole run replayed as
+    one captured HIP graph."""
+    import numpy as np
+
+    from paper_1212_0262_amd import autotune, inputs
+    sizes = inputs.ensemble_sizes(ENS_NB, seed=4)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    parts = [inputs.ensemble_member(b, int(n), seed=4) for b, n in enumerate(sizes)]
+    q0 = np.concatenate([a for a, _ in parts], axis=1)
+    p0 = np.concatenate([b for _, b in parts], axis=1)
+    pairs_per_eval = float((sizes.astype(np.float64) ** 2).sum())
+    prec = md.MIXED_KAHAN
+    stream = torch.cuda.Stream()
+    torch.cuda.current_stream().wait_stream(stream)
+    ctx = md.md_batch_init(md.RING, prec, off, ENS_EPS, stream=stream)
+    q = torch.from_numpy(q0).cuda()
+    p = torch.from_numpy(p0).cuda()
+    f = torch.empty_like(q)
+    torch.cuda.synchronize()
+    default_tiles = md.md_get_tiles(ctx)
+    with torch.cuda.stream(stream):
+        t_default = autotune.time_force(ctx, q)
+        best, table = autotune.tune(ctx, q, cache=None)
+    log(f"bench: ensemble tiles default {default_tiles} {t_default:.3f} ms/force, tuned {best} {table[0][1]:.3f} ms")
+    with torch.cuda.stream(stream):
+        e0 = md.md_energy(ctx, q, p).cpu().numpy()
+        md.md_force(ctx, q, f)
+        # eager run on copies (also the warm-up)
+        qe, pe, fe = q.clone(), p.clone(), f.clone()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        md.md_step(ctx, qe, pe, fe, ENS_DT, args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        eager_ms = ev0.elapsed_time(ev1)
+        # capture the whole run as one graph on the real buffers, then replay it once (timed)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            md.md_step(ctx, q, p, f, ENS_DT, args.steps)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        g.replay()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = ev0.elapsed_time(ev1)
+        e1 = md.md_energy(ctx, q, p).cpu().numpy()
+        same = bool(torch.equal(q, qe) and torch.equal(p, pe))
+    dE = np.abs(e1[:, 2] - e0[:, 2]) / np.abs(e0[:, 2])
+    pairs = 3.0 * pairs_per_eval * args.steps
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        oracle.set_threads(threads)
+        small = np.argsort(sizes)[:8]
+        t0 = time.perf_counter()
+        npairs = 0.0
+        for b in small:
+            qb, pb = q0[:, off[b]:off[b + 1]], p0[:, off[b]:off[b + 1]]
+            fo = oracle.force(oracle.RING, qb, ENS_EPS)
+            oracle.step(oracle.RING, qb, pb, fo, ENS_DT, 2, ENS_EPS)
+            npairs += 7.0 * float(sizes[b]) ** 2
+        dt = time.perf_counter() - t0
+        cpu = {"value": npairs / dt / 1e9, "unit": "Gpair-interactions/s", "cores": oracle.get_threads(),
+               "kind": "oracle", "sample": "force + 2 FP64 Yoshida steps of the 8 smallest realizations"}
+    ctx.close()
+    return {
+        "metric": "Gpair-interactions/s (Ring ensemble, 256 realizations, graph-replayed)",
+        "value": round(pairs / (graph_ms * 1e-3) / 1e9, 3), "unit": "Gpair-interactions/s",
+        "ms_per_step": round(graph_ms / args.steps, 4), "dtype": "f32",
+        "config": {"workload": "ring ensemble nb=256 N_b log-uniform [1000,16384] seed=4 eps=0.01 dt=0.05",
+                   "model": "ring", "nb": ENS_NB, "n_total": int(off[-1]), "pairs_per_eval": pairs_per_eval,
+                   "precision": "mixed_kahan", "tiles": list(best), "tiles_default": list(default_tiles)},
+        "roofline": None, "cpu_baseline": cpu,
+        "ensemble": {"graph_ms": graph_ms, "eager_ms": eager_ms, "graph_equals_eager": same,
+                     "force_ms_default_tiles": t_default, "force_ms_tuned": table[0][1],
+                     "tune_table_top5": [[list(t), ms] for t, ms in table[:5]],
+                     "dE_E_max": float(dE.max()), "dE_E_median": float(np.median(dE))},
+    }
+
+
 def grav2d_workload(md, torch, args):
     import numpy as np
 
@@ -331,7 +422,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 100 grav2d, 50 ring, 1000 hmf)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["grav2d", "ring", "hmf"], default="grav2d")
+    ap.add_argument("--workload", choices=["grav2d", "ring", "hmf", "ensemble"], default="grav2d")
     ap.add_argument("--no-fp64", action="store_true", help="grav2d: skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
@@ -341,7 +432,7 @@ def main() -> int:
               "(the sharded design is described in DESIGN.md)", file=sys.stderr)
         return 2
     if args.steps is None:
-        args.steps = {"grav2d": 100, "ring": 50, "hmf": 1000}[args.workload]
+        args.steps = {"grav2d": 100, "ring": 50, "hmf": 1000, "ensemble": 200}[args.workload]
 
     import torch
 
@@ -351,7 +442,8 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     md.load()
-    fn = {"grav2d": grav2d_workload, "ring": ring_workload, "hmf": hmf_workload}[args.workload]
+    fn = {"grav2d": grav2d_workload, "ring": ring_workload, "hmf": hmf_workload,
+          "ensemble": ensemble_workload}[args.workload]
     out = fn(md, torch, args)
     line = {"metric": out.pop("metric"), "value": out.pop("value"), "unit": out.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": out.pop("ms_per_step"),

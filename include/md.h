@@ -112,6 +112,33 @@ size_t md_workspace_bytes(int model, int prec, int64_t n);
 int md_init(md_ctx **out, int model, int prec, int64_t n, double eps,
             void *hip_stream, void *workspace, size_t workspace_bytes);
 
+/*
+ * Batched ensembles: nb independent realizations of one pair model (MD_RING or
+ * MD_GRAV2D; MD_HMF is MD_EUNSUPPORTED) advanced together, e.g. for ensemble
+ * averages over initial conditions of quasi-stationary states (Sec. 1).  Each
+ * realization b is the system of eqs. 1 or 3 with its own N_b = offsets[b+1] -
+ * offsets[b] >= 1 particles, its own 1/N_b coupling and its own eps[b] > 0;
+ * realizations do not interact.
+ *   offsets: host int64 [nb + 1], offsets[0] = 0, strictly increasing,
+ *            offsets[nb] <= 2^24 (total particles).
+ *   eps:     host FP64 [nb].
+ * Arrays passed to md_force / md_step / md_energy are the realizations
+ * concatenated in order: device FP64 [d][offsets[nb]].  md_energy then writes
+ * 3*nb doubles, {K, V, E} of realization b at out[3b .. 3b+2].  md_set_tiles
+ * applies to every realization; j_split is the number of j chunks of the largest
+ * realization (smaller ones use the same chunk length, so fewer chunks), up to
+ * min(32, N_max/64).  md_batch_init copies its work lists into the workspace with
+ * asynchronous copies on hip_stream (the host arrays may be freed on return);
+ * md_set_tiles on a batch context re-uploads the tile-dependent lists the same way.
+ * Errors as md_init (MD_EINVAL for a bad offsets/eps array).
+ */
+size_t md_batch_workspace_bytes(int model, int prec, int nb, const int64_t *offsets, const double *eps);
+int md_batch_init(md_ctx **out, int model, int prec, int nb, const int64_t *offsets, const double *eps,
+                  void *hip_stream, void *workspace, size_t workspace_bytes);
+
+/* Number of realizations of a context: nb for a batch, 1 otherwise, 0 for NULL. */
+int md_batch_size(const md_ctx *c);
+
 /* Change the stream later calls enqueue on. */
 int md_set_stream(md_ctx *c, void *hip_stream);
 

@@ -19,7 +19,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "md_internal.h"
 
@@ -121,22 +123,31 @@ void yoshida(double *b0, double *b1, double *d0, double *d1)
         if (e_ != hipSuccess) return dev_fail(c, e_, what); \
     } while (0)
 
+// Pair partials and update stage of a single system or a batched ensemble.
+hipError_t pair_(md_ctx *c, const double *q) { return c->batch ? batch_pair(c, q) : launch_pair(c, q); }
+
+hipError_t update_(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p, double *f)
+{
+    return c->batch ? batch_update(c, flags, kick1, kick2, drift, q, p, f)
+                    : launch_update(c, flags, kick1, kick2, drift, q, p, f);
+}
+
 int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps)
 {
     double B0, B1, D0, D1;
     yoshida(&B0, &B1, &D0, &D1);
     const int stage = UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1 | UPD_DRIFT | UPD_PREP;
-    MD_TRY(launch_update(c, UPD_KICK1 | UPD_DRIFT | UPD_PREP, B0 * dt, 0.0, D0 * dt, q, p, f), "step: first kick");
+    MD_TRY(update_(c, UPD_KICK1 | UPD_DRIFT | UPD_PREP, B0 * dt, 0.0, D0 * dt, q, p, f), "step: first kick");
     for (int64_t s = 0; s < nsteps; ++s) {
-        MD_TRY(launch_pair(c, q), "step: pair kernel");
-        MD_TRY(launch_update(c, stage, B1 * dt, 0.0, D1 * dt, q, p, f), "step: update");
-        MD_TRY(launch_pair(c, q), "step: pair kernel");
-        MD_TRY(launch_update(c, stage, B1 * dt, 0.0, D0 * dt, q, p, f), "step: update");
-        MD_TRY(launch_pair(c, q), "step: pair kernel");
+        MD_TRY(pair_(c, q), "step: pair kernel");
+        MD_TRY(update_(c, stage, B1 * dt, 0.0, D1 * dt, q, p, f), "step: update");
+        MD_TRY(pair_(c, q), "step: pair kernel");
+        MD_TRY(update_(c, stage, B1 * dt, 0.0, D0 * dt, q, p, f), "step: update");
+        MD_TRY(pair_(c, q), "step: pair kernel");
         if (s + 1 < nsteps)
-            MD_TRY(launch_update(c, stage | UPD_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, f), "step: update");
+            MD_TRY(update_(c, stage | UPD_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, f), "step: update");
         else
-            MD_TRY(launch_update(c, UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1, B0 * dt, 0.0, 0.0, q, p, f),
+            MD_TRY(update_(c, UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1, B0 * dt, 0.0, 0.0, q, p, f),
                    "step: last kick");
     }
     return MD_OK;
@@ -154,18 +165,172 @@ int step_hmf(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nste
            "step: first pass");
     for (int64_t s = 0; s < nsteps; ++s) {
         MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D1 * dt, q, p, nullptr, nullptr, f32), "step: pass");
-            MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32), "step: pass");
-            if (s + 1 < nsteps) {
+        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32), "step: pass");
+        if (s + 1 < nsteps)
             MD_TRY(launch_hmf_pass(c, stage | HMF_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, nullptr, nullptr, f32),
                    "step: pass");
-                } else {
+        else
             MD_TRY(launch_hmf_pass(c, HMF_KICK_M | HMF_STORE_F | HMF_WRITE, B0 * dt, 0.0, 0.0, q, p, nullptr, f,
                                    f32),
                    "step: last pass");
-        }
     }
     if (f32) MD_TRY(launch_hmf_convert(c, q, p, false), "step: convert out");
     return MD_OK;
+}
+
+// ------------------------------------------------------------ batched ensembles --
+
+constexpr int64_t kMaxBatchTotal = int64_t(1) << 24;  // particles over all realizations
+constexpr int kBatchMaxSplit = 32;
+constexpr int kERowsI = 256;    // energy items: i rows per block
+constexpr int kEChunk = 2048;   // energy items: j per block
+
+int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// j-chunk length for j_split pieces of the largest realization (a multiple of 64).
+int64_t batch_chunk(const Batch &B, int jsplit) { return div_up(div_up(B.nmax, jsplit), 64) * 64; }
+
+// Validates the ensemble description and fills the tile-independent parts of B.
+int make_batch(int model, int nb, const int64_t *off, const double *eps, Batch &B)
+{
+    if (nb < 1 || !off || !eps) return MD_EINVAL;
+    if (off[0] != 0) return MD_EINVAL;
+    B.nb = nb;
+    B.off.assign(off, off + nb + 1);
+    B.eps.assign(eps, eps + nb);
+    B.pref.resize(nb);
+    B.nmax = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int64_t n = off[b + 1] - off[b];
+        if (n < 1 || off[b + 1] > kMaxBatchTotal) return MD_EINVAL;
+        if (!(eps[b] > 0.0 && isfinite(eps[b]))) return MD_EINVAL;
+        if (n > B.nmax) B.nmax = n;
+        B.pref[b] = model == MD_GRAV2D ? -2.0 / (double)n : -1.0 / (2.0 * sqrt(2.0) * (double)n);
+    }
+    int64_t sm = B.nmax / 64;
+    B.smax = (int)(sm < 1 ? 1 : (sm > kBatchMaxSplit ? kBatchMaxSplit : sm));
+    // rows (their S_b is set by build_lists), energy items and their ranges
+    B.n_rows = 0;
+    B.roff.assign(nb + 1, 0);
+    B.eitems.clear();
+    B.eoff.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+        B.roff[b] = B.n_rows;
+        B.eoff[b] = (int)(B.eitems.size() / 8);
+        const int64_t o = off[b], n = off[b + 1] - off[b];
+        B.n_rows += (int)div_up(n, 256);
+        for (int64_t i0 = o; i0 < o + n; i0 += kERowsI) {
+            const int64_t i1 = i0 + kERowsI < o + n ? i0 + kERowsI : o + n;
+            for (int64_t j0 = o; j0 < o + n; j0 += kEChunk) {
+                const int64_t j1 = j0 + kEChunk < o + n ? j0 + kEChunk : o + n;
+                if (j1 <= i0 + 1) continue;  // no pair with j > i
+                const int it[8] = {b, (int)i0, (int)i1, 0, (int)j0, (int)j1, 0, 0};
+                B.eitems.insert(B.eitems.end(), it, it + 8);
+            }
+        }
+    }
+    B.roff[nb] = B.n_rows;
+    B.n_eitems = (int)(B.eitems.size() / 8);
+    B.eoff[nb] = B.n_eitems;
+    // largest pair-item count over all tile choices: 64-particle i blocks, smax pieces
+    const int64_t cmin = batch_chunk(B, B.smax);
+    int64_t mx = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int64_t n = off[b + 1] - off[b];
+        mx += div_up(n, 64) * div_up(n, cmin);
+    }
+    B.max_items = (int)mx;
+    return MD_OK;
+}
+
+// Pair items for the current tiles (largest first) and the rows' chunk counts.
+void build_lists(Batch &B, const Tiles &t)
+{
+    const int64_t chunk = batch_chunk(B, t.jsplit);
+    const int64_t iblock = (int64_t)kWave * t.ipl * t.waves;
+    struct Item {
+        int64_t cost;
+        int v[8];
+    };
+    std::vector<Item> items;
+    B.rows.clear();
+    for (int b = 0; b < B.nb; ++b) {
+        const int64_t o = B.off[b], n = B.off[b + 1] - B.off[b];
+        const int S = (int)div_up(n, chunk);
+        for (int64_t i0 = o; i0 < o + n; i0 += 256) {
+            const int r[4] = {b, (int)i0, (int)(i0 + 256 < o + n ? i0 + 256 : o + n), S};
+            B.rows.insert(B.rows.end(), r, r + 4);
+        }
+        for (int64_t i0 = o; i0 < o + n; i0 += iblock) {
+            const int64_t i1 = i0 + iblock < o + n ? i0 + iblock : o + n;
+            for (int s = 0; s < S; ++s) {
+                const int64_t j0 = o + s * chunk;
+                const int64_t j1 = j0 + chunk < o + n ? j0 + chunk : o + n;
+                items.push_back({(i1 - i0) * (j1 - j0), {b, (int)i0, (int)i1, s, (int)j0, (int)j1, 0, 0}});
+            }
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+    B.items.resize(items.size() * 8);
+    for (size_t k = 0; k < items.size(); ++k)
+        for (int m = 0; m < 8; ++m) B.items[k * 8 + m] = items[k].v[m];
+    B.n_items = (int)items.size();
+}
+
+struct BatchLayout {
+    size_t scal, ops, part, items, rows, eitems, eps, pref, ered, kred, eoff, roff, off, total;
+};
+
+BatchLayout batch_layout(int model, int prec, const Batch &B)
+{
+    BatchLayout L{};
+    const size_t npad = (size_t)pad_n(B.off[B.nb]);
+    const int d = dims(model);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.scal = take(sizeof(double) * 32);
+    size_t ops = 0;
+    if (model == MD_RING) ops = 2 * npad * (prec == MD_FP64 ? sizeof(double) : sizeof(float));
+    else if (prec != MD_FP64) ops = 2 * npad * sizeof(float);
+    L.ops = take(ops);
+    L.part = take((size_t)B.smax * d * npad * sizeof(double));
+    L.items = take((size_t)B.max_items * 8 * sizeof(int));
+    L.rows = take((size_t)B.n_rows * 4 * sizeof(int));
+    L.eitems = take((size_t)B.n_eitems * 8 * sizeof(int));
+    L.eps = take(B.nb * sizeof(double));
+    L.pref = take(B.nb * sizeof(double));
+    L.ered = take((size_t)B.n_eitems * sizeof(double));
+    L.kred = take((size_t)B.n_rows * sizeof(double));
+    L.eoff = take((B.nb + 1) * sizeof(int));
+    L.roff = take((B.nb + 1) * sizeof(int));
+    L.off = take((B.nb + 1) * sizeof(int64_t));
+    L.total = o;
+    return L;
+}
+
+Tiles batch_default_tiles(const Batch &B)
+{
+    Tiles t;
+    t.ipl = 1;
+    t.waves = 4;
+    t.jsplit = B.smax < 8 ? B.smax : 8;
+    t.jtile = 128;
+    return t;
+}
+
+// Uploads the tile-dependent lists (pair items, rows).
+hipError_t upload_lists(md_ctx *c)
+{
+    Batch &B = *c->batch;
+    hipError_t e = hipMemcpyAsync(B.d_items, B.items.data(), B.items.size() * sizeof(int), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B.d_rows, B.rows.data(), B.rows.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    return e;
 }
 
 }  // namespace
@@ -259,6 +424,83 @@ int md_init(md_ctx **out, int model, int prec, int64_t n, double eps, void *hip_
     return MD_OK;
 }
 
+size_t md_batch_workspace_bytes(int model, int prec, int nb, const int64_t *offsets, const double *eps)
+{
+    if (!(model == MD_RING || model == MD_GRAV2D) || !prec_ok(model, prec)) return 0;
+    Batch B;
+    if (make_batch(model, nb, offsets, eps, B) != MD_OK) return 0;
+    return batch_layout(model, prec, B).total;
+}
+
+int md_batch_init(md_ctx **out, int model, int prec, int nb, const int64_t *offsets, const double *eps,
+                  void *hip_stream, void *workspace, size_t workspace_bytes)
+{
+    if (!out) return MD_EINVAL;
+    *out = nullptr;
+    if (!model_ok(model)) return MD_EINVAL;
+    if (model == MD_HMF || !prec_ok(model, prec)) return MD_EUNSUPPORTED;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return MD_EINVAL;
+    Batch *B = new (std::nothrow) Batch();
+    if (!B) return MD_ENOMEM;
+    int st = make_batch(model, nb, offsets, eps, *B);
+    if (st != MD_OK) {
+        delete B;
+        return st;
+    }
+    const BatchLayout L = batch_layout(model, prec, *B);
+    if (workspace_bytes < L.total) {
+        delete B;
+        return MD_ENOMEM;
+    }
+    md_ctx *c = new (std::nothrow) md_ctx();
+    if (!c) {
+        delete B;
+        return MD_ENOMEM;
+    }
+    c->batch = B;
+    c->model = model;
+    c->prec = prec;
+    c->n = B->off[nb];
+    c->npad = pad_n(c->n);
+    c->eps = B->eps[0];
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ws = static_cast<char *>(workspace);
+    c->ws_bytes = workspace_bytes;
+    c->scal = reinterpret_cast<double *>(c->ws + L.scal);
+    c->ops = L.part > L.ops ? static_cast<void *>(c->ws + L.ops) : nullptr;
+    c->part = reinterpret_cast<double *>(c->ws + L.part);
+    B->d_items = c->ws + L.items;
+    B->d_rows = c->ws + L.rows;
+    B->d_eitems = c->ws + L.eitems;
+    B->d_eps = reinterpret_cast<double *>(c->ws + L.eps);
+    B->d_pref = reinterpret_cast<double *>(c->ws + L.pref);
+    B->d_ered = reinterpret_cast<double *>(c->ws + L.ered);
+    B->d_kred = reinterpret_cast<double *>(c->ws + L.kred);
+    B->d_eoff = reinterpret_cast<int *>(c->ws + L.eoff);
+    B->d_roff = reinterpret_cast<int *>(c->ws + L.roff);
+    B->d_off = reinterpret_cast<int64_t *>(c->ws + L.off);
+    c->tiles = batch_default_tiles(*B);
+    build_lists(*B, c->tiles);
+    hipError_t e = hipGetDevice(&c->dev);
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    if (e == hipSuccess) e = upload_lists(c);
+    if (e == hipSuccess && B->n_eitems > 0)
+        e = hipMemcpyAsync(B->d_eitems, B->eitems.data(), B->eitems.size() * sizeof(int), h2d, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->d_eps, B->eps.data(), nb * sizeof(double), h2d, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->d_pref, B->pref.data(), nb * sizeof(double), h2d, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->d_eoff, B->eoff.data(), (nb + 1) * sizeof(int), h2d, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->d_roff, B->roff.data(), (nb + 1) * sizeof(int), h2d, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->d_off, B->off.data(), (nb + 1) * sizeof(int64_t), h2d, c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return MD_EDEVICE;
+    }
+    *out = c;
+    return MD_OK;
+}
+
+int md_batch_size(const md_ctx *c) { return c ? (c->batch ? c->batch->nb : 1) : 0; }
+
 int md_set_stream(md_ctx *c, void *hip_stream)
 {
     if (!c) return MD_EINVAL;
@@ -270,7 +512,8 @@ int md_set_tiles(md_ctx *c, int i_per_lane, int waves, int j_split, int j_tile)
 {
     if (!c) return MD_EINVAL;
     c->err.clear();
-    const Tiles d = default_tiles(c->model, c->prec, c->n);
+    const Tiles d = c->batch ? batch_default_tiles(*c->batch) : default_tiles(c->model, c->prec, c->n);
+    const int smax = c->batch ? c->batch->smax : max_j_split(c->n);
     Tiles t;
     t.ipl = i_per_lane ? i_per_lane : d.ipl;
     t.waves = waves ? waves : d.waves;
@@ -280,11 +523,17 @@ int md_set_tiles(md_ctx *c, int i_per_lane, int waves, int j_split, int j_tile)
         return fail(c, MD_EUNSUPPORTED, "i_per_lane must be 1, 2 or 4 (got %d)", t.ipl);
     if (t.waves != 1 && t.waves != 2 && t.waves != 4)
         return fail(c, MD_EUNSUPPORTED, "waves must be 1, 2 or 4 (got %d)", t.waves);
-    if (t.jsplit < 1 || t.jsplit > max_j_split(c->n))
-        return fail(c, MD_EINVAL, "j_split must be in [1, %d] (got %d)", max_j_split(c->n), t.jsplit);
+    if (t.jsplit < 1 || t.jsplit > smax)
+        return fail(c, MD_EINVAL, "j_split must be in [1, %d] (got %d)", smax, t.jsplit);
     if (t.jtile < 16 || t.jtile > 4096 || t.jtile % 16)
         return fail(c, MD_EINVAL, "j_tile must be a multiple of 16 in [16, 4096] (got %d)", t.jtile);
     c->tiles = t;
+    if (c->batch) {
+        build_lists(*c->batch, t);
+        DeviceGuard g(c->dev);
+        if (g.err != hipSuccess) return dev_fail(c, g.err, "md_set_tiles: set device");
+        MD_TRY(upload_lists(c), "md_set_tiles: upload work lists");
+    }
     return MD_OK;
 }
 
@@ -311,9 +560,9 @@ int md_force(md_ctx *c, const double *q, double *f)
         MD_TRY(launch_hmf_pass(c, HMF_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, nullptr, f, false), "force: store");
         return MD_OK;
     }
-    MD_TRY(launch_prep(c, q), "force: operands");
-    MD_TRY(launch_pair(c, q), "force: pair kernel");
-    MD_TRY(launch_update(c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, f), "force: combine");
+    MD_TRY(update_(c, UPD_PREP, 0.0, 0.0, 0.0, qm, nullptr, nullptr), "force: operands");
+    MD_TRY(pair_(c, q), "force: pair kernel");
+    MD_TRY(update_(c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, f), "force: combine");
     return MD_OK;
 }
 
@@ -339,7 +588,7 @@ int md_energy(md_ctx *c, const double *q, const double *p, double *out_dev3)
         return fail(c, MD_EINVAL, "md_energy: null or misaligned pointer");
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_energy: set device");
-    MD_TRY(launch_energy(c, q, p, out_dev3), "energy");
+    MD_TRY(c->batch ? batch_energy(c, q, p, out_dev3) : launch_energy(c, q, p, out_dev3), "energy");
     return MD_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "md.h"
 
@@ -46,6 +47,27 @@ struct Tiles {
     int jtile = 0;   // j per FP32 partial
 };
 
+
+// Host-side description of a batched ensemble (md_batch_init).  The work lists
+// are built on the host, kept here (they are the source of asynchronous uploads)
+// and copied into the workspace.
+struct Batch {
+    int nb = 0;
+    int64_t nmax = 0;
+    int smax = 1;                   // largest j_split accepted (pieces of the largest realization)
+    std::vector<int64_t> off;       // nb + 1 CSR offsets
+    std::vector<double> eps, pref;  // per realization
+    std::vector<int> items;         // pair items, 8 ints each: b, i0, i1, slot, j0, j1, 0, 0
+    std::vector<int> rows;          // row items, 4 ints each: b, i0, i1, S_b
+    std::vector<int> eitems;        // energy items, 8 ints each
+    std::vector<int> eoff, roff;    // per-realization ranges of energy / row items
+    int n_items = 0, n_rows = 0, n_eitems = 0, max_items = 0;
+    void *d_items = nullptr, *d_rows = nullptr, *d_eitems = nullptr;
+    double *d_eps = nullptr, *d_pref = nullptr, *d_ered = nullptr, *d_kred = nullptr;
+    int *d_eoff = nullptr, *d_roff = nullptr;
+    int64_t *d_off = nullptr;
+};
+
 }  // namespace md
 
 struct md_ctx {
@@ -63,7 +85,9 @@ struct md_ctx {
     float *th32 = nullptr;    // HMF FP32 state
     float *p32 = nullptr;
     md::Tiles tiles;
+    md::Batch *batch = nullptr;  // non-null for a batched ensemble (owned)
     std::string err;
+    ~md_ctx() { delete batch; }
 };
 
 namespace md {
@@ -87,6 +111,11 @@ hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, dou
 hipError_t launch_hmf_magnetization(md_ctx *c, double *out2);
 const double *hmf_partials(const md_ctx *c);  // block partials of the latest reducing pass
 hipError_t launch_hmf_convert(md_ctx *c, double *th, double *p, bool to_f32);
+// batch.hip
+hipError_t batch_pair(md_ctx *c, const double *q);
+hipError_t batch_update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
+                        double *f);
+hipError_t batch_energy(md_ctx *c, const double *q, const double *p, double *out);
 // energy.hip
 hipError_t launch_energy(md_ctx *c, const double *q, const double *p, double *out3);
 hipError_t launch_magnetization(md_ctx *c, const double *q, double *out2);

@@ -20,85 +20,12 @@
 // Kahan-compensated FP32 per pair; FP64 add per pair; plain FP64.
 #include "device.h"
 #include "md_internal.h"
+#include "pair_terms.h"
 
 namespace md {
 namespace {
 
-// ---------------------------------------------------------------- accumulators --
-
-// FP32 partial over a j tile, folded into an FP64 total once per tile.
-struct AccTile {
-    float s = 0.f;
-    double t = 0.0;
-    __device__ __forceinline__ void add(float a, float b) { s = __builtin_fmaf(a, b, s); }
-    __device__ __forceinline__ void fold() { t += (double)s; s = 0.f; }
-    __device__ __forceinline__ double get() const { return t; }
-};
-
-// Kahan-compensated FP32 sum of every pair term; -c holds the lost low part.
-struct AccKahan {
-    float s = 0.f, c = 0.f;
-    __device__ __forceinline__ void add(float a, float b)
-    {
-        const float y = a * b - c;
-        const float u = s + y;
-        c = (u - s) - y;
-        s = u;
-    }
-    __device__ __forceinline__ void fold() {}
-    __device__ __forceinline__ double get() const { return (double)s - (double)c; }
-};
-
-// Each FP32 pair term added into an FP64 accumulator.
-struct AccPair64 {
-    double t = 0.0;
-    __device__ __forceinline__ void add(float a, float b) { t += (double)(a * b); }
-    __device__ __forceinline__ void fold() {}
-    __device__ __forceinline__ double get() const { return t; }
-};
-
-// Plain FP64.
-struct AccF64 {
-    double t = 0.0;
-    __device__ __forceinline__ void add(double a, double b) { t = __builtin_fma(a, b, t); }
-    __device__ __forceinline__ void fold() {}
-    __device__ __forceinline__ double get() const { return t; }
-};
-
-__device__ __forceinline__ float rcp_(float x) { return rcp32(x); }
-__device__ __forceinline__ double rcp_(double x) { return rcp64(x); }
-__device__ __forceinline__ float rsq_(float x) { return rsq32(x); }
-__device__ __forceinline__ double rsq_(double x) { return rsq64(x); }
-__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// ------------------------------------------------------------------ pair terms --
-
-// 2D: adds (r_i - r_j) / (|r_i - r_j|^2 + eps) to (ax, ay).
-template <typename T, typename A>
-__device__ __forceinline__ void pair_2d(T xi, T yi, T xj, T yj, T eps, A &ax, A &ay)
-{
-    const T dx = xi - xj;
-    const T dy = yi - yj;
-    const T w = rcp_(fma_(dx, dx, fma_(dy, dy, eps)));
-    ax.add(dx, w);
-    ay.add(dy, w);
-}
-
-// Ring (eq. 9): adds sin(ti - tj) / (1 - cos(ti - tj) + eps)^{3/2} to a, from the
-// cosines and sines of both angles.  one_eps = 1 + eps.
-template <typename T, typename A>
-__device__ __forceinline__ void pair_ring(T ci, T si, T cj, T sj, T one_eps, A &a)
-{
-    T num;
-    {
-#pragma clang fp contract(off)
-        num = si * cj - ci * sj;
-    }
-    const T u = fma_(-ci, cj, fma_(-si, sj, one_eps));
-    const T r = rsq_(u);
-    a.add(num, r * r * r);
-}
+using namespace pairs;
 
 // ---------------------------------------------------------------- pair kernels --
 
@@ -255,7 +182,7 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ part,
                 static_cast<float *>(ops)[(size_t)d * npad + i] = (float)qd;
             } else if (PREP == PREP_SINCOS32 || PREP == PREP_SINCOS64) {
                 double sn, cn;
-                sincos(qd, &sn, &cn);
+                sincos64(qd, &sn, &cn);
                 if (PREP == PREP_SINCOS32) {
                     static_cast<float *>(ops)[i] = (float)cn;
                     static_cast<float *>(ops)[npad + i] = (float)sn;

@@ -36,6 +36,9 @@ _V, _I, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_
 SIGNATURES = {
     "md_workspace_bytes": (_SZ, [_I, _I, _I64]),
     "md_init": (_I, [ctypes.POINTER(_V), _I, _I, _I64, _D, _V, _V, _SZ]),
+    "md_batch_workspace_bytes": (_SZ, [_I, _I, _I, _V, _V]),
+    "md_batch_init": (_I, [ctypes.POINTER(_V), _I, _I, _I, _V, _V, _V, _V, _SZ]),
+    "md_batch_size": (_I, [_V]),
     "md_set_stream": (_I, [_V, _V]),
     "md_set_tiles": (_I, [_V, _I, _I, _I, _I]),
     "md_get_tiles": (_I, [_V, ctypes.POINTER(_I)]),
@@ -156,6 +159,45 @@ def md_init(model: int, prec: int, n: int, eps: float = 0.0, stream=None,
     return Context(h.value, int(model), int(prec), int(n), float(eps), workspace)
 
 
+def _batch_arrays(offsets, eps):
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    nb = off.size - 1
+    e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (max(nb, 0),)))
+    return off, e, nb
+
+
+def md_batch_workspace_bytes(model: int, prec: int, offsets, eps) -> int:
+    off, e, nb = _batch_arrays(offsets, eps)
+    return int(load().md_batch_workspace_bytes(int(model), int(prec), nb, off.ctypes.data, e.ctypes.data))
+
+
+def md_batch_init(model: int, prec: int, offsets, eps, stream=None,
+                  workspace: Optional[torch.Tensor] = None) -> Context:
+    """Context for an ensemble of realizations: offsets[nb + 1] (CSR, host), eps per
+    realization (scalar or [nb]).  Arrays are the realizations concatenated."""
+    off, e, nb = _batch_arrays(offsets, eps)
+    need = md_batch_workspace_bytes(model, prec, off, e)
+    if workspace is None:
+        if need == 0:
+            raise MDError(EINVAL, "md_batch_init", "invalid model/prec/offsets/eps")
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    st = load().md_batch_init(ctypes.byref(h), int(model), int(prec), nb, off.ctypes.data, e.ctypes.data,
+                              _stream_handle(stream), workspace.data_ptr(),
+                              workspace.numel() * workspace.element_size())
+    if st != OK:
+        raise MDError(st, "md_batch_init")
+    ctx = Context(h.value, int(model), int(prec), int(off[-1]), float(e[0]), workspace)
+    ctx.nb = nb
+    ctx.offsets = off.copy()
+    return ctx
+
+
+def md_batch_size(ctx: Context) -> int:
+    return int(load().md_batch_size(ctx.handle))
+
+
 def md_set_stream(ctx: Context, stream=None) -> None:
     ctx._check(load().md_set_stream(ctx.handle, _stream_handle(stream)), "md_set_stream")
 
@@ -182,11 +224,13 @@ def md_step(ctx: Context, q: torch.Tensor, p: torch.Tensor, f: torch.Tensor, dt:
 
 
 def md_energy(ctx: Context, q: torch.Tensor, p: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """{K, V, E} as a device float64 tensor of 3 (read it on the host to synchronise)."""
+    """{K, V, E} as a device float64 tensor of 3 ([nb, 3] for a batch context);
+    read it on the host to synchronise."""
+    nb = getattr(ctx, "nb", 1)
     if out is None:
-        out = torch.empty(3, dtype=torch.float64, device=q.device)
-    if out.dtype != torch.float64 or out.numel() < 3 or out.device.type != "cuda":
-        raise ValueError("out: expected a device float64 tensor of at least 3 elements")
+        out = torch.empty((nb, 3) if nb > 1 or hasattr(ctx, "nb") else 3, dtype=torch.float64, device=q.device)
+    if out.dtype != torch.float64 or out.numel() < 3 * nb or out.device.type != "cuda" or not out.is_contiguous():
+        raise ValueError(f"out: expected a contiguous device float64 tensor of at least {3 * nb} elements")
     ctx._check(load().md_energy(ctx.handle, ctx._arr(q, "q"), ctx._arr(p, "p"), out.data_ptr()), "md_energy")
     return out
 

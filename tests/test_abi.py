@@ -128,3 +128,30 @@ def test_product_path_has_no_oracle_dependency():
     so = md.LIB_PATH
     if os.path.exists(so):
         assert b"or_force" not in open(so, "rb").read()
+
+
+def test_batch_validation_on_host():
+    """Batched ensembles: bad CSR offsets or eps are rejected before any device work."""
+    import numpy as np
+    lib = _lib()
+    h = ctypes.c_void_p()
+    e2 = np.array([0.01, 0.01])
+
+    def init(model, prec, off, eps, nb=None):
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        nb = off.size - 1 if nb is None else nb
+        return lib.md_batch_init(ctypes.byref(h), model, prec, nb, off.ctypes.data, eps.ctypes.data, None, 256,
+                                 1 << 40)
+    assert init(md.RING, md.FP64, [0, 10, 5], e2) == md.EINVAL        # decreasing offsets
+    assert init(md.RING, md.FP64, [0, 10, 10], e2) == md.EINVAL       # empty realization
+    assert init(md.RING, md.FP64, [3, 10, 20], e2) == md.EINVAL       # offsets[0] != 0
+    assert init(md.RING, md.FP64, [0, 10, 20], [0.01, 0.0]) == md.EINVAL
+    assert init(md.GRAV2D, md.MIXED, [0, 10, 20], [0.01, float("inf")]) == md.EINVAL
+    assert init(md.RING, md.FP64, [0, 10], [0.01], nb=0) == md.EINVAL
+    assert init(md.HMF, md.FP64, [0, 10, 20], e2) == md.EUNSUPPORTED
+    assert init(md.RING, md.MIXED_F32STATE, [0, 10, 20], e2) == md.EUNSUPPORTED
+    assert init(md.RING, md.FP64, [0, 1 << 23, (1 << 24) + 1], e2) == md.EINVAL  # too many particles in total
+    assert md.md_batch_workspace_bytes(md.RING, md.FP64, [0, 10, 20], 0.01) > 0
+    assert md.md_batch_workspace_bytes(md.RING, md.FP64, [0, 10, 5], 0.01) == 0
+    assert lib.md_batch_size(None) == 0

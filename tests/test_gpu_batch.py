@@ -1,0 +1,181 @@
+"""GPU parity of batched ensembles (md_batch_init): every realization of the
+ensemble against the FP64 oracle run on that realization alone, and against the
+single-system path of the library.
+
+Tolerances are those of the single-system tests (test_gpu_parity.py), since each
+realization is the same computation: FP64 forces 5e-12, mixed 2D 2e-5, mixed
+Ring 2e-4 (relative to max |f| of the realization); energies 1e-12 of K + |V|.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_0262_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+md = pytest.importorskip("paper_1212_0262_amd.md")
+from gpu_helpers import dev, host, rel_inf  # noqa: E402
+
+RING, GRAV2D = md.RING, md.GRAV2D
+FORCE_TOL = {md.FP64: 5e-12, md.MIXED: {GRAV2D: 2e-5, RING: 2e-4}, md.MIXED_KAHAN: {GRAV2D: 2e-5, RING: 2e-4},
+             md.MIXED_PAIRF64: {GRAV2D: 2e-5, RING: 2e-4}}
+SIZES = [1, 2, 63, 65, 257, 1000, 3001]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_threads():
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def tol(prec, model):
+    t = FORCE_TOL[prec]
+    return t if isinstance(t, float) else t[model]
+
+
+def ensemble(model, sizes, seed):
+    qs, ps = [], []
+    for b, n in enumerate(sizes):
+        if model == GRAV2D:
+            q, p = inputs.grav2d_disk(int(n), seed=seed + b)
+        else:
+            q, p = inputs.ensemble_member(b, int(n), seed=seed)
+        qs.append(q)
+        ps.append(p)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return np.concatenate(qs, axis=1), np.concatenate(ps, axis=1), off
+
+
+def split(a, off):
+    return [a[:, off[b]:off[b + 1]] for b in range(len(off) - 1)]
+
+
+@pytest.mark.parametrize("prec", [md.FP64, md.MIXED, md.MIXED_KAHAN, md.MIXED_PAIRF64])
+@pytest.mark.parametrize("model,eps", [(RING, 0.01), (GRAV2D, 1e-3)])
+def test_batch_force_matches_oracle_per_realization(model, eps, prec):
+    q, _, off = ensemble(model, SIZES, seed=40)
+    eps_b = np.full(len(SIZES), eps)
+    eps_b[-1] = 3 * eps  # realizations may differ in eps
+    ctx = md.md_batch_init(model, prec, off, eps_b)
+    assert md.md_batch_size(ctx) == len(SIZES)
+    qd = dev(q)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    fg = split(host(f), off)
+    for b, qb in enumerate(split(q, off)):
+        fo = oracle.force(model, qb, eps_b[b])
+        if SIZES[b] == 1:
+            assert np.all(fg[b] == 0.0)
+            continue
+        assert rel_inf(fg[b], fo) < tol(prec, model), (b, SIZES[b])
+
+
+@pytest.mark.parametrize("model,eps", [(RING, 0.01), (GRAV2D, 1e-3)])
+def test_batch_equals_single_system_bitwise(model, eps):
+    """With one j chunk per realization and the same lanes, a batched realization
+    is the single-system sum in the same order: bit-identical forces."""
+    q, _, off = ensemble(model, [300, 1000, 777], seed=41)
+    ctx = md.md_batch_init(model, md.MIXED, off, eps)
+    md.md_set_tiles(ctx, 1, 4, 1, 128)
+    qd = dev(q)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    fg = split(host(f), off)
+    for b, qb in enumerate(split(q, off)):
+        s = md.md_init(model, md.MIXED, qb.shape[1], eps)
+        md.md_set_tiles(s, 1, 4, 1, 128)
+        qs = dev(qb)
+        fs = torch.empty_like(qs)
+        md.md_force(s, qs, fs)
+        np.testing.assert_array_equal(fg[b], host(fs))
+
+
+@pytest.mark.parametrize("tiles", [(1, 1, 1, 16), (2, 2, 3, 64), (4, 4, 5, 128), (1, 4, 7, 4096)])
+def test_batch_tile_independent(tiles):
+    q, _, off = ensemble(RING, SIZES, seed=42)
+    ctx = md.md_batch_init(RING, md.FP64, off, 0.01)
+    qd = dev(q)
+    f0 = torch.empty_like(qd)
+    md.md_force(ctx, qd, f0)
+    md.md_set_tiles(ctx, *tiles)
+    f1 = torch.empty_like(qd)
+    md.md_force(ctx, qd, f1)
+    for a, b in zip(split(host(f1), off), split(host(f0), off)):
+        if a.size > 1:
+            assert rel_inf(a, b) < 1e-13
+
+
+@pytest.mark.parametrize("model,eps", [(RING, 0.01), (GRAV2D, 1e-3)])
+def test_batch_energies_match_oracle(model, eps):
+    q, p, off = ensemble(model, SIZES, seed=43)
+    ctx = md.md_batch_init(model, md.FP64, off, eps)
+    e = host(md.md_energy(ctx, dev(q), dev(p)))
+    assert e.shape == (len(SIZES), 3)
+    for b, (qb, pb) in enumerate(zip(split(q, off), split(p, off))):
+        eo = oracle.energy(model, qb, pb, eps)
+        assert np.abs(e[b] - eo).max() <= 1e-12 * (abs(eo[0]) + abs(eo[1])), b
+
+
+def test_batch_trajectory_smallest_and_largest():
+    """Ring ensemble with sizes drawn log-uniform in [1000, 16384] (seed 4),
+    FP32 pairs with Kahan-compensated accumulation, dt = 0.05: the 3 smallest and
+    3 largest realizations against the FP64 oracle after 6 steps."""
+    sizes = inputs.ensemble_sizes(24, seed=4)
+    q, p, off = ensemble(RING, sizes, seed=4)
+    ctx = md.md_batch_init(RING, md.MIXED_KAHAN, off, 0.01)
+    qd, pd = dev(q), dev(p)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    md.md_step(ctx, qd, pd, f, 0.05, 6)
+    eg = host(md.md_energy(ctx, qd, pd))
+    qg, pg = split(host(qd), off), split(host(pd), off)
+    order = np.argsort(sizes)
+    for b in list(order[:3]) + list(order[-3:]):
+        qb, pb = q[:, off[b]:off[b + 1]], p[:, off[b]:off[b + 1]]
+        fo = oracle.force(RING, qb, 0.01)
+        e0 = oracle.energy(RING, qb, pb, 0.01)
+        qo, po, _ = oracle.step(RING, qb, pb, fo, 0.05, 6, 0.01)
+        eo = oracle.energy(RING, qo, po, 0.01)
+        assert abs(eg[b, 2] - eo[2]) < 1e-5 * (abs(e0[0]) + abs(e0[1])), b
+        assert np.abs(qg[b] - qo).max() < 1e-4 and np.abs(pg[b] - po).max() < 1e-4, b
+
+
+def test_batch_graph_replay_matches_eager():
+    """The whole multi-step update captured as one HIP graph: every replay (with
+    eager work and synchronisation in between) equals the eager run, bit for bit."""
+    sizes = inputs.ensemble_sizes(12, seed=4, nmin=100, nmax=2000)
+    q, p, off = ensemble(RING, sizes, seed=4)
+    ctx = md.md_batch_init(RING, md.MIXED_KAHAN, off, 0.01)
+    qd, pd = dev(q), dev(p)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    torch.cuda.synchronize()
+    # eager reference: 3 successive 4-step calls
+    qe, pe, fe = qd.clone(), pd.clone(), f.clone()
+    ref = []
+    for _ in range(3):
+        md.md_step(ctx, qe, pe, fe, 0.05, 4)
+        ref.append((host(qe), host(pe)))
+    # graph: capture one 4-step call on static buffers
+    qg, pg, fg = qd.clone(), pd.clone(), f.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        md.md_set_stream(ctx, s)
+        with torch.cuda.graph(g, stream=s):
+            md.md_step(ctx, qg, pg, fg, 0.05, 4)
+    md.md_set_stream(ctx, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    # capture does not execute: the buffers still hold the initial state
+    np.testing.assert_array_equal(host(qg), q)
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (qd * 2.0).sum().item()  # eager work between replays
+        np.testing.assert_array_equal(host(qg), ref[r][0])
+        np.testing.assert_array_equal(host(pg), ref[r][1])
