@@ -314,6 +314,29 @@ def ensemble_workload(md, torch, args):
         same = bool(torch.equal(q, qe) and torch.equal(p, pe))
     dE = np.abs(e1[:, 2] - e0[:, 2]) / np.abs(e0[:, 2])
     pairs = 3.0 * pairs_per_eval * args.steps
+    # the same run in FP64 and in plain mixed (eager): the integrator's own energy
+    # error, and what each FP32 form adds to it, per realization
+    ref = {}
+    for name, pr in (("fp64", md.FP64), ("mixed", md.MIXED)):
+        c2 = md.md_batch_init(md.RING, pr, off, ENS_EPS, stream=stream)
+        with torch.cuda.stream(stream):
+            q2 = torch.from_numpy(q0).cuda()
+            p2 = torch.from_numpy(p0).cuda()
+            f2 = torch.empty_like(q2)
+            md.md_force(c2, q2, f2)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            md.md_step(c2, q2, p2, f2, ENS_DT, args.steps)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ref[name] = {"ms": ev0.elapsed_time(ev1), "E1": md.md_energy(c2, q2, p2).cpu().numpy(),
+                         "tiles": list(md.md_get_tiles(c2))}
+        c2.close()
+        del q2, p2, f2
+    e64 = ref["fp64"]["E1"]
+    prec_err = np.abs(e1[:, 2] - e64[:, 2]) / np.abs(e0[:, 2])
+    prec_err_mixed = np.abs(ref["mixed"]["E1"][:, 2] - e64[:, 2]) / np.abs(e0[:, 2])
+    dE64 = np.abs(e64[:, 2] - e0[:, 2]) / np.abs(e0[:, 2])
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -342,7 +365,14 @@ def ensemble_workload(md, torch, args):
         "ensemble": {"graph_ms": graph_ms, "eager_ms": eager_ms, "graph_equals_eager": same,
                      "force_ms_default_tiles": t_default, "force_ms_tuned": table[0][1],
                      "tune_table_top5": [[list(t), ms] for t, ms in table[:5]],
-                     "dE_E_max": float(dE.max()), "dE_E_median": float(np.median(dE))},
+                     "dE_E_max": float(dE.max()), "dE_E_median": float(np.median(dE)),
+                     "fp64_dE_E_max": float(dE64.max()), "fp64_dE_E_median": float(np.median(dE64)),
+                     "kahan_vs_fp64_energy_diff_over_absE0_max": float(prec_err.max()),
+                     "gate_kahan_vs_fp64_le_1e-5": bool(prec_err.max() <= 1e-5),
+                     "mixed_vs_fp64_energy_diff_over_absE0_max": float(prec_err_mixed.max()),
+                     "fp64_gpairs_per_s": pairs / (ref["fp64"]["ms"] * 1e-3) / 1e9,
+                     "mixed_gpairs_per_s": pairs / (ref["mixed"]["ms"] * 1e-3) / 1e9,
+                     "fp64_tiles": ref["fp64"]["tiles"], "mixed_tiles": ref["mixed"]["tiles"]},
     }
 
 

@@ -59,6 +59,8 @@ def _load():
             "or_potential": (_D, [_I, _L, _D, _P]),
             "or_hmf_potential_pairs": (_D, [_L, _P]),
             "or_energy": (_I, [_I, _L, _D, _P, _P, _P]),
+            "or_hvp": (_I, [_I, _L, _D, _P, _P, _P]),
+            "or_step_vjp": (_I, [_I, _L, _D, _P, _P, _D, _L, _P, _P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -168,3 +170,25 @@ def energy(model: int, q, p, eps: float = 0.0) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle energy: bad arguments")
     return out
+
+
+def hvp(model: int, q, w, eps: float = 0.0) -> np.ndarray:
+    """H(q) w, H the Hessian of the potential (eqs. 1-3); shape [d, n]."""
+    q, w = _f64(q), _f64(w)
+    out = np.zeros_like(q)
+    rc = _load().or_hvp(model, q.shape[-1], float(eps), _ptr(q), _ptr(w), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle hvp: bad arguments")
+    return out
+
+
+def step_vjp(model: int, q0, p0, dt: float, nsteps: int, lam_q, lam_p, eps: float = 0.0):
+    """Adjoints at the start of nsteps Yoshida steps from (q0, p0), given the
+    adjoints (lam_q, lam_p) at their end; returns (dJ/dq0, dJ/dp0)."""
+    q0, p0 = _f64(q0), _f64(p0)
+    lq, lp = _f64(lam_q).copy(), _f64(lam_p).copy()
+    rc = _load().or_step_vjp(model, q0.shape[-1], float(eps), _ptr(q0), _ptr(p0), float(dt), int(nsteps),
+                             _ptr(lq), _ptr(lp))
+    if rc != 0:
+        raise ValueError("oracle step_vjp: bad arguments")
+    return lq, lp

@@ -20,6 +20,10 @@
  *                first of the next.
  *   energies     K = 1/2 sum p^2; V exactly per the Hamiltonians over i<j; HMF also
  *                through eq. 5.  Large sums are Neumaier-compensated.
+ *   adjoint      Hessian-vector products of V and the reverse-mode derivative of
+ *                the integrator (recompute the forward steps, undo kicks and drifts
+ *                in reverse order); not part of the paper, which integrates forward
+ *                only -- derivatives of the same discrete map.
  *
  * Readings of the paper taken here (each is pinned by the tests):
  *   - Ring force sign: eqs. 8 and 9 print +dV/dtheta_i; the force used is
@@ -341,5 +345,112 @@ int or_energy(int model, long n, double eps, const double *q, const double *p, d
     out[0] = or_kinetic(model, n, p);
     out[1] = or_potential(model, n, eps, q);
     out[2] = out[0] + out[1];
+    return 0;
+}
+
+/* ------------------------------------------------------------------ adjoint -- */
+/*
+ * Hessian-vector product out = H(q) w, H = second derivatives of the potential V
+ * of eqs. 1-3 (the force is -grad V, so the Jacobian of the force is -H).  For a
+ * pair potential V = sum_{i<j} phi(q_i - q_j) the product is
+ *     (H w)_i = sum_{j != i} phi''(q_i - q_j) (w_i - w_j),
+ * with phi'' the 1x1 (angles) or 2x2 (2D) second derivative of the pair term:
+ *   Ring  phi(d) = -(1/(sqrt2 N)) u^{-1/2}, u = 1 - cos d + eps:
+ *         phi''(d) = (1/(2 sqrt2 N)) [cos d u^{-3/2} - (3/2) sin^2 d u^{-5/2}]
+ *   HMF   phi(d) = (1/N)(1 - cos d):  phi''(d) = (1/N) cos d
+ *   2D    phi(r) = (1/N) log(|r|^2 + eps), s = |r|^2 + eps:
+ *         phi''(r) = (2/N) [I/s - 2 r r^T / s^2]
+ */
+int or_hvp(int model, long n, double eps, const double *q, const double *w, double *out)
+{
+    if (!or_model_ok(model) || n < 0) return -1;
+    long i;
+    if (model == OR_GRAV2D) {
+        const double *x = q, *y = q + n, *wx = w, *wy = w + n;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (i = 0; i < n; ++i) {
+            double ax = 0.0, ay = 0.0;
+            for (long j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double dx = x[i] - x[j], dy = y[i] - y[j];
+                double s = dx * dx + dy * dy + eps;
+                double ux = wx[i] - wx[j], uy = wy[i] - wy[j];
+                double rdotu = dx * ux + dy * uy;
+                ax += ux / s - 2.0 * dx * rdotu / (s * s);
+                ay += uy / s - 2.0 * dy * rdotu / (s * s);
+            }
+            out[i] = 2.0 * ax / (double)n;
+            out[n + i] = 2.0 * ay / (double)n;
+        }
+    } else {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (i = 0; i < n; ++i) {
+            double a = 0.0;
+            for (long j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double d = q[i] - q[j];
+                double h;
+                if (model == OR_RING) {
+                    double u = 1.0 - cos(d) + eps;
+                    h = (cos(d) / (u * sqrt(u)) - 1.5 * sin(d) * sin(d) / (u * u * sqrt(u))) /
+                        (2.0 * sqrt(2.0) * (double)n);
+                } else {
+                    h = cos(d) / (double)n;
+                }
+                a += h * (w[i] - w[j]);
+            }
+            out[i] = a;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Reverse-mode derivative (vector-Jacobian product) of nsteps Yoshida steps
+ * (eq. 4) started from (q0, p0): on entry (lq, lp) are the adjoints dJ/dq, dJ/dp
+ * of some J at the final state; on exit they are dJ/dq0, dJ/dp0.  The forward
+ * steps are recomputed and every position at which a kick evaluates the force is
+ * kept; the kicks and drifts are then undone in reverse order:
+ *     drift q += a p:        lp += a lq
+ *     kick  p += h F(q):     lq -= h H(q) lp        (F = -grad V)
+ */
+int or_step_vjp(int model, long n, double eps, const double *q0, const double *p0, double dt, long nsteps,
+                double *lq, double *lp)
+{
+    if (!or_model_ok(model) || n < 0 || nsteps < 0) return -1;
+    double c[4];
+    or_yoshida(c);
+    const double kick_w[4] = {c[0], c[1], c[1], c[0]};
+    const double drift_w[3] = {c[2], c[3], c[2]};
+    long len = (long)or_dims(model) * n;
+    /* positions at the 4 kicks of every step: (nsteps * 4) x len */
+    double *qs = (double *)malloc(sizeof(double) * (size_t)len * (size_t)(4 * nsteps + 1));
+    double *q = (double *)malloc(sizeof(double) * (size_t)len);
+    double *p = (double *)malloc(sizeof(double) * (size_t)len);
+    double *f = (double *)malloc(sizeof(double) * (size_t)len);
+    double *hw = (double *)malloc(sizeof(double) * (size_t)len);
+    if (!qs || !q || !p || !f || !hw) {
+        free(qs); free(q); free(p); free(f); free(hw);
+        return -1;
+    }
+    memcpy(q, q0, sizeof(double) * (size_t)len);
+    memcpy(p, p0, sizeof(double) * (size_t)len);
+    for (long s = 0; s < nsteps; ++s) {
+        for (int k = 0; k < 4; ++k) {
+            memcpy(qs + (size_t)(4 * s + k) * len, q, sizeof(double) * (size_t)len);
+            or_force(model, n, eps, q, f);
+            kick(len, p, f, kick_w[k] * dt);
+            if (k < 3) drift(len, q, p, drift_w[k] * dt);
+        }
+    }
+    for (long s = nsteps - 1; s >= 0; --s) {
+        for (int k = 3; k >= 0; --k) {
+            if (k < 3) /* undo drift k: q += a p */
+                for (long m = 0; m < len; ++m) lp[m] += drift_w[k] * dt * lq[m];
+            or_hvp(model, n, eps, qs + (size_t)(4 * s + k) * len, lp, hw);
+            for (long m = 0; m < len; ++m) lq[m] -= kick_w[k] * dt * hw[m];
+        }
+    }
+    free(qs); free(q); free(p); free(f); free(hw);
     return 0;
 }

@@ -349,3 +349,82 @@ def test_force_rows_match_full_force():
     np.testing.assert_array_equal(oracle.force_rows(RING, q, rows, 0.01), oracle.force(RING, q, 0.01)[:, rows])
     q, _ = inputs.grav2d_disk(500, seed=13)
     np.testing.assert_array_equal(oracle.force_rows(GRAV2D, q, rows, 1e-3), oracle.force(GRAV2D, q, 1e-3)[:, rows])
+
+
+# ------------------------------------------------------------------ adjoint --
+
+@pytest.mark.parametrize("model,eps,gen", [
+    (HMF, 0.0, lambda: inputs.hmf_waterbag(20, seed=31)),
+    (RING, 0.05, lambda: inputs.ring_waterbag(20, seed=31)),
+    (GRAV2D, 1e-2, lambda: inputs.grav2d_disk(20, seed=31)),
+])
+def test_hvp_is_the_derivative_of_the_force(model, eps, gen):
+    """H w = -dF/dq . w: 4th-order central differences of the oracle force along w."""
+    q, _ = gen()
+    w = np.random.default_rng(3).normal(size=q.shape)
+    hw = oracle.hvp(model, q, w, eps)
+    h = 1e-4
+    fs = [oracle.force(model, q + s * h * w, eps) for s in (-2, -1, 1, 2)]
+    fd = -(fs[0] - 8 * fs[1] + 8 * fs[2] - fs[3]) / (12 * h)
+    assert np.abs(hw - fd).max() < 1e-8 * max(1.0, np.abs(hw).max()), np.abs(hw - fd).max()
+
+
+@pytest.mark.parametrize("model,eps", [(HMF, 0.0), (RING, 0.01), (GRAV2D, 1e-3)])
+def test_hvp_is_symmetric(model, eps):
+    """H is a Hessian: u . (H w) = w . (H u)."""
+    q, _ = inputs.uniform_state(model, 40, seed=32)
+    rng = np.random.default_rng(4)
+    u, w = rng.normal(size=q.shape), rng.normal(size=q.shape)
+    a = np.sum(u * oracle.hvp(model, q, w, eps))
+    b = np.sum(w * oracle.hvp(model, q, u, eps))
+    assert abs(a - b) < 1e-12 * max(1.0, abs(a))
+
+
+@pytest.mark.parametrize("model,eps,dt", [(HMF, 0.0, 0.1), (RING, 0.05, 0.05), (GRAV2D, 1e-2, 0.02)])
+def test_vjp_matches_finite_differences(model, eps, dt):
+    """Gradient of J = |p_T|^2 / 2 after 15 steps: <dJ/dx0, v> equals the central
+    difference of J along v (v random over all of q0 and p0)."""
+    q0, p0 = inputs.uniform_state(model, 12, seed=33, qscale=1.0, pscale=0.4)
+    nst = 15
+
+    def J(q, p):
+        f = oracle.force(model, q, eps)
+        _, pT, _ = oracle.step(model, q, p, f, dt, nst, eps)
+        return 0.5 * np.sum(pT * pT)
+    f = oracle.force(model, q0, eps)
+    _, pT, _ = oracle.step(model, q0, p0, f, dt, nst, eps)
+    lq, lp = oracle.step_vjp(model, q0, p0, dt, nst, np.zeros_like(q0), pT, eps)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        vq, vp = rng.normal(size=q0.shape), rng.normal(size=p0.shape)
+        h = 1e-5
+        fd = (J(q0 + h * vq, p0 + h * vp) - J(q0 - h * vq, p0 - h * vp)) / (2 * h)
+        ad = np.sum(lq * vq) + np.sum(lp * vp)
+        assert abs(ad - fd) < 1e-7 * max(1.0, abs(fd)), (ad, fd)
+
+
+def test_vjp_of_a_free_particle_is_exact():
+    """N = 1 feels no force: q_T = q0 + T p0, p_T = p0, so (lq, lp) at T maps to
+    (lq, lp + T lq) at 0 (the drift weights sum to one)."""
+    for model in (HMF, RING, GRAV2D):
+        d = oracle.dims(model)
+        q0, p0 = np.full((d, 1), 0.3), np.full((d, 1), -0.7)
+        a, b = np.full((d, 1), 1.25), np.full((d, 1), -0.5)
+        lq, lp = oracle.step_vjp(model, q0, p0, 0.1, 7, a, b, 0.1)
+        assert np.abs(lq - a).max() < 1e-15
+        assert np.abs(lp - (b + 0.7 * a)).max() < 1e-14
+
+
+def test_vjp_composes_over_segments():
+    """Checkpointing: the adjoint over 9 steps equals the adjoint over the last 5
+    (from the state after 4) followed by the first 4, bit for bit."""
+    q0, p0 = inputs.grav2d_disk(30, seed=34)
+    eps, dt = 1e-2, 0.01
+    f = oracle.force(GRAV2D, q0, eps)
+    q4, p4, f4 = oracle.step(GRAV2D, q0, p0, f, dt, 4, eps)
+    _, pT, _ = oracle.step(GRAV2D, q4, p4, f4, dt, 5, eps)
+    lq, lp = oracle.step_vjp(GRAV2D, q0, p0, dt, 9, np.zeros_like(q0), pT, eps)
+    mq, mp = oracle.step_vjp(GRAV2D, q4, p4, dt, 5, np.zeros_like(q0), pT, eps)
+    mq, mp = oracle.step_vjp(GRAV2D, q0, p0, dt, 4, mq, mp, eps)
+    np.testing.assert_array_equal(lq, mq)
+    np.testing.assert_array_equal(lp, mp)
