@@ -19,7 +19,7 @@ the FP64 CPU oracle's pair throughput on a bounded sample of force rows of the
 same configuration (cpu_baseline).
 
 Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-fp64] [--no-cpu]
-       python bench.py --workload ring|hmf|ensemble   (the other workloads)
+       python bench.py --workload ring|hmf|ensemble|adjoint|paper_errors   (the other workloads)
 """
 from __future__ import annotations
 
@@ -376,6 +376,155 @@ def ensemble_workload(md, torch, args):
     }
 
 
+ADJ_N = 32_768
+ADJ_EPS = 1e-3
+ADJ_DT = 0.01
+ADJ_CKPT = 50
+
+
+def adjoint_workload(md, torch, args):
+    """2D gravity adjoint: N = 32768, eps = 1e-3, uniform disk (seed 5), dt = 0.01,
+    1000 steps with checkpoints every 50: gradient of the final kinetic energy with
+    respect to (x, y, px, py) at t = 0 through md_step_vjp (FP64), checked against
+    FP64 central differences of the forward map along 16 random unit directions
+    (seeded [5, k])."""
+    import numpy as np
+
+    from paper_1212_0262_amd import autograd as mdgrad
+    from paper_1212_0262_amd import inputs
+    q0, p0 = inputs.grav2d_disk(ADJ_N, seed=5)
+    ctx = md.md_init(md.GRAV2D, md.FP64, ADJ_N, ADJ_EPS)
+    qd, pd = torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda()
+    nst = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    K, gq, gp = mdgrad.kinetic_energy_gradient(ctx, qd, pd, ADJ_DT, nst, ADJ_CKPT)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+
+    def J(q, p):
+        qq, pp = torch.from_numpy(q).cuda(), torch.from_numpy(p).cuda()
+        f = torch.empty_like(qq)
+        md.md_force(ctx, qq, f)
+        md.md_step(ctx, qq, pp, f, ADJ_DT, nst)
+        return 0.5 * float((pp * pp).sum())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J0 = J(q0, p0)
+    t_fwd = time.perf_counter() - t0
+    gq, gp = gq.cpu().numpy(), gp.cpu().numpy()
+    dirs = []
+    for k in range(16):
+        rng = np.random.default_rng([5, k])
+        v = rng.normal(size=(4, ADJ_N))
+        v /= np.linalg.norm(v)
+        dirs.append(v)
+    # step size: sweep on the first direction
+    sweep = {}
+    v = dirs[0]
+    ad0 = float(np.sum(gq * v[:2]) + np.sum(gp * v[2:]))
+    for h in (1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+        fd = (J(q0 + h * v[:2], p0 + h * v[2:]) - J(q0 - h * v[:2], p0 - h * v[2:])) / (2 * h)
+        sweep[h] = {"fd": fd, "rel_err": abs(ad0 - fd) / max(abs(fd), 1e-300)}
+        log(f"bench: adjoint h={h:g} fd={fd:.10e} ad={ad0:.10e}")
+    hbest = min(sweep, key=lambda k: sweep[k]["rel_err"])
+    rel = []
+    for v in dirs:
+        ad = float(np.sum(gq * v[:2]) + np.sum(gp * v[2:]))
+        fd = (J(q0 + hbest * v[:2], p0 + hbest * v[2:]) - J(q0 - hbest * v[:2], p0 - hbest * v[2:])) / (2 * hbest)
+        rel.append(abs(ad - fd) / max(abs(fd), 1e-300))
+    ctx.close()
+    pairs_fwd = 3.0 * ADJ_N ** 2 * nst
+    return {
+        "metric": "s per gradient of K_T w.r.t. (q0, p0) (2D adjoint N=32768, 1000 steps, FP64)",
+        "value": round(t_grad, 4), "unit": "s", "ms_per_step": round(1e3 * t_grad / nst, 4), "dtype": "f64",
+        "config": {"workload": "grav2d adjoint N=32768 eps=1e-3 dt=0.01 uniform disk seed=5, checkpoints every 50",
+                   "model": "grav2d", "n": ADJ_N, "steps": nst, "checkpoint_every": ADJ_CKPT, "precision": "fp64"},
+        "roofline": None, "cpu_baseline": None,
+        "adjoint": {"K_T": float(K), "forward_s": t_fwd, "gradient_s": t_grad,
+                    "gradient_over_forward": t_grad / t_fwd,
+                    "forward_gpairs_per_s": pairs_fwd / t_fwd / 1e9,
+                    "fd_step": hbest, "fd_sweep_dir0": {str(k): v for k, v in sweep.items()},
+                    "rel_err_16_dirs_max": max(rel), "rel_err_16_dirs_median": float(np.median(rel)),
+                    "grad_norm": float(np.sqrt(np.sum(gq * gq) + np.sum(gp * gp)))},
+    }
+
+
+def paper_errors_workload(md, torch, args):
+    """The accuracy runs of Sec. 4: relative energy error eps(t) = |E(t) - E0|/|E0| of
+    the CPU FP64 oracle, the GPU FP64 form and the GPU mixed form on the same
+    initial state.  HMF and Ring spatially homogeneous at rest (theta ~ U(-pi, pi),
+    p = 0), 2D uniform on the shell 1 <= r <= 1.5 at rest; dt = 0.1 (HMF) and
+    0.005 (Ring, 2D), eps = 1e-3 (Ring, 2D).  The paper does not state N; the GPU
+    runs use N = 10^6 (HMF) and 16384 (Ring, 2D); the oracle follows the same run
+    for a bounded prefix (its cost grows as N^2)."""
+    import numpy as np
+
+    import oracle
+    from paper_1212_0262_amd import inputs
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    runs = [("hmf", md.HMF, 1_000_000, 0.0, 0.1, 1000, 20, 200),
+            ("ring", md.RING, 16384, 1e-3, 0.005, 2000, 20, 20),
+            ("grav2d", md.GRAV2D, 16384, 1e-3, 0.005, 2000, 20, 40)]
+    out = {}
+    for name, model, n, eps, dt, nsteps, every, cpu_steps in runs:
+        if model == md.GRAV2D:
+            q0, p0 = inputs.shell_at_rest(n, seed=6)
+        else:
+            q0, p0 = inputs.homogeneous_at_rest(n, seed=6)
+        curves = {}
+        precs = [("gpu_fp64", md.FP64), ("gpu_mixed", md.MIXED_F32STATE if model == md.HMF else md.MIXED)]
+        for label, prec in precs:
+            ctx = md.md_init(model, prec, n, eps)
+            q, p = torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda()
+            f = torch.empty_like(q)
+            md.md_force(ctx, q, f)
+            es = [md.md_energy(ctx, q, p).cpu().numpy()]
+            for _ in range(nsteps // every):
+                md.md_step(ctx, q, p, f, dt, every)
+                es.append(md.md_energy(ctx, q, p).cpu().numpy())
+            curves[label] = np.array(es)
+            ctx.close()
+        # oracle prefix
+        t0 = time.perf_counter()
+        f = oracle.force(model, q0, eps)
+        qo, po = q0, p0
+        eo = [oracle.energy(model, qo, po, eps)]
+        for _ in range(cpu_steps // every):
+            qo, po, f = oracle.step(model, qo, po, f, dt, every, eps)
+            eo.append(oracle.energy(model, qo, po, eps))
+        cpu_s = time.perf_counter() - t0
+        eo = np.array(eo)
+        E0 = eo[0, 2]
+        k = len(eo)
+        rel = {lab: np.abs(c[:, 2] - E0) / abs(E0) for lab, c in curves.items()}
+        rel["cpu_fp64"] = np.abs(eo[:, 2] - E0) / abs(E0)
+        out[name] = {
+            "n": n, "dt": dt, "eps": eps, "steps": nsteps, "report_every": every, "cpu_steps": cpu_steps,
+            "E0": float(E0), "K_end_gpu_fp64": float(curves["gpu_fp64"][-1, 0]),
+            "max_rel_err": {lab: float(r.max()) for lab, r in rel.items()},
+            "max_rel_err_prefix": {lab: float(r[:k].max()) for lab, r in rel.items()},
+            "gpu_fp64_vs_cpu_max_dE_over_absE0": float(np.abs(curves["gpu_fp64"][:k, 2] - eo[:, 2]).max() / abs(E0)),
+            "gpu_mixed_vs_cpu_max_dE_over_absE0": float(np.abs(curves["gpu_mixed"][:k, 2] - eo[:, 2]).max()
+                                                        / abs(E0)),
+            "gpu_mixed_vs_gpu_fp64_max_dE_over_absE0": float(np.abs(curves["gpu_mixed"][:, 2]
+                                                                    - curves["gpu_fp64"][:, 2]).max() / abs(E0)),
+            "curve_t": [float(dt * every * i) for i in range(len(rel["gpu_fp64"]))][::5],
+            "curve_gpu_fp64": [float(x) for x in rel["gpu_fp64"][::5]],
+            "curve_gpu_mixed": [float(x) for x in rel["gpu_mixed"][::5]],
+            "cpu_seconds": cpu_s,
+        }
+        log(f"bench: paper errors {name}: max eps fp64 {out[name]['max_rel_err']['gpu_fp64']:.2e} "
+            f"mixed {out[name]['max_rel_err']['gpu_mixed']:.2e} cpu(prefix) {out[name]['max_rel_err']['cpu_fp64']:.2e}")
+    worst = max(v["gpu_mixed_vs_gpu_fp64_max_dE_over_absE0"] for v in out.values())
+    return {
+        "metric": "max |E_mixed - E_fp64| / |E0| over the paper's accuracy runs (HMF, Ring, 2D shell)",
+        "value": worst, "unit": "relative", "ms_per_step": None, "dtype": "f64+f32",
+        "config": {"workload": "accuracy runs of Sec. 4: homogeneous at rest (HMF, Ring), shell at rest (2D)"},
+        "roofline": None, "cpu_baseline": None, "paper_errors": out,
+    }
+
+
 def grav2d_workload(md, torch, args):
     import numpy as np
 
@@ -452,7 +601,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 100 grav2d, 50 ring, 1000 hmf)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["grav2d", "ring", "hmf", "ensemble"], default="grav2d")
+    ap.add_argument("--workload", choices=["grav2d", "ring", "hmf", "ensemble", "adjoint", "paper_errors"],
+                    default="grav2d")
     ap.add_argument("--no-fp64", action="store_true", help="grav2d: skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
@@ -462,7 +612,8 @@ def main() -> int:
               "(the sharded design is described in DESIGN.md)", file=sys.stderr)
         return 2
     if args.steps is None:
-        args.steps = {"grav2d": 100, "ring": 50, "hmf": 1000, "ensemble": 200}[args.workload]
+        args.steps = {"grav2d": 100, "ring": 50, "hmf": 1000, "ensemble": 200, "adjoint": 1000,
+                      "paper_errors": 0}[args.workload]
 
     import torch
 
@@ -473,11 +624,13 @@ def main() -> int:
         return 1
     md.load()
     fn = {"grav2d": grav2d_workload, "ring": ring_workload, "hmf": hmf_workload,
-          "ensemble": ensemble_workload}[args.workload]
+          "ensemble": ensemble_workload, "adjoint": adjoint_workload,
+          "paper_errors": paper_errors_workload}[args.workload]
     out = fn(md, torch, args)
+    hib = out["unit"] not in ("s", "relative")
     line = {"metric": out.pop("metric"), "value": out.pop("value"), "unit": out.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": out.pop("ms_per_step"),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": out.pop("dtype"),
+            "higher_is_better": hib, "scaling": "weak", "vs_baseline": None, "dtype": out.pop("dtype"),
             "data": "synthetic"}
     line.update(out)
     print(json.dumps(line), flush=True)

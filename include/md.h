@@ -192,6 +192,29 @@ int md_energy(md_ctx *c, const double *q, const double *p, double *out_dev3);
  */
 int md_magnetization(md_ctx *c, const double *q, double *out_dev2);
 
+/*
+ * Derivatives (single MD_RING or MD_GRAV2D contexts; others MD_EUNSUPPORTED).
+ * They differentiate the same discrete map md_step computes (eq. 4 with the
+ * forces of eqs. 1 and 3), in the context's precision.
+ *
+ * md_hvp: out = H(q) w, H the Hessian of the potential V (the force is -grad V, so
+ * its Jacobian is -H).  q, w, out: device [d][n] FP64.
+ *
+ * md_step_vjp: reverse-mode derivative of nsteps Yoshida steps started from the
+ * state (q0, p0) (e.g. a checkpoint kept during the forward run).  On entry
+ * (lam_q, lam_p) hold dJ/dq, dJ/dp of some scalar J at the state nsteps later;
+ * on exit they hold dJ/dq0, dJ/dp0.  The steps are recomputed forward from
+ * (q0, p0) (q0, p0 are not modified) and every position at which a kick evaluates
+ * the force is kept in `stage`; kicks and drifts are then undone in reverse:
+ * a drift q += a p by lam_p += a lam_q, a kick p += h F(q) by lam_q -= h H(q) lam_p.
+ * stage: caller device scratch of at least md_vjp_stage_bytes(c, nsteps) bytes
+ * (3 nsteps + 3 arrays of [d][n] FP64).  nsteps = 0 is a no-op.
+ */
+int md_hvp(md_ctx *c, const double *q, const double *w, double *out);
+size_t md_vjp_stage_bytes(const md_ctx *c, int64_t nsteps);
+int md_step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps,
+                double *lam_q, double *lam_p, double *stage, size_t stage_bytes);
+
 /* Destroy a context (does not touch the workspace).  NULL is accepted. */
 int md_destroy(md_ctx *c);
 

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmd.so")
-SOURCES = ["api.hip", "pair.hip", "hmf.hip", "energy.hip", "batch.hip"]
+SOURCES = ["api.hip", "pair.hip", "hmf.hip", "energy.hip", "batch.hip", "adjoint.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code.

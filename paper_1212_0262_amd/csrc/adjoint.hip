@@ -1,0 +1,313 @@
+// adjoint.hip -- Hessian-vector products of the pair potentials and the reverse
+// sweep of the Yoshida step (eq. 4), for gradients of an observable of the final
+// state with respect to the initial state.
+//
+// For V = sum_{i<j} phi(q_i - q_j) the product is (H w)_i = sum_j phi''(q_i - q_j)
+// (w_i - w_j), with
+//   2D (eq. 3):   phi''(r) = (2/N) [I/s - 2 r r^T / s^2],  s = |r|^2 + eps
+//   Ring (eq. 1): phi''(d) = (1/(2 sqrt2 N)) u^{-3/2} [cos d - (3/2) sin^2 d / u],
+//                 u = 1 - cos d + eps, from the cosines and sines of both angles
+//                 (FP64) or from their half angles (FP32 forms, as the force)
+// computed with the same j-broadcast, i-in-registers, j-split scheme as the force
+// (pair.hip), in FP64 or with FP32 pair arithmetic and the same accumulators.
+// The self pair contributes exactly zero (w_i - w_i = 0 and, in 2D, r = 0).
+//
+// Reverse sweep: a drift q += a p is undone by lp += a lq, a kick p += h F(q) by
+// lq -= h H(q) lp (F = -grad V).  One fused elementwise kernel combines the
+// Hessian-vector partials, applies the kick and the next drift in reverse order,
+// and refreshes the operands of the next product.
+#include "device.h"
+#include "md_internal.h"
+#include "pair_terms.h"
+
+namespace md {
+namespace {
+
+using namespace pairs;
+
+// 2D: adds (u - 2 r (r.u)/s)/s, u = w_i - w_j, r = r_i - r_j, to (ax, ay).
+template <typename T, typename A>
+__device__ __forceinline__ void hvp_2d(T xi, T yi, T wxi, T wyi, T xj, T yj, T wxj, T wyj, T eps, A &ax, A &ay)
+{
+    const T dx = xi - xj, dy = yi - yj;
+    const T inv = rcp_(fma_(dx, dx, fma_(dy, dy, eps)));
+    const T ux = wxi - wxj, uy = wyi - wyj;
+    const T t = fma_(dx, ux, dy * uy) * inv;
+    const T c = (t + t) * inv;
+    ax.add(inv, ux);
+    ax.add(-c, dx);
+    ay.add(inv, uy);
+    ay.add(-c, dy);
+}
+
+// Ring: adds phi''(d) (w_i - w_j) / pref, d = ti - tj.
+// FP64: from (cos t, sin t): u^{-3/2} [cos d - 1.5 sin^2 d / u], u = e - cos d,
+//   e = 1 + eps; pref = 1/(2 sqrt2 N).
+// FP32: from the half-angle operands sqrt2 (cos(t/2), sin(t/2)) of the force
+//   (pair_terms.h): a = 2 sin(d/2), b = 2 cos(d/2), r' = (a^2 + 2 eps)^{-1/2}
+//   (e = 2 eps): the same quantity is r'^3 [(1 - a^2/2) - (3/4) a^2 b^2 r'^2] with
+//   pref = 1/N.
+template <typename T, typename A>
+__device__ __forceinline__ void hvp_ring(T ci, T si, T wi, T cj, T sj, T wj, T e, A &acc)
+{
+    if constexpr (sizeof(T) == 8) {
+        const T cd = fma_(ci, cj, si * sj);
+        const T sd = fma_(si, cj, -(ci * sj));
+        const T r = rsq_(e - cd);
+        const T r2 = r * r;
+        const T h = r2 * r * fma_(T(-1.5) * sd * sd, r2, cd);
+        acc.add(h, wi - wj);
+    } else {
+        T a;
+        {
+#pragma clang fp contract(off)
+            a = si * cj - ci * sj;
+        }
+        const T b = fma_(ci, cj, si * sj);
+        const T a2 = a * a;
+        const T r = rsq_(a2 + e);
+        const T r2 = r * r;
+        const T h = r2 * r * fma_(T(-0.75) * a2 * b * b, r2, fma_(T(-0.5), a2, T(1)));
+        acc.add(h, wi - wj);
+    }
+}
+
+template <typename T, typename A, int IPL>
+__global__ __launch_bounds__(256) void k_hvp_2d(const T *__restrict__ xs, const T *__restrict__ ys,
+                                                const T *__restrict__ wxs, const T *__restrict__ wys, int n,
+                                                int npad, int jlen, int jtile, T eps, double *__restrict__ part)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int ibase = (blockIdx.x * (blockDim.x / kWave) + wave) * (kWave * IPL) + lane;
+    const int s = blockIdx.y;
+    const int j0 = s * jlen;
+    const int j1 = min(n, j0 + jlen);
+    T xi[IPL], yi[IPL], wxi[IPL], wyi[IPL];
+    A ax[IPL], ay[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = min(ibase + kWave * k, n - 1);
+        xi[k] = xs[i];
+        yi[k] = ys[i];
+        wxi[k] = wxs[i];
+        wyi[k] = wys[i];
+    }
+    for (int jt = j0; jt < j1; jt += jtile) {
+        const int je = min(j1, jt + jtile);
+        int j = jt;
+        for (; j + 4 <= je; j += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const T xj = xs[j + u], yj = ys[j + u], wxj = wxs[j + u], wyj = wys[j + u];
+#pragma unroll
+                for (int k = 0; k < IPL; ++k)
+                    hvp_2d(xi[k], yi[k], wxi[k], wyi[k], xj, yj, wxj, wyj, eps, ax[k], ay[k]);
+            }
+        }
+        for (; j < je; ++j) {
+            const T xj = xs[j], yj = ys[j], wxj = wxs[j], wyj = wys[j];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k)
+                hvp_2d(xi[k], yi[k], wxi[k], wyi[k], xj, yj, wxj, wyj, eps, ax[k], ay[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            ax[k].fold();
+            ay[k].fold();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = ibase + kWave * k;
+        if (i < n) {
+            part[(size_t)(2 * s) * npad + i] = ax[k].get();
+            part[(size_t)(2 * s + 1) * npad + i] = ay[k].get();
+        }
+    }
+}
+
+template <typename T, typename A, int IPL>
+__global__ __launch_bounds__(256) void k_hvp_ring(const T *__restrict__ cs, const T *__restrict__ ws, int n,
+                                                  int npad, int jlen, int jtile, T one_eps,
+                                                  double *__restrict__ part)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int ibase = (blockIdx.x * (blockDim.x / kWave) + wave) * (kWave * IPL) + lane;
+    const int s = blockIdx.y;
+    const int j0 = s * jlen;
+    const int j1 = min(n, j0 + jlen);
+    const T *__restrict__ cc = cs;
+    const T *__restrict__ ss = cs + npad;
+    T ci[IPL], si[IPL], wi[IPL];
+    A a[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = min(ibase + kWave * k, n - 1);
+        ci[k] = cc[i];
+        si[k] = ss[i];
+        wi[k] = ws[i];
+    }
+    for (int jt = j0; jt < j1; jt += jtile) {
+        const int je = min(j1, jt + jtile);
+        int j = jt;
+        for (; j + 8 <= je; j += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T cj = cc[j + u], sj = ss[j + u], wj = ws[j + u];
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) hvp_ring(ci[k], si[k], wi[k], cj, sj, wj, one_eps, a[k]);
+            }
+        }
+        for (; j < je; ++j) {
+            const T cj = cc[j], sj = ss[j], wj = ws[j];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) hvp_ring(ci[k], si[k], wi[k], cj, sj, wj, one_eps, a[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) a[k].fold();
+    }
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = ibase + kWave * k;
+        if (i < n) part[(size_t)s * npad + i] = a[k].get();
+    }
+}
+
+enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_HALF32 = 2, PREP_SINCOS64 = 3 };
+
+// Elementwise: hw = pref * (sum of the product partials, fixed order); out = hw;
+// lq -= h hw; lp += a lq; operands of the next product (positions pos, vector lp).
+template <int D, int PREP>
+__global__ __launch_bounds__(256) void k_adj_update(const double *__restrict__ part, int S, int n, int npad,
+                                                    double pref, int flags, double h, double h2, double a,
+                                                    double *__restrict__ lq, double *__restrict__ lp,
+                                                    double *__restrict__ out, const double *__restrict__ pos,
+                                                    void *__restrict__ ops, float *__restrict__ wops)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const size_t k = (size_t)d * n + i;
+        if (flags & (ADJ_OUT | ADJ_KICK)) {
+            double s = 0.0;
+            for (int b = 0; b < S; ++b) s += part[(size_t)(b * D + d) * npad + i];
+            const double hw = pref * s;
+            if (flags & ADJ_OUT) out[k] = hw;
+            if (flags & ADJ_KICK) {
+                double l = lq[k] - h * hw;
+                if (flags & ADJ_KICK2) l -= h2 * hw;  // a second kick at the same positions
+                lq[k] = l;
+            }
+        }
+        if (flags & ADJ_DRIFT) lp[k] += a * lq[k];
+        if (flags & ADJ_PREPW) wops[(size_t)d * npad + i] = (float)lp[k];
+        if ((flags & ADJ_PREPQ) && PREP != PREP_NONE) {
+            const double qd = pos[k];
+            if (PREP == PREP_CAST32) {
+                static_cast<float *>(ops)[(size_t)d * npad + i] = (float)qd;
+            } else if (PREP == PREP_HALF32) {
+                double sn, cn;
+                sincos64(0.5 * qd, &sn, &cn);
+                static_cast<float *>(ops)[i] = (float)(1.4142135623730951 * cn);
+                static_cast<float *>(ops)[npad + i] = (float)(1.4142135623730951 * sn);
+            } else {
+                double sn, cn;
+                sincos64(qd, &sn, &cn);
+                static_cast<double *>(ops)[i] = cn;
+                static_cast<double *>(ops)[npad + i] = sn;
+            }
+        }
+    }
+}
+
+int prep_kind(const md_ctx *c)
+{
+    if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? PREP_NONE : PREP_CAST32;
+    return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_HALF32;
+}
+
+template <typename T, typename A>
+hipError_t hvp_launch(md_ctx *c, const void *qsrc, const void *wsrc, dim3 grid, dim3 block, int jlen)
+{
+    const int n = (int)c->n, npad = (int)c->npad, jt = c->tiles.jtile;
+    const bool fp64 = c->prec == MD_FP64;
+    if (c->model == MD_GRAV2D) {
+        const T *x = static_cast<const T *>(qsrc);
+        const T *y = x + (fp64 ? n : npad);
+        const T *wx = static_cast<const T *>(wsrc);
+        const T *wy = wx + (fp64 ? n : npad);
+        const T eps = (T)c->eps;
+        switch (c->tiles.ipl) {
+        case 1: hipLaunchKernelGGL((k_hvp_2d<T, A, 1>), grid, block, 0, c->stream, x, y, wx, wy, n, npad, jlen, jt, eps, c->part); break;
+        case 2: hipLaunchKernelGGL((k_hvp_2d<T, A, 2>), grid, block, 0, c->stream, x, y, wx, wy, n, npad, jlen, jt, eps, c->part); break;
+        default: hipLaunchKernelGGL((k_hvp_2d<T, A, 4>), grid, block, 0, c->stream, x, y, wx, wy, n, npad, jlen, jt, eps, c->part); break;
+        }
+    } else {
+        const T *cs = static_cast<const T *>(qsrc);
+        const T *w = static_cast<const T *>(wsrc);
+        const T one_eps = sizeof(T) == 8 ? (T)(1.0 + c->eps) : (T)(2.0 * c->eps);  // FP32 half-angle form: 2 eps
+        switch (c->tiles.ipl) {
+        case 1: hipLaunchKernelGGL((k_hvp_ring<T, A, 1>), grid, block, 0, c->stream, cs, w, n, npad, jlen, jt, one_eps, c->part); break;
+        case 2: hipLaunchKernelGGL((k_hvp_ring<T, A, 2>), grid, block, 0, c->stream, cs, w, n, npad, jlen, jt, one_eps, c->part); break;
+        default: hipLaunchKernelGGL((k_hvp_ring<T, A, 4>), grid, block, 0, c->stream, cs, w, n, npad, jlen, jt, one_eps, c->part); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Product partials of H(pos) w into c->part.  FP64 2D reads pos and w directly;
+// every other form reads the operands prepared by launch_adj_update (ADJ_PREPQ,
+// ADJ_PREPW), i.e. `pos` and `w` must be the arrays those operands came from.
+hipError_t launch_hvp_pair(md_ctx *c, const double *pos, const double *w)
+{
+    const Tiles &t = c->tiles;
+    const int n = (int)c->n;
+    const int per_block = kWave * t.ipl * t.waves;
+    const dim3 block((unsigned)(kWave * t.waves));
+    const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)t.jsplit);
+    int jlen = (n + t.jsplit - 1) / t.jsplit;
+    jlen = (jlen + 15) / 16 * 16;
+    const bool fp64 = c->prec == MD_FP64;
+    const void *qsrc = (c->model == MD_GRAV2D && fp64) ? (const void *)pos : (const void *)c->ops;
+    const void *wsrc = fp64 ? (const void *)w : (const void *)c->wops;
+    switch (c->prec) {
+    case MD_FP64: return hvp_launch<double, AccF64>(c, qsrc, wsrc, grid, block, jlen);
+    case MD_MIXED: return hvp_launch<float, AccTile>(c, qsrc, wsrc, grid, block, jlen);
+    case MD_MIXED_KAHAN: return hvp_launch<float, AccKahan>(c, qsrc, wsrc, grid, block, jlen);
+    default: return hvp_launch<float, AccPair64>(c, qsrc, wsrc, grid, block, jlen);
+    }
+}
+
+hipError_t launch_adj_update(md_ctx *c, int flags, double h, double h2, double a, double *lq, double *lp,
+                             double *out, const double *pos)
+{
+    const int n = (int)c->n;
+    const dim3 block(256), grid((unsigned)((n + 255) / 256));
+    // Hessian prefactors: 2/N (2D); 1/(2 sqrt2 N) (Ring, FP64 terms); 1/N (Ring, half-angle FP32 terms)
+    const double pref = c->model == MD_GRAV2D ? 2.0 / (double)n
+                        : c->prec == MD_FP64  ? 1.0 / (2.0 * 1.4142135623730951 * (double)n)
+                                              : 1.0 / (double)n;
+    const int pk = prep_kind(c);
+    if (c->prec == MD_FP64) flags &= ~ADJ_PREPW;
+    if (pk == PREP_NONE) flags &= ~ADJ_PREPQ;
+    const int S = c->tiles.jsplit, npad = (int)c->npad;
+#define MD_ADJ(D_, P_)                                                                                          \
+    hipLaunchKernelGGL((k_adj_update<D_, P_>), grid, block, 0, c->stream, c->part, S, n, npad, pref, flags, h, h2, a, \
+                       lq, lp, out, pos, c->ops, c->wops)
+    if (c->model == MD_GRAV2D) {
+        if (pk == PREP_CAST32) MD_ADJ(2, PREP_CAST32);
+        else MD_ADJ(2, PREP_NONE);
+    } else {
+        if (pk == PREP_HALF32) MD_ADJ(1, PREP_HALF32);
+        else MD_ADJ(1, PREP_SINCOS64);
+    }
+#undef MD_ADJ
+    return hipGetLastError();
+}
+
+}  // namespace md

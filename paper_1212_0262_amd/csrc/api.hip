@@ -44,7 +44,7 @@ bool prec_ok(int model, int prec)
 bool model_ok(int model) { return model == MD_HMF || model == MD_RING || model == MD_GRAV2D; }
 
 struct Layout {
-    size_t red, scal, ops, part, th32, p32, total;
+    size_t red, scal, ops, wops, part, th32, p32, total;
 };
 
 Layout layout(int model, int prec, int64_t n)
@@ -59,6 +59,8 @@ Layout layout(int model, int prec, int64_t n)
     L.ops = off;
     if (model == MD_RING) off = align_up(off + 2 * npad * (prec == MD_FP64 ? sizeof(double) : sizeof(float)));
     else if (model == MD_GRAV2D && prec != MD_FP64) off = align_up(off + 2 * npad * sizeof(float));
+    L.wops = off;
+    if (model != MD_HMF && prec != MD_FP64) off = align_up(off + (size_t)dims(model) * npad * sizeof(float));
     L.part = off;
     if (model != MD_HMF) off = align_up(off + (size_t)max_j_split(n) * dims(model) * npad * sizeof(double));
     L.th32 = off;
@@ -126,30 +128,80 @@ void yoshida(double *b0, double *b1, double *d0, double *d1)
 // Pair partials and update stage of a single system or a batched ensemble.
 hipError_t pair_(md_ctx *c, const double *q) { return c->batch ? batch_pair(c, q) : launch_pair(c, q); }
 
-hipError_t update_(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p, double *f)
+// snap (single systems only): the positions after every drift are also written to
+// consecutive [d][n] slots of snap.
+hipError_t update_(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p, double *f,
+                   double *snap = nullptr)
 {
     return c->batch ? batch_update(c, flags, kick1, kick2, drift, q, p, f)
-                    : launch_update(c, flags, kick1, kick2, drift, q, p, f);
+                    : launch_update(c, flags, kick1, kick2, drift, q, p, f, snap);
 }
 
-int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps)
+int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps, double *snap = nullptr)
 {
     double B0, B1, D0, D1;
     yoshida(&B0, &B1, &D0, &D1);
     const int stage = UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1 | UPD_DRIFT | UPD_PREP;
-    MD_TRY(update_(c, UPD_KICK1 | UPD_DRIFT | UPD_PREP, B0 * dt, 0.0, D0 * dt, q, p, f), "step: first kick");
+    const size_t len = (size_t)dims(c->model) * c->n;
+    int64_t slot = 0;
+    auto next = [&]() { return snap ? snap + (size_t)(slot++) * len : nullptr; };
+    MD_TRY(update_(c, UPD_KICK1 | UPD_DRIFT | UPD_PREP, B0 * dt, 0.0, D0 * dt, q, p, f, next()), "step: first kick");
     for (int64_t s = 0; s < nsteps; ++s) {
         MD_TRY(pair_(c, q), "step: pair kernel");
-        MD_TRY(update_(c, stage, B1 * dt, 0.0, D1 * dt, q, p, f), "step: update");
+        MD_TRY(update_(c, stage, B1 * dt, 0.0, D1 * dt, q, p, f, next()), "step: update");
         MD_TRY(pair_(c, q), "step: pair kernel");
-        MD_TRY(update_(c, stage, B1 * dt, 0.0, D0 * dt, q, p, f), "step: update");
+        MD_TRY(update_(c, stage, B1 * dt, 0.0, D0 * dt, q, p, f, next()), "step: update");
         MD_TRY(pair_(c, q), "step: pair kernel");
         if (s + 1 < nsteps)
-            MD_TRY(update_(c, stage | UPD_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, f), "step: update");
+            MD_TRY(update_(c, stage | UPD_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, f, next()), "step: update");
         else
             MD_TRY(update_(c, UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1, B0 * dt, 0.0, 0.0, q, p, f),
                    "step: last kick");
     }
+    return MD_OK;
+}
+
+// Reverse sweep of nsteps steps (see md_step_vjp).  stage = [q | p | f | P_1 .. P_3n],
+// each [d][n]; P_m are the positions at which the kicks evaluate the force
+// (P_0 = q0).
+int step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps, double *lq, double *lp,
+             double *stage)
+{
+    double B0, B1, D0, D1;
+    yoshida(&B0, &B1, &D0, &D1);
+    const size_t len = (size_t)dims(c->model) * c->n;
+    double *qw = stage, *pw = stage + len, *fw = stage + 2 * len, *P = stage + 3 * len;
+    auto pos = [&](int64_t m) -> const double * { return m == 0 ? q0 : P + (size_t)(m - 1) * len; };
+    MD_TRY(hipMemcpyAsync(qw, q0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy q");
+    MD_TRY(hipMemcpyAsync(pw, p0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy p");
+    // forward recompute, keeping the kick positions
+    MD_TRY(update_(c, UPD_PREP, 0.0, 0.0, 0.0, qw, nullptr, nullptr), "vjp: operands");
+    MD_TRY(pair_(c, qw), "vjp: pair kernel");
+    MD_TRY(update_(c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, fw), "vjp: force");
+    int st = step_pairs(c, qw, pw, fw, dt, nsteps, P);
+    if (st != MD_OK) return st;
+    // reverse: pending product at P_3n, kick weight B0 dt
+    const int prep = ADJ_PREPQ | ADJ_PREPW;
+    MD_TRY(launch_adj_update(c, prep, 0.0, 0.0, 0.0, lq, lp, nullptr, pos(3 * nsteps)), "vjp: operands");
+    MD_TRY(launch_hvp_pair(c, pos(3 * nsteps), lp), "vjp: hvp");
+    int kick = ADJ_KICK;  // the pending product's kick(s)
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+        MD_TRY(launch_adj_update(c, kick | ADJ_DRIFT | prep, B0 * dt, B0 * dt, D0 * dt, lq, lp, nullptr,
+                                 pos(3 * s + 2)),
+               "vjp: update");
+        MD_TRY(launch_hvp_pair(c, pos(3 * s + 2), lp), "vjp: hvp");
+        MD_TRY(launch_adj_update(c, ADJ_KICK | ADJ_DRIFT | prep, B1 * dt, 0.0, D1 * dt, lq, lp, nullptr,
+                                 pos(3 * s + 1)),
+               "vjp: update");
+        MD_TRY(launch_hvp_pair(c, pos(3 * s + 1), lp), "vjp: hvp");
+        MD_TRY(launch_adj_update(c, ADJ_KICK | ADJ_DRIFT | prep, B1 * dt, 0.0, D0 * dt, lq, lp, nullptr, pos(3 * s)),
+               "vjp: update");
+        MD_TRY(launch_hvp_pair(c, pos(3 * s), lp), "vjp: hvp");
+        // the first kick of step s and the last kick of step s - 1 act at the same
+        // positions with no drift between them: one product, applied as two kicks
+        kick = s > 0 ? (ADJ_KICK | ADJ_KICK2) : ADJ_KICK;
+    }
+    MD_TRY(launch_adj_update(c, kick, B0 * dt, B0 * dt, 0.0, lq, lp, nullptr, nullptr), "vjp: last kick");
     return MD_OK;
 }
 
@@ -191,7 +243,7 @@ int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int64_t batch_chunk(const Batch &B, int jsplit) { return div_up(div_up(B.nmax, jsplit), 64) * 64; }
 
 // Validates the ensemble description and fills the tile-independent parts of B.
-int make_batch(int model, int nb, const int64_t *off, const double *eps, Batch &B)
+int make_batch(int model, int prec, int nb, const int64_t *off, const double *eps, Batch &B)
 {
     if (nb < 1 || !off || !eps) return MD_EINVAL;
     if (off[0] != 0) return MD_EINVAL;
@@ -205,7 +257,7 @@ int make_batch(int model, int nb, const int64_t *off, const double *eps, Batch &
         if (n < 1 || off[b + 1] > kMaxBatchTotal) return MD_EINVAL;
         if (!(eps[b] > 0.0 && isfinite(eps[b]))) return MD_EINVAL;
         if (n > B.nmax) B.nmax = n;
-        B.pref[b] = model == MD_GRAV2D ? -2.0 / (double)n : -1.0 / (2.0 * sqrt(2.0) * (double)n);
+        B.pref[b] = force_prefactor(model, prec, n);
     }
     int64_t sm = B.nmax / 64;
     B.smax = (int)(sm < 1 ? 1 : (sm > kBatchMaxSplit ? kBatchMaxSplit : sm));
@@ -410,7 +462,8 @@ int md_init(md_ctx **out, int model, int prec, int64_t n, double eps, void *hip_
     c->ws_bytes = workspace_bytes;
     c->red = reinterpret_cast<double *>(c->ws + L.red);
     c->scal = reinterpret_cast<double *>(c->ws + L.scal);
-    c->ops = (L.part > L.ops) ? static_cast<void *>(c->ws + L.ops) : nullptr;
+    c->ops = (L.wops > L.ops) ? static_cast<void *>(c->ws + L.ops) : nullptr;
+    c->wops = (L.part > L.wops) ? reinterpret_cast<float *>(c->ws + L.wops) : nullptr;
     c->part = (L.th32 > L.part) ? reinterpret_cast<double *>(c->ws + L.part) : nullptr;
     c->th32 = (L.p32 > L.th32) ? reinterpret_cast<float *>(c->ws + L.th32) : nullptr;
     c->p32 = (L.total > L.p32) ? reinterpret_cast<float *>(c->ws + L.p32) : nullptr;
@@ -428,7 +481,7 @@ size_t md_batch_workspace_bytes(int model, int prec, int nb, const int64_t *offs
 {
     if (!(model == MD_RING || model == MD_GRAV2D) || !prec_ok(model, prec)) return 0;
     Batch B;
-    if (make_batch(model, nb, offsets, eps, B) != MD_OK) return 0;
+    if (make_batch(model, prec, nb, offsets, eps, B) != MD_OK) return 0;
     return batch_layout(model, prec, B).total;
 }
 
@@ -442,7 +495,7 @@ int md_batch_init(md_ctx **out, int model, int prec, int nb, const int64_t *offs
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return MD_EINVAL;
     Batch *B = new (std::nothrow) Batch();
     if (!B) return MD_ENOMEM;
-    int st = make_batch(model, nb, offsets, eps, *B);
+    int st = make_batch(model, prec, nb, offsets, eps, *B);
     if (st != MD_OK) {
         delete B;
         return st;
@@ -603,6 +656,48 @@ int md_magnetization(md_ctx *c, const double *q, double *out_dev2)
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_magnetization: set device");
     MD_TRY(launch_magnetization(c, q, out_dev2), "magnetization");
     return MD_OK;
+}
+
+int md_hvp(md_ctx *c, const double *q, const double *w, double *out)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (c->model == MD_HMF || c->batch) return fail(c, MD_EUNSUPPORTED, "md_hvp: Ring and 2D single systems only");
+    if (!q || !w || !out || !aligned8(q) || !aligned8(w) || !aligned8(out))
+        return fail(c, MD_EINVAL, "md_hvp: null or misaligned pointer");
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_hvp: set device");
+    double *wm = const_cast<double *>(w);
+    MD_TRY(launch_adj_update(c, ADJ_PREPQ | ADJ_PREPW, 0.0, 0.0, 0.0, nullptr, wm, nullptr, q), "hvp: operands");
+    MD_TRY(launch_hvp_pair(c, q, w), "hvp: pair kernel");
+    MD_TRY(launch_adj_update(c, ADJ_OUT, 0.0, 0.0, 0.0, nullptr, nullptr, out, nullptr), "hvp: combine");
+    return MD_OK;
+}
+
+size_t md_vjp_stage_bytes(const md_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return 0;
+    return (size_t)(3 * nsteps + 3) * dims(c->model) * (size_t)c->n * sizeof(double);
+}
+
+int md_step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps, double *lam_q,
+                double *lam_p, double *stage, size_t stage_bytes)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (c->model == MD_HMF || c->batch)
+        return fail(c, MD_EUNSUPPORTED, "md_step_vjp: Ring and 2D single systems only");
+    if (!q0 || !p0 || !lam_q || !lam_p || !stage || !aligned8(q0) || !aligned8(p0) || !aligned8(lam_q) ||
+        !aligned8(lam_p) || !aligned8(stage))
+        return fail(c, MD_EINVAL, "md_step_vjp: null or misaligned pointer");
+    if (!isfinite(dt)) return fail(c, MD_EINVAL, "md_step_vjp: dt must be finite");
+    if (nsteps < 0) return fail(c, MD_EINVAL, "md_step_vjp: nsteps must be >= 0");
+    if (stage_bytes < md_vjp_stage_bytes(c, nsteps))
+        return fail(c, MD_ENOMEM, "md_step_vjp: stage buffer needs %zu bytes", md_vjp_stage_bytes(c, nsteps));
+    if (nsteps == 0) return MD_OK;
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_step_vjp: set device");
+    return step_vjp(c, q0, p0, dt, nsteps, lam_q, lam_p, stage);
 }
 
 int md_destroy(md_ctx *c)

@@ -82,6 +82,14 @@ __global__ __launch_bounds__(256) void k_batch_pair_2d(const PairItem *__restric
     }
 }
 
+// Ring pair term: eq. 9 in FP64, the half-angle form in FP32 (see pair_terms.h).
+template <typename T, typename A>
+__device__ __forceinline__ void ring_term(T c0, T s0, T c1, T s1, T e, A &a)
+{
+    if constexpr (sizeof(T) == 8) pair_ring(c0, s0, c1, s1, e, a);
+    else pair_ring_half(s0, c0, s1, c1, e, a);
+}
+
 template <typename T, typename A, int IPL>
 __global__ __launch_bounds__(256) void k_batch_pair_ring(const PairItem *__restrict__ items, const T *__restrict__ cs,
                                                          const double *__restrict__ beps, int npad, int jtile,
@@ -91,7 +99,7 @@ __global__ __launch_bounds__(256) void k_batch_pair_ring(const PairItem *__restr
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int ibase = it.i0 + wave * (kWave * IPL) + lane;
-    const T one_eps = (T)(1.0 + beps[it.b]);
+    const T one_eps = sizeof(T) == 8 ? (T)(1.0 + beps[it.b]) : (T)(2.0 * beps[it.b]);  // FP32 half-angle form: 2 eps
     const T *__restrict__ cc = cs;
     const T *__restrict__ ss = cs + npad;
     T ci[IPL], si[IPL];
@@ -111,14 +119,14 @@ __global__ __launch_bounds__(256) void k_batch_pair_ring(const PairItem *__restr
                 const T cj = cc[j + u];
                 const T sj = ss[j + u];
 #pragma unroll
-                for (int k = 0; k < IPL; ++k) pair_ring(ci[k], si[k], cj, sj, one_eps, a[k]);
+                for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, one_eps, a[k]);
             }
         }
         for (; j < je; ++j) {
             const T cj = cc[j];
             const T sj = ss[j];
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) pair_ring(ci[k], si[k], cj, sj, one_eps, a[k]);
+            for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, one_eps, a[k]);
         }
 #pragma unroll
         for (int k = 0; k < IPL; ++k) a[k].fold();
@@ -130,11 +138,12 @@ __global__ __launch_bounds__(256) void k_batch_pair_ring(const PairItem *__restr
     }
 }
 
-enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_SINCOS32 = 2, PREP_SINCOS64 = 3 };
+enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_HALF32 = 2, PREP_SINCOS64 = 3 };
 
 // One kick-drift stage for the particles [i0, i1) of realization b (one block per
 // row item, up to 256 particles): f = pref_b * (chunk partials added in order),
-// kick(s), drift, refresh of the pair operands.  rows[k] = (b, i0, i1, S_b).
+// kick(s), drift, refresh of the pair operands.  rows[k] = (b, i0, i1, S_b);
+// bpref[b] is the realization's force prefactor (1/N_b coupling).
 template <int D, int PREP>
 __global__ __launch_bounds__(256) void k_batch_update(const int4 *__restrict__ rows,
                                                       const double *__restrict__ bpref,
@@ -176,16 +185,16 @@ __global__ __launch_bounds__(256) void k_batch_update(const int4 *__restrict__ r
         if (flags & UPD_PREP) {
             if (PREP == PREP_CAST32) {
                 static_cast<float *>(ops)[(size_t)d * npad + i] = (float)qd;
-            } else if (PREP == PREP_SINCOS32 || PREP == PREP_SINCOS64) {
+            } else if (PREP == PREP_HALF32) {
+                double sn, cn;
+                sincos64(0.5 * qd, &sn, &cn);
+                static_cast<float *>(ops)[i] = (float)(1.4142135623730951 * cn);
+                static_cast<float *>(ops)[npad + i] = (float)(1.4142135623730951 * sn);
+            } else if (PREP == PREP_SINCOS64) {
                 double sn, cn;
                 sincos64(qd, &sn, &cn);
-                if (PREP == PREP_SINCOS32) {
-                    static_cast<float *>(ops)[i] = (float)cn;
-                    static_cast<float *>(ops)[npad + i] = (float)sn;
-                } else {
-                    static_cast<double *>(ops)[i] = cn;
-                    static_cast<double *>(ops)[npad + i] = sn;
-                }
+                static_cast<double *>(ops)[i] = cn;
+                static_cast<double *>(ops)[npad + i] = sn;
             }
         }
     }
@@ -273,7 +282,7 @@ __global__ __launch_bounds__(256) void k_batch_energy_finalize(const double *__r
 int prep_kind(const md_ctx *c)
 {
     if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? PREP_NONE : PREP_CAST32;
-    return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_SINCOS32;
+    return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_HALF32;
 }
 
 template <typename T, typename A>
@@ -331,7 +340,7 @@ hipError_t batch_update(md_ctx *c, int flags, double kick1, double kick2, double
         if (pk == PREP_CAST32) MD_BUPD(2, PREP_CAST32);
         else MD_BUPD(2, PREP_NONE);
     } else {
-        if (pk == PREP_SINCOS32) MD_BUPD(1, PREP_SINCOS32);
+        if (pk == PREP_HALF32) MD_BUPD(1, PREP_HALF32);
         else MD_BUPD(1, PREP_SINCOS64);
     }
 #undef MD_BUPD

@@ -79,6 +79,7 @@ struct md_ctx {
     size_t ws_bytes = 0;
     // workspace carve-up
     void *ops = nullptr;      // pair operands: 2D [2][npad] FP32 copy; Ring [2][npad] cos,sin (FP32 or FP64)
+    float *wops = nullptr;    // FP32 copy of the Hessian-vector product's vector (mixed forms)
     double *part = nullptr;   // pair partials [jsplit][d][npad]
     double *red = nullptr;    // reduction partials [kRedSlots]
     double *scal = nullptr;   // small device scalars (HMF magnetization, ...)
@@ -97,13 +98,21 @@ int dims(int model);
 int max_j_split(int64_t n);
 Tiles default_tiles(int model, int prec, int64_t n);
 int hmf_grid(int64_t n);  // blocks of the HMF passes (fixed per n: reproducible sums)
+// f = prefactor * (sum of the pair terms): -2/N (2D); -1/(2 sqrt2 N) for the Ring
+// terms of eq. 9 (FP64); -1/(2N) for the half-angle Ring terms (FP32 forms).
+inline double force_prefactor(int model, int prec, int64_t n)
+{
+    if (model == MD_GRAV2D) return -2.0 / (double)n;
+    return prec == MD_FP64 ? -1.0 / (2.0 * 1.4142135623730951 * (double)n) : -1.0 / (2.0 * (double)n);
+}
 
 // Launchers return hipSuccess or the launch error.  All enqueue on c->stream.
 // pair.hip
 hipError_t launch_prep(md_ctx *c, const double *q);
 hipError_t launch_pair(md_ctx *c, const double *q);
+// snap (nullable): with UPD_DRIFT, the drifted positions are also written there.
 hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift,
-                         double *q, double *p, double *f);
+                         double *q, double *p, double *f, double *snap = nullptr);
 // hmf.hip
 hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, double drift,
                            double *th, double *p, const double *f_in, double *f_out,
@@ -116,6 +125,18 @@ hipError_t batch_pair(md_ctx *c, const double *q);
 hipError_t batch_update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
                         double *f);
 hipError_t batch_energy(md_ctx *c, const double *q, const double *p, double *out);
+// adjoint.hip
+enum : int {
+    ADJ_OUT = 1 << 0,    // out = H w (combine the partials)
+    ADJ_KICK = 1 << 1,   // lq -= h * (H w)
+    ADJ_DRIFT = 1 << 2,  // lp += a * lq
+    ADJ_PREPQ = 1 << 3,  // pair operands from the positions pos
+    ADJ_PREPW = 1 << 4,  // FP32 vector operand from lp (mixed forms)
+    ADJ_KICK2 = 1 << 5,  // then lq -= h2 * (H w): a second kick at the same positions
+};
+hipError_t launch_hvp_pair(md_ctx *c, const double *pos, const double *w);
+hipError_t launch_adj_update(md_ctx *c, int flags, double h, double h2, double a, double *lq, double *lp,
+                             double *out, const double *pos);
 // energy.hip
 hipError_t launch_energy(md_ctx *c, const double *q, const double *p, double *out3);
 hipError_t launch_magnetization(md_ctx *c, const double *q, double *out2);

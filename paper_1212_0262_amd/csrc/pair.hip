@@ -84,8 +84,17 @@ __global__ __launch_bounds__(256) void k_pair_2d(const T *__restrict__ xs, const
     }
 }
 
+// The Ring pair term of the context's precision: eq. 9 on (cos t, sin t) in FP64;
+// the half-angle form on sqrt2 (cos(t/2), sin(t/2)) in FP32 (then one_eps holds 2 eps).
+template <typename T, typename A>
+__device__ __forceinline__ void ring_term(T c0, T s0, T c1, T s1, T e, A &a)
+{
+    if constexpr (sizeof(T) == 8) pair_ring(c0, s0, c1, s1, e, a);
+    else pair_ring_half(s0, c0, s1, c1, e, a);
+}
+
 // part[s*npad + i] = sum over j in the s-th j range of the Ring pair term.
-// cs = [cos row | sin row], each npad long.
+// cs = two rows of npad: [cos t | sin t] (FP64) or sqrt2 [cos(t/2) | sin(t/2)] (FP32).
 template <typename T, typename A, int IPL>
 __global__ __launch_bounds__(256) void k_pair_ring(const T *__restrict__ cs, int n, int npad, int jlen,
                                                    int jtile, T one_eps, double *__restrict__ part)
@@ -116,14 +125,14 @@ __global__ __launch_bounds__(256) void k_pair_ring(const T *__restrict__ cs, int
                 const T cj = cc[j + u];
                 const T sj = ss[j + u];
 #pragma unroll
-                for (int k = 0; k < IPL; ++k) pair_ring(ci[k], si[k], cj, sj, one_eps, a[k]);
+                for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, one_eps, a[k]);
             }
         }
         for (; j < je; ++j) {
             const T cj = cc[j];
             const T sj = ss[j];
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) pair_ring(ci[k], si[k], cj, sj, one_eps, a[k]);
+            for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, one_eps, a[k]);
         }
 #pragma unroll
         for (int k = 0; k < IPL; ++k) a[k].fold();
@@ -138,7 +147,7 @@ __global__ __launch_bounds__(256) void k_pair_ring(const T *__restrict__ cs, int
 // --------------------------------------------------------------- update kernel --
 
 // Operand refresh after a drift.
-enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_SINCOS32 = 2, PREP_SINCOS64 = 3 };
+enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_HALF32 = 2, PREP_SINCOS64 = 3 };
 
 // One kick-drift stage, elementwise over particles (eq. 4 and the step list of
 // Sec. 3): f from the pair partials (times the model prefactor), p += kick * f,
@@ -148,7 +157,7 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ part,
                                                 double pref, double *__restrict__ f,
                                                 double *__restrict__ p, double *__restrict__ q,
                                                 void *__restrict__ ops, double kick1, double kick2,
-                                                double drift, int flags)
+                                                double drift, int flags, double *__restrict__ snap)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -175,21 +184,22 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ part,
             if (flags & UPD_DRIFT) {
                 qd += drift * pd;
                 q[k] = qd;
+                if (snap) snap[k] = qd;
             }
         }
         if (flags & UPD_PREP) {
             if (PREP == PREP_CAST32) {
                 static_cast<float *>(ops)[(size_t)d * npad + i] = (float)qd;
-            } else if (PREP == PREP_SINCOS32 || PREP == PREP_SINCOS64) {
+            } else if (PREP == PREP_HALF32) {
+                double sn, cn;
+                sincos64(0.5 * qd, &sn, &cn);
+                static_cast<float *>(ops)[i] = (float)(1.4142135623730951 * cn);
+                static_cast<float *>(ops)[npad + i] = (float)(1.4142135623730951 * sn);
+            } else if (PREP == PREP_SINCOS64) {
                 double sn, cn;
                 sincos64(qd, &sn, &cn);
-                if (PREP == PREP_SINCOS32) {
-                    static_cast<float *>(ops)[i] = (float)cn;
-                    static_cast<float *>(ops)[npad + i] = (float)sn;
-                } else {
-                    static_cast<double *>(ops)[i] = cn;
-                    static_cast<double *>(ops)[npad + i] = sn;
-                }
+                static_cast<double *>(ops)[i] = cn;
+                static_cast<double *>(ops)[npad + i] = sn;
             }
         }
     }
@@ -200,27 +210,27 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ part,
 int prep_kind(const md_ctx *c)
 {
     if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? PREP_NONE : PREP_CAST32;
-    return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_SINCOS32;
+    return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_HALF32;
 }
 
 hipError_t update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
-                  double *f)
+                  double *f, double *snap)
 {
     const int n = (int)c->n;
     const dim3 block(256), grid((unsigned)((n + 255) / 256));
-    const double pref = c->model == MD_GRAV2D ? -2.0 / (double)n : -1.0 / (2.0 * sqrt(2.0) * (double)n);
+    const double pref = force_prefactor(c->model, c->prec, n);
     const int S = c->tiles.jsplit;
     const int npad = (int)c->npad;
     const int pk = prep_kind(c);
     if (pk == PREP_NONE) flags &= ~UPD_PREP;
 #define MD_UPD(D_, P_)                                                                                    \
     hipLaunchKernelGGL((k_update<D_, P_>), grid, block, 0, c->stream, c->part, S, n, npad, pref, f, p, q, \
-                       c->ops, kick1, kick2, drift, flags)
+                       c->ops, kick1, kick2, drift, flags, snap)
     if (c->model == MD_GRAV2D) {
         if (pk == PREP_CAST32) MD_UPD(2, PREP_CAST32);
         else MD_UPD(2, PREP_NONE);
     } else {
-        if (pk == PREP_SINCOS32) MD_UPD(1, PREP_SINCOS32);
+        if (pk == PREP_HALF32) MD_UPD(1, PREP_HALF32);
         else MD_UPD(1, PREP_SINCOS64);
     }
 #undef MD_UPD
@@ -242,7 +252,7 @@ hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
         }
     } else {
         const T *cs = static_cast<const T *>(src);
-        const T one_eps = (T)(1.0 + c->eps);
+        const T one_eps = sizeof(T) == 8 ? (T)(1.0 + c->eps) : (T)(2.0 * c->eps);  // FP32 half-angle form: 2 eps
         switch (c->tiles.ipl) {
         case 1: hipLaunchKernelGGL((k_pair_ring<T, A, 1>), grid, block, 0, c->stream, cs, n, npad, jlen, jt, one_eps, c->part); break;
         case 2: hipLaunchKernelGGL((k_pair_ring<T, A, 2>), grid, block, 0, c->stream, cs, n, npad, jlen, jt, one_eps, c->part); break;
@@ -257,13 +267,13 @@ hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
 hipError_t launch_prep(md_ctx *c, const double *q)
 {
     if (prep_kind(c) == PREP_NONE) return hipSuccess;
-    return update(c, UPD_PREP, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr);
+    return update(c, UPD_PREP, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr, nullptr);
 }
 
 hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
-                         double *f)
+                         double *f, double *snap)
 {
-    return update(c, flags, kick1, kick2, drift, q, p, f);
+    return update(c, flags, kick1, kick2, drift, q, p, f, snap);
 }
 
 // Pair partials of the current operands.  For FP64 2D the operands are q itself.

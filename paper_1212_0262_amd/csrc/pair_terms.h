@@ -85,5 +85,26 @@ __device__ __forceinline__ void pair_ring(T ci, T si, T cj, T sj, T one_eps, A &
     a.add(num, r * r * r);
 }
 
+// Ring, half-angle operands (the FP32 forms): A = sqrt2 sin(t/2), B = sqrt2 cos(t/2)
+// of each angle.  With d = ti - tj:  a = A_i B_j - B_i A_j = 2 sin(d/2) (exactly
+// antisymmetric: two rounded products) and b = B_i B_j + A_i A_j = 2 cos(d/2), so
+// 1 - cos d = a^2/2 and sin d = a b/2.  With u' = a^2 + 2 eps = 2 (1 - cos d + eps)
+// and r' = u'^{-1/2}, the term sin d / (1 - cos d + eps)^{3/2} is sqrt2 a b r'^3;
+// the sqrt2 goes into the prefactor, and eps2 = 2 eps.  Unlike eq. 9's angle-sum
+// form, 1 - cos d is formed without cancelling against 1: its rounding error
+// scales with |d|, which matters in FP32 for close pairs.
+template <typename T, typename A>
+__device__ __forceinline__ void pair_ring_half(T ai, T bi, T aj, T bj, T eps2, A &acc)
+{
+    T a;
+    {
+#pragma clang fp contract(off)
+        a = ai * bj - bi * aj;
+    }
+    const T b = fma_(bi, bj, ai * aj);
+    const T r = rsq_(fma_(a, a, eps2));
+    acc.add(a * b, r * r * r);
+}
+
 }  // namespace pairs
 }  // namespace md

@@ -47,6 +47,9 @@ SIGNATURES = {
     "md_step": (_I, [_V, _V, _V, _V, _D, _I64]),
     "md_energy": (_I, [_V, _V, _V, _V]),
     "md_magnetization": (_I, [_V, _V, _V]),
+    "md_hvp": (_I, [_V, _V, _V, _V]),
+    "md_vjp_stage_bytes": (_SZ, [_V, _I64]),
+    "md_step_vjp": (_I, [_V, _V, _V, _D, _I64, _V, _V, _V, _SZ]),
     "md_destroy": (_I, [_V]),
     "md_strerror": (ctypes.c_char_p, [_I]),
     "md_last_error": (ctypes.c_char_p, [_V]),
@@ -240,6 +243,30 @@ def md_magnetization(ctx: Context, q: torch.Tensor, out: Optional[torch.Tensor] 
         out = torch.empty(2, dtype=torch.float64, device=q.device)
     ctx._check(load().md_magnetization(ctx.handle, ctx._arr(q, "q"), out.data_ptr()), "md_magnetization")
     return out
+
+
+def md_hvp(ctx: Context, q: torch.Tensor, w: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """out = H(q) w, H the Hessian of the potential."""
+    if out is None:
+        out = torch.empty_like(q)
+    ctx._check(load().md_hvp(ctx.handle, ctx._arr(q, "q"), ctx._arr(w, "w"), ctx._arr(out, "out")), "md_hvp")
+    return out
+
+
+def md_vjp_stage_bytes(ctx: Context, nsteps: int) -> int:
+    return int(load().md_vjp_stage_bytes(ctx.handle, int(nsteps)))
+
+
+def md_step_vjp(ctx: Context, q0: torch.Tensor, p0: torch.Tensor, dt: float, nsteps: int, lam_q: torch.Tensor,
+                lam_p: torch.Tensor, stage: Optional[torch.Tensor] = None) -> None:
+    """In place: (lam_q, lam_p) at the end of nsteps steps from (q0, p0) become the
+    adjoints at (q0, p0).  stage: device scratch (allocated here if None)."""
+    need = md_vjp_stage_bytes(ctx, nsteps)
+    if stage is None:
+        stage = torch.empty(max(need, 8), dtype=torch.uint8, device=q0.device)
+    ctx._check(load().md_step_vjp(ctx.handle, ctx._arr(q0, "q0"), ctx._arr(p0, "p0"), float(dt), int(nsteps),
+                                  ctx._arr(lam_q, "lam_q"), ctx._arr(lam_p, "lam_p"), stage.data_ptr(),
+                                  stage.numel() * stage.element_size()), "md_step_vjp")
 
 
 def md_destroy(ctx: Context) -> None:

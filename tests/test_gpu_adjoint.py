@@ -1,0 +1,148 @@
+"""GPU parity of the derivatives: Hessian-vector products (md_hvp) and the reverse
+sweep of the integrator (md_step_vjp) against the FP64 oracle, and the gradient of
+the final kinetic energy (autograd.kinetic_energy_gradient) against central finite
+differences of the GPU's own FP64 forward map.
+
+Tolerances (max-norm relative to the largest oracle value):
+  * FP64 products: 1e-10 -- only the summation order and the refined reciprocal
+    differ from the oracle; the Hessian terms cancel more than the force terms.
+  * Mixed 2D products: 1e-4 -- FP32 positions move dx by up to 6e-8, i.e. up to
+    2e-6 relative for the closest pairs (|r| ~ sqrt(eps)), amplified by the
+    1/s^2 term; the vector w is rounded to FP32 as well.
+  * Mixed Ring products: 1e-3 -- the FP32 cancellation in 1 + eps - cos(ti - tj)
+    (1.2e-7 absolute against u >= eps = 0.01) enters as u^{-5/2}.
+  * FP64 reverse sweeps: 1e-9 (10 steps of products and axpys).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_0262_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+md = pytest.importorskip("paper_1212_0262_amd.md")
+from paper_1212_0262_amd import autograd as mdgrad  # noqa: E402
+from gpu_helpers import dev, host, rel_inf  # noqa: E402
+
+RING, GRAV2D = md.RING, md.GRAV2D
+HVP_TOL = {(GRAV2D, md.FP64): 1e-10, (RING, md.FP64): 1e-10, (GRAV2D, md.MIXED): 1e-4, (RING, md.MIXED): 1e-3,
+           (GRAV2D, md.MIXED_KAHAN): 1e-4, (RING, md.MIXED_KAHAN): 1e-3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_threads():
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def _state(model, n, seed):
+    return inputs.grav2d_disk(n, seed=seed) if model == GRAV2D else inputs.ring_waterbag(n, seed=seed)
+
+
+@pytest.mark.parametrize("n", [1, 2, 65, 257, 1000, 3001])
+@pytest.mark.parametrize("prec", [md.FP64, md.MIXED, md.MIXED_KAHAN])
+@pytest.mark.parametrize("model,eps", [(GRAV2D, 1e-3), (RING, 0.01)])
+def test_hvp_matches_oracle(model, eps, prec, n):
+    q, _ = _state(model, n, seed=60 + n)
+    w = np.random.default_rng(n).normal(size=q.shape)
+    ho = oracle.hvp(model, q, w, eps)
+    ctx = md.md_init(model, prec, n, eps)
+    hg = host(md.md_hvp(ctx, dev(q), dev(w)))
+    if n == 1:
+        assert np.all(hg == 0.0)
+        return
+    err = rel_inf(hg, ho)
+    print(f"hvp model={model} prec={prec} n={n} rel_err={err:.3e}")
+    assert err < HVP_TOL[(model, prec)], err
+
+
+@pytest.mark.parametrize("model,eps,dt", [(GRAV2D, 1e-3, 0.01), (RING, 0.01, 0.05)])
+def test_step_vjp_matches_oracle(model, eps, dt):
+    n, nst = 300, 10
+    q0, p0 = _state(model, n, seed=61)
+    rng = np.random.default_rng(7)
+    lq0, lp0 = rng.normal(size=q0.shape), rng.normal(size=p0.shape)
+    oq, op = oracle.step_vjp(model, q0, p0, dt, nst, lq0, lp0, eps)
+    ctx = md.md_init(model, md.FP64, n, eps)
+    lq, lp = dev(lq0), dev(lp0)
+    md.md_step_vjp(ctx, dev(q0), dev(p0), dt, nst, lq, lp)
+    eq, ep = rel_inf(host(lq), oq), rel_inf(host(lp), op)
+    print(f"vjp model={model} rel_err q={eq:.3e} p={ep:.3e}")
+    assert eq < 1e-9 and ep < 1e-9
+
+
+def test_step_vjp_mixed_close_to_oracle():
+    """Mixed 2D: the adjoint of the FP32-pair map is within 1e-3 (relative) of the
+    FP64 oracle's after 10 steps."""
+    n, nst, eps, dt = 300, 10, 1e-3, 0.01
+    q0, p0 = _state(GRAV2D, n, seed=62)
+    rng = np.random.default_rng(8)
+    lq0, lp0 = rng.normal(size=q0.shape), rng.normal(size=p0.shape)
+    oq, op = oracle.step_vjp(GRAV2D, q0, p0, dt, nst, lq0, lp0, eps)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, eps)
+    lq, lp = dev(lq0), dev(lp0)
+    md.md_step_vjp(ctx, dev(q0), dev(p0), dt, nst, lq, lp)
+    assert rel_inf(host(lq), oq) < 1e-3 and rel_inf(host(lp), op) < 1e-3
+
+
+def test_step_vjp_composes_over_segments():
+    """Checkpointed segments: 9 steps at once == 5 then 4, bit for bit."""
+    n, eps, dt = 500, 1e-3, 0.01
+    q0, p0 = _state(GRAV2D, n, seed=63)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, eps)
+    qd, pd = dev(q0), dev(p0)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    q4, p4, f4 = qd.clone(), pd.clone(), f.clone()
+    md.md_step(ctx, q4, p4, f4, dt, 4)
+    rng = np.random.default_rng(9)
+    l0q, l0p = rng.normal(size=q0.shape), rng.normal(size=p0.shape)
+    aq, ap = dev(l0q), dev(l0p)
+    md.md_step_vjp(ctx, qd, pd, dt, 9, aq, ap)
+    bq, bp = dev(l0q), dev(l0p)
+    md.md_step_vjp(ctx, q4, p4, dt, 5, bq, bp)
+    md.md_step_vjp(ctx, qd, pd, dt, 4, bq, bp)
+    np.testing.assert_array_equal(host(aq), host(bq))
+    np.testing.assert_array_equal(host(ap), host(bp))
+
+
+def test_step_vjp_rejects_small_stage_buffer():
+    ctx = md.md_init(GRAV2D, md.FP64, 100, 1e-3)
+    q = torch.zeros((2, 100), dtype=torch.float64, device="cuda")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(md.MDError):
+        md.md_step_vjp(ctx, q, q.clone(), 0.01, 3, q.clone(), q.clone(), small)
+    hmf = md.md_init(md.HMF, md.FP64, 100, 0.0)
+    with pytest.raises(md.MDError):
+        md.md_hvp(hmf, q[:1].contiguous(), q[:1].contiguous())
+
+
+@pytest.mark.parametrize("model,eps,dt", [(GRAV2D, 1e-2, 0.01), (RING, 0.02, 0.02)])
+def test_kinetic_energy_gradient_matches_finite_differences(model, eps, dt):
+    """d K_T / d(q0, p0) through the autograd Function (checkpoints every 7 steps)
+    against central differences of the FP64 forward map along 4 random directions."""
+    n, nst = 256, 30
+    q0, p0 = _state(model, n, seed=64)
+    ctx = md.md_init(model, md.FP64, n, eps)
+    K, gq, gp = mdgrad.kinetic_energy_gradient(ctx, dev(q0), dev(p0), dt, nst, checkpoint_every=7)
+
+    def J(q, p):
+        qd, pd = dev(q), dev(p)
+        f = torch.empty_like(qd)
+        md.md_force(ctx, qd, f)
+        md.md_step(ctx, qd, pd, f, dt, nst)
+        return 0.5 * float((pd * pd).sum())
+    assert abs(J(q0, p0) - float(K)) <= 1e-14 * abs(float(K))
+    rng = np.random.default_rng(10)
+    gq, gp = host(gq), host(gp)
+    for _ in range(4):
+        vq, vp = rng.normal(size=q0.shape), rng.normal(size=p0.shape)
+        h = 1e-6
+        fd = (J(q0 + h * vq, p0 + h * vp) - J(q0 - h * vq, p0 - h * vp)) / (2 * h)
+        ad = float(np.sum(gq * vq) + np.sum(gp * vp))
+        print(f"grad model={model} ad={ad:.12e} fd={fd:.12e}")
+        assert abs(ad - fd) < 1e-6 * max(1.0, abs(fd)), (ad, fd)
