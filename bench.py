@@ -177,7 +177,26 @@ def ring_workload(md, torch, args):
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
         e1 = md.md_energy(ctx, q, p).cpu().numpy()
-        res[name] = {"ms": ms, "us_per_step": 1e3 * ms / args.steps,
+        # the same steps captured as one HIP graph (launch-bound at this N)
+        qg, pg, fg = qw.clone(), pw.clone(), fw.clone()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        md.md_set_stream(ctx, s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            md.md_step(ctx, qg, pg, fg, RING_DT, args.steps)
+        md.md_set_stream(ctx, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ev0.record()
+        g.replay()
+        ev1.record()
+        torch.cuda.synchronize()
+        graph_ms = ev0.elapsed_time(ev1)
+        res_graph = {"graph_us_per_step": 1e3 * graph_ms / args.steps,
+                     "graph_gpairs_per_s": 3.0 * RING_N ** 2 * args.steps / (graph_ms * 1e-3) / 1e9}
+        res[name] = {"ms": ms, "us_per_step": 1e3 * ms / args.steps, **res_graph,
                      "gpairs_per_s": 3.0 * RING_N ** 2 * args.steps / (ms * 1e-3) / 1e9,
                      "dE_E": float(abs(e1[2] - e0[2]) / abs(e0[2])), "tiles": list(md.md_get_tiles(ctx))}
         ctx.close()
