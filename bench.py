@@ -45,7 +45,7 @@ FLOPS_PER_PAIR = 10          # 2 sub, 2 FMA (r^2 + eps), 2 FMA (accumulate); plu
 PEAK_FP32_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32 (packed FP32 is not used)
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
-PAIR_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("pair.hip", "device.h")]
+PAIR_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("pair.hip", "pair_terms.h", "device.h")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "grav2d_pair_mixed_n262144_pmc.txt")
 
 
