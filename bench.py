@@ -196,7 +196,19 @@ def ring_workload(md, torch, args):
         graph_ms = ev0.elapsed_time(ev1)
         res_graph = {"graph_us_per_step": 1e3 * graph_ms / args.steps,
                      "graph_gpairs_per_s": 3.0 * RING_N ** 2 * args.steps / (graph_ms * 1e-3) / 1e9}
-        res[name] = {"ms": ms, "us_per_step": 1e3 * ms / args.steps, **res_graph,
+        form = "fused" if md.md_get_launch(ctx) == md.LAUNCH_FUSED else "staged"
+        # the other launch form on the same tiles (pair kernel + update kernel per force)
+        md.md_set_launch(ctx, md.LAUNCH_STAGED)
+        qs, ps, fs = qw.clone(), pw.clone(), fw.clone()
+        md.md_step(ctx, qs, ps, fs, RING_DT, 2)
+        torch.cuda.synchronize()
+        ev0.record()
+        md.md_step(ctx, qs, ps, fs, RING_DT, args.steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        staged_ms = ev0.elapsed_time(ev1)
+        res[name] = {"ms": ms, "us_per_step": 1e3 * ms / args.steps, **res_graph, "launch": form,
+                     "staged_us_per_step": 1e3 * staged_ms / args.steps,
                      "gpairs_per_s": 3.0 * RING_N ** 2 * args.steps / (ms * 1e-3) / 1e9,
                      "dE_E": float(abs(e1[2] - e0[2]) / abs(e0[2])), "tiles": list(md.md_get_tiles(ctx))}
         ctx.close()

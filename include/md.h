@@ -163,6 +163,29 @@ int md_get_tiles(const md_ctx *c, int *out4);
 int md_max_j_split(int64_t n);
 
 /*
+ * Launch form of md_step for single Ring and 2D systems (eq. 4's stages):
+ *   MD_LAUNCH_STAGED  two launches per force evaluation: the pair kernel over
+ *                     (i block, j range) tiles, then an elementwise kernel that
+ *                     adds the j-range partials and kicks, drifts and refreshes
+ *                     the pair operands;
+ *   MD_LAUNCH_FUSED   one launch per force evaluation (small N, where launch
+ *                     latency dominates): a block owns one i tile, its j_split
+ *                     wavefronts take the j ranges, the partials are added in LDS
+ *                     and the same block runs the stage on its own particles.
+ *                     The j ranges, folds and order of additions are the staged
+ *                     ones, so both forms give bit-identical results for the same
+ *                     tiles.  Needs n <= 65536, j_split <= 16 and
+ *                     j_split * i_per_lane * d <= 64 (MD_EUNSUPPORTED otherwise;
+ *                     md_set_tiles then refuses tiles outside that range);
+ *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 16384.
+ * md_get_launch returns the form md_step will take (STAGED or FUSED), or a
+ * negative status.  HMF and batch contexts are always STAGED.
+ */
+enum md_launch { MD_LAUNCH_AUTO = 0, MD_LAUNCH_STAGED = 1, MD_LAUNCH_FUSED = 2 };
+int md_set_launch(md_ctx *c, int mode);
+int md_get_launch(const md_ctx *c);
+
+/*
  * f = -dV/dq at positions q (eqs. 6-9 and the 2D gradient of eq. 3).
  * q: device [d][n] FP64, read only.  f: device [d][n] FP64, written.
  * For MD_HMF this also caches the magnetization of q in the workspace.
@@ -193,12 +216,15 @@ int md_energy(md_ctx *c, const double *q, const double *p, double *out_dev3);
 int md_magnetization(md_ctx *c, const double *q, double *out_dev2);
 
 /*
- * Derivatives (single MD_RING or MD_GRAV2D contexts; others MD_EUNSUPPORTED).
- * They differentiate the same discrete map md_step computes (eq. 4 with the
- * forces of eqs. 1 and 3), in the context's precision.
+ * Derivatives (single-system contexts; batched ones MD_EUNSUPPORTED).  They
+ * differentiate the same discrete map md_step computes (eq. 4 with the forces of
+ * eqs. 1-3), in the context's precision.  HMF md_step_vjp needs an MD_FP64
+ * context (MD_EUNSUPPORTED otherwise); HMF md_hvp runs in FP64 for either.
  *
  * md_hvp: out = H(q) w, H the Hessian of the potential V (the force is -grad V, so
- * its Jacobian is -H).  q, w, out: device [d][n] FP64.
+ * its Jacobian is -H).  q, w, out: device [d][n] FP64.  HMF uses the mean-field
+ * form of eqs. 6 and 7: (H w)_i = w_i (cos q_i Mx + sin q_i My) - cos q_i Cw
+ * - sin q_i Sw with Cw, Sw the averages of cos q_j w_j and sin q_j w_j, O(N).
  *
  * md_step_vjp: reverse-mode derivative of nsteps Yoshida steps started from the
  * state (q0, p0) (e.g. a checkpoint kept during the forward run).  On entry
@@ -208,7 +234,9 @@ int md_magnetization(md_ctx *c, const double *q, double *out_dev2);
  * the force is kept in `stage`; kicks and drifts are then undone in reverse:
  * a drift q += a p by lam_p += a lam_q, a kick p += h F(q) by lam_q -= h H(q) lam_p.
  * stage: caller device scratch of at least md_vjp_stage_bytes(c, nsteps) bytes
- * (3 nsteps + 3 arrays of [d][n] FP64).  nsteps = 0 is a no-op.
+ * (3 nsteps + 3 slots, each [d][n] FP64 rounded up to an even count of doubles);
+ * 8-byte aligned at least.  With stage, q0, p0 16-byte aligned the recomputed
+ * trajectory is bit-identical to md_step's.  nsteps = 0 is a no-op.
  */
 int md_hvp(md_ctx *c, const double *q, const double *w, double *out);
 size_t md_vjp_stage_bytes(const md_ctx *c, int64_t nsteps);

@@ -72,3 +72,20 @@ def kinetic_energy_gradient(ctx: md.Context, q0: torch.Tensor, p0: torch.Tensor,
     K = 0.5 * (pT * pT).sum()
     K.backward()
     return K.detach(), q0.grad, p0.grad
+
+
+def magnetization_gradient(ctx: md.Context, q0: torch.Tensor, p0: torch.Tensor, dt: float, nsteps: int,
+                           checkpoint_every: int = 50):
+    """(M_T, dM_T/dq0, dM_T/dp0) for the final magnetization modulus
+    M_T = |(1/N) sum_i (cos q_i, sin q_i)| of an angle model (HMF eq. 7; also the
+    order parameter of the Ring model).  Only the observable is differentiated by
+    torch; the trajectory's derivative is md_step_vjp."""
+    if q0.shape[0] != 1:
+        raise ValueError("magnetization_gradient: angle models (HMF, Ring) only")
+    q0 = q0.detach().clone().requires_grad_(True)
+    p0 = p0.detach().clone().requires_grad_(True)
+    qT, _ = trajectory(ctx, q0, p0, dt, nsteps, checkpoint_every)
+    M = torch.sqrt(torch.cos(qT).mean() ** 2 + torch.sin(qT).mean() ** 2)
+    M.backward()
+    return M.detach(), q0.grad, p0.grad
+

@@ -44,7 +44,7 @@ bool prec_ok(int model, int prec)
 bool model_ok(int model) { return model == MD_HMF || model == MD_RING || model == MD_GRAV2D; }
 
 struct Layout {
-    size_t red, scal, ops, wops, part, th32, p32, total;
+    size_t red, scal, ops, wops, part, th32, p32, fops0, fops1, total;
 };
 
 Layout layout(int model, int prec, int64_t n)
@@ -67,6 +67,11 @@ Layout layout(int model, int prec, int64_t n)
     if (model == MD_HMF && prec == MD_MIXED_F32STATE) off = align_up(off + npad * sizeof(float));
     L.p32 = off;
     if (model == MD_HMF && prec == MD_MIXED_F32STATE) off = align_up(off + npad * sizeof(float));
+    const bool fused = model != MD_HMF && n <= kFusedMaxN;
+    L.fops0 = off;
+    if (fused) off = align_up(off + 2 * npad * sizeof(double));
+    L.fops1 = off;
+    if (fused) off = align_up(off + 2 * npad * sizeof(double));
     L.total = off;
     return L;
 }
@@ -129,7 +134,7 @@ void yoshida(double *b0, double *b1, double *d0, double *d1)
 hipError_t pair_(md_ctx *c, const double *q) { return c->batch ? batch_pair(c, q) : launch_pair(c, q); }
 
 // snap (single systems only): the positions after every drift are also written to
-// consecutive [d][n] slots of snap.
+// consecutive [d][n] slots of snap, snap_stride doubles apart.
 hipError_t update_(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p, double *f,
                    double *snap = nullptr)
 {
@@ -137,14 +142,54 @@ hipError_t update_(md_ctx *c, int flags, double kick1, double kick2, double drif
                     : launch_update(c, flags, kick1, kick2, drift, q, p, f, snap);
 }
 
-int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps, double *snap = nullptr)
+// The fused stage applies: single system with its operand buffers, and tiles
+// whose j ranges fit one block's wavefronts and LDS.
+bool fused_ok(const md_ctx *c, const Tiles &t)
+{
+    return !c->batch && c->model != MD_HMF && c->fops[0] && t.jsplit <= kFusedMaxSplit &&
+           t.jsplit * t.ipl * dims(c->model) <= kFusedMaxLds;
+}
+
+// md_step's launch form for this context: MD_LAUNCH_STAGED or MD_LAUNCH_FUSED.
+int launch_form(const md_ctx *c)
+{
+    if (c->launch == MD_LAUNCH_STAGED || !fused_ok(c, c->tiles)) return MD_LAUNCH_STAGED;
+    if (c->launch == MD_LAUNCH_FUSED || c->n <= kFusedAutoN) return MD_LAUNCH_FUSED;
+    return MD_LAUNCH_STAGED;
+}
+
+int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps, double *snap = nullptr,
+               size_t snap_stride = 0)
 {
     double B0, B1, D0, D1;
     yoshida(&B0, &B1, &D0, &D1);
     const int stage = UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1 | UPD_DRIFT | UPD_PREP;
-    const size_t len = (size_t)dims(c->model) * c->n;
     int64_t slot = 0;
-    auto next = [&]() { return snap ? snap + (size_t)(slot++) * len : nullptr; };
+    auto next = [&]() { return snap ? snap + (size_t)(slot++) * snap_stride : nullptr; };
+    if (launch_form(c) == MD_LAUNCH_FUSED) {
+        // the same stage sequence as below, pair kernel and update in one launch;
+        // the operand buffers alternate
+        void *const buf[2] = {c->fops[0], c->fops[1]};
+        int cur = 0;
+        auto fused = [&](int flags, double k1, double k2, double dr, double *sn) {
+            hipError_t e = launch_fused(c, flags, k1, k2, dr, q, p, f, buf[cur], buf[cur ^ 1], sn);
+            cur ^= 1;
+            return e;
+        };
+        MD_TRY(launch_update_fused(c, UPD_KICK1 | UPD_DRIFT | UPD_PREP, B0 * dt, 0.0, D0 * dt, q, p, f, buf[0],
+                                   next()),
+               "step: first kick");
+        for (int64_t s = 0; s < nsteps; ++s) {
+            MD_TRY(fused(stage, B1 * dt, 0.0, D1 * dt, next()), "step: fused stage");
+            MD_TRY(fused(stage, B1 * dt, 0.0, D0 * dt, next()), "step: fused stage");
+            if (s + 1 < nsteps)
+                MD_TRY(fused(stage | UPD_KICK2, B0 * dt, B0 * dt, D0 * dt, next()), "step: fused stage");
+            else
+                MD_TRY(fused(UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1, B0 * dt, 0.0, 0.0, nullptr),
+                       "step: last kick");
+        }
+        return MD_OK;
+    }
     MD_TRY(update_(c, UPD_KICK1 | UPD_DRIFT | UPD_PREP, B0 * dt, 0.0, D0 * dt, q, p, f, next()), "step: first kick");
     for (int64_t s = 0; s < nsteps; ++s) {
         MD_TRY(pair_(c, q), "step: pair kernel");
@@ -161,24 +206,29 @@ int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t ns
     return MD_OK;
 }
 
+// Doubles per stage slot: d n rounded up to even, so a 16-byte aligned stage keeps
+// every slot 16-byte aligned (the HMF pass then uses the same vector width, hence
+// the same reduction order, as md_step on aligned arrays).
+size_t vjp_slot(const md_ctx *c) { return ((size_t)dims(c->model) * (size_t)c->n + 1) & ~(size_t)1; }
+
 // Reverse sweep of nsteps steps (see md_step_vjp).  stage = [q | p | f | P_1 .. P_3n],
-// each [d][n]; P_m are the positions at which the kicks evaluate the force
-// (P_0 = q0).
+// each a slot holding [d][n]; P_m are the positions at which the kicks evaluate the
+// force (P_0 = q0).
 int step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps, double *lq, double *lp,
              double *stage)
 {
     double B0, B1, D0, D1;
     yoshida(&B0, &B1, &D0, &D1);
-    const size_t len = (size_t)dims(c->model) * c->n;
-    double *qw = stage, *pw = stage + len, *fw = stage + 2 * len, *P = stage + 3 * len;
-    auto pos = [&](int64_t m) -> const double * { return m == 0 ? q0 : P + (size_t)(m - 1) * len; };
+    const size_t len = (size_t)dims(c->model) * c->n, slot = vjp_slot(c);
+    double *qw = stage, *pw = stage + slot, *fw = stage + 2 * slot, *P = stage + 3 * slot;
+    auto pos = [&](int64_t m) -> const double * { return m == 0 ? q0 : P + (size_t)(m - 1) * slot; };
     MD_TRY(hipMemcpyAsync(qw, q0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy q");
     MD_TRY(hipMemcpyAsync(pw, p0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy p");
     // forward recompute, keeping the kick positions
     MD_TRY(update_(c, UPD_PREP, 0.0, 0.0, 0.0, qw, nullptr, nullptr), "vjp: operands");
     MD_TRY(pair_(c, qw), "vjp: pair kernel");
     MD_TRY(update_(c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, fw), "vjp: force");
-    int st = step_pairs(c, qw, pw, fw, dt, nsteps, P);
+    int st = step_pairs(c, qw, pw, fw, dt, nsteps, P, slot);
     if (st != MD_OK) return st;
     // reverse: pending product at P_3n, kick weight B0 dt
     const int prep = ADJ_PREPQ | ADJ_PREPW;
@@ -205,21 +255,27 @@ int step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t n
     return MD_OK;
 }
 
-int step_hmf(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps)
+// snap (FP64 state only): the angles after every drift are also written to
+// consecutive slots of snap, snap_stride doubles apart.
+int step_hmf(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps, double *snap = nullptr,
+             size_t snap_stride = 0)
 {
     double B0, B1, D0, D1;
     yoshida(&B0, &B1, &D0, &D1);
     const bool f32 = c->prec == MD_MIXED_F32STATE;
     const int stage = HMF_KICK_M | HMF_DRIFT | HMF_WRITE | HMF_REDUCE;
+    int64_t slot = 0;
+    auto next = [&]() { return snap ? snap + (size_t)(slot++) * snap_stride : nullptr; };
     if (f32) MD_TRY(launch_hmf_convert(c, q, p, true), "step: convert in");
     MD_TRY(launch_hmf_pass(c, HMF_KICK_F | HMF_DRIFT | HMF_WRITE | HMF_REDUCE, B0 * dt, 0.0, D0 * dt, q, p, f,
-                           nullptr, f32),
+                           nullptr, f32, next()),
            "step: first pass");
     for (int64_t s = 0; s < nsteps; ++s) {
-        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D1 * dt, q, p, nullptr, nullptr, f32), "step: pass");
-        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32), "step: pass");
+        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D1 * dt, q, p, nullptr, nullptr, f32, next()), "step: pass");
+        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32, next()), "step: pass");
         if (s + 1 < nsteps)
-            MD_TRY(launch_hmf_pass(c, stage | HMF_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, nullptr, nullptr, f32),
+            MD_TRY(launch_hmf_pass(c, stage | HMF_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, nullptr, nullptr, f32,
+                                   next()),
                    "step: pass");
         else
             MD_TRY(launch_hmf_pass(c, HMF_KICK_M | HMF_STORE_F | HMF_WRITE, B0 * dt, 0.0, 0.0, q, p, nullptr, f,
@@ -227,6 +283,41 @@ int step_hmf(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nste
                    "step: last pass");
     }
     if (f32) MD_TRY(launch_hmf_convert(c, q, p, false), "step: convert out");
+    return MD_OK;
+}
+
+// HMF reverse sweep: as step_vjp, with the O(N) product -- per kick one pass of
+// sums over (P_m, lambda_p) and one elementwise pass that applies the kick and the
+// preceding drift.  stage = [q | p | f | P_1 .. P_3n], one slot each.
+int step_vjp_hmf(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps, double *lq, double *lp,
+                 double *stage)
+{
+    double B0, B1, D0, D1;
+    yoshida(&B0, &B1, &D0, &D1);
+    const size_t len = (size_t)c->n, slot = vjp_slot(c);
+    double *qw = stage, *pw = stage + slot, *fw = stage + 2 * slot, *P = stage + 3 * slot;
+    auto pos = [&](int64_t m) -> const double * { return m == 0 ? q0 : P + (size_t)(m - 1) * slot; };
+    MD_TRY(hipMemcpyAsync(qw, q0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy q");
+    MD_TRY(hipMemcpyAsync(pw, p0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy p");
+    MD_TRY(launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, qw, nullptr, nullptr, nullptr, false), "vjp: reduce");
+    MD_TRY(launch_hmf_pass(c, HMF_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, nullptr, fw, false), "vjp: force");
+    int st = step_hmf(c, qw, pw, fw, dt, nsteps, P, slot);
+    if (st != MD_OK) return st;
+    MD_TRY(launch_hmf_hvp_sums(c, pos(3 * nsteps), lp), "vjp: sums");
+    int kick = ADJ_KICK;
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 3), kick | ADJ_DRIFT, B0 * dt, B0 * dt, D0 * dt, lq, lp, nullptr),
+               "vjp: update");
+        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s + 2), lp), "vjp: sums");
+        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 2), ADJ_KICK | ADJ_DRIFT, B1 * dt, 0.0, D1 * dt, lq, lp, nullptr),
+               "vjp: update");
+        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s + 1), lp), "vjp: sums");
+        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 1), ADJ_KICK | ADJ_DRIFT, B1 * dt, 0.0, D0 * dt, lq, lp, nullptr),
+               "vjp: update");
+        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s), lp), "vjp: sums");
+        kick = s > 0 ? (ADJ_KICK | ADJ_KICK2) : ADJ_KICK;
+    }
+    MD_TRY(launch_hmf_adj_update(c, q0, kick, B0 * dt, B0 * dt, 0.0, lq, lp, nullptr), "vjp: last kick");
     return MD_OK;
 }
 
@@ -419,6 +510,8 @@ Tiles default_tiles(int model, int prec, int64_t n)
     if (s > cap) s = cap;
     int64_t p2 = 1;
     while (p2 * 2 <= s) p2 *= 2;
+    // up to the automatic fused-launch size the j ranges are one block's wavefronts
+    if (n <= kFusedAutoN && p2 > kFusedMaxSplit) p2 = kFusedMaxSplit;
     t.jsplit = (int)p2;
     return t;
 }
@@ -466,7 +559,11 @@ int md_init(md_ctx **out, int model, int prec, int64_t n, double eps, void *hip_
     c->wops = (L.part > L.wops) ? reinterpret_cast<float *>(c->ws + L.wops) : nullptr;
     c->part = (L.th32 > L.part) ? reinterpret_cast<double *>(c->ws + L.part) : nullptr;
     c->th32 = (L.p32 > L.th32) ? reinterpret_cast<float *>(c->ws + L.th32) : nullptr;
-    c->p32 = (L.total > L.p32) ? reinterpret_cast<float *>(c->ws + L.p32) : nullptr;
+    c->p32 = (L.fops0 > L.p32) ? reinterpret_cast<float *>(c->ws + L.p32) : nullptr;
+    if (L.total > L.fops0) {
+        c->fops[0] = c->ws + L.fops0;
+        c->fops[1] = c->ws + L.fops1;
+    }
     c->tiles = default_tiles(model, prec, n);
     hipError_t e = hipGetDevice(&c->dev);
     if (e != hipSuccess) {
@@ -580,6 +677,9 @@ int md_set_tiles(md_ctx *c, int i_per_lane, int waves, int j_split, int j_tile)
         return fail(c, MD_EINVAL, "j_split must be in [1, %d] (got %d)", smax, t.jsplit);
     if (t.jtile < 16 || t.jtile > 4096 || t.jtile % 16)
         return fail(c, MD_EINVAL, "j_tile must be a multiple of 16 in [16, 4096] (got %d)", t.jtile);
+    if (c->launch == MD_LAUNCH_FUSED && !fused_ok(c, t))
+        return fail(c, MD_EUNSUPPORTED, "the fused launch needs j_split <= %d and j_split * i_per_lane * d <= %d",
+                    kFusedMaxSplit, kFusedMaxLds);
     c->tiles = t;
     if (c->batch) {
         build_lists(*c->batch, t);
@@ -588,6 +688,28 @@ int md_set_tiles(md_ctx *c, int i_per_lane, int waves, int j_split, int j_tile)
         MD_TRY(upload_lists(c), "md_set_tiles: upload work lists");
     }
     return MD_OK;
+}
+
+int md_set_launch(md_ctx *c, int mode)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (mode != MD_LAUNCH_AUTO && mode != MD_LAUNCH_STAGED && mode != MD_LAUNCH_FUSED)
+        return fail(c, MD_EINVAL, "md_set_launch: unknown mode %d", mode);
+    if (mode == MD_LAUNCH_FUSED && !fused_ok(c, c->tiles))
+        return fail(c, MD_EUNSUPPORTED,
+                    "md_set_launch: the fused launch needs a single Ring or 2D system with n <= %lld, j_split <= %d "
+                    "and j_split * i_per_lane * d <= %d",
+                    (long long)kFusedMaxN, kFusedMaxSplit, kFusedMaxLds);
+    c->launch = mode;
+    return MD_OK;
+}
+
+int md_get_launch(const md_ctx *c)
+{
+    if (!c) return MD_EINVAL;
+    if (c->model == MD_HMF) return MD_LAUNCH_STAGED;
+    return launch_form(c);
 }
 
 int md_get_tiles(const md_ctx *c, int *out4)
@@ -662,12 +784,17 @@ int md_hvp(md_ctx *c, const double *q, const double *w, double *out)
 {
     if (!c) return MD_EINVAL;
     c->err.clear();
-    if (c->model == MD_HMF || c->batch) return fail(c, MD_EUNSUPPORTED, "md_hvp: Ring and 2D single systems only");
+    if (c->batch) return fail(c, MD_EUNSUPPORTED, "md_hvp: single systems only");
     if (!q || !w || !out || !aligned8(q) || !aligned8(w) || !aligned8(out))
         return fail(c, MD_EINVAL, "md_hvp: null or misaligned pointer");
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_hvp: set device");
     double *wm = const_cast<double *>(w);
+    if (c->model == MD_HMF) {
+        MD_TRY(launch_hmf_hvp_sums(c, q, w), "hvp: sums");
+        MD_TRY(launch_hmf_adj_update(c, q, ADJ_OUT, 0.0, 0.0, 0.0, nullptr, wm, out), "hvp: product");
+        return MD_OK;
+    }
     MD_TRY(launch_adj_update(c, ADJ_PREPQ | ADJ_PREPW, 0.0, 0.0, 0.0, nullptr, wm, nullptr, q), "hvp: operands");
     MD_TRY(launch_hvp_pair(c, q, w), "hvp: pair kernel");
     MD_TRY(launch_adj_update(c, ADJ_OUT, 0.0, 0.0, 0.0, nullptr, nullptr, out, nullptr), "hvp: combine");
@@ -677,7 +804,7 @@ int md_hvp(md_ctx *c, const double *q, const double *w, double *out)
 size_t md_vjp_stage_bytes(const md_ctx *c, int64_t nsteps)
 {
     if (!c || nsteps < 0) return 0;
-    return (size_t)(3 * nsteps + 3) * dims(c->model) * (size_t)c->n * sizeof(double);
+    return (size_t)(3 * nsteps + 3) * vjp_slot(c) * sizeof(double);
 }
 
 int md_step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps, double *lam_q,
@@ -685,8 +812,9 @@ int md_step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_
 {
     if (!c) return MD_EINVAL;
     c->err.clear();
-    if (c->model == MD_HMF || c->batch)
-        return fail(c, MD_EUNSUPPORTED, "md_step_vjp: Ring and 2D single systems only");
+    if (c->batch) return fail(c, MD_EUNSUPPORTED, "md_step_vjp: single systems only");
+    if (c->model == MD_HMF && c->prec != MD_FP64)
+        return fail(c, MD_EUNSUPPORTED, "md_step_vjp: HMF needs an FP64-state context");
     if (!q0 || !p0 || !lam_q || !lam_p || !stage || !aligned8(q0) || !aligned8(p0) || !aligned8(lam_q) ||
         !aligned8(lam_p) || !aligned8(stage))
         return fail(c, MD_EINVAL, "md_step_vjp: null or misaligned pointer");
@@ -697,7 +825,8 @@ int md_step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_
     if (nsteps == 0) return MD_OK;
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_step_vjp: set device");
-    return step_vjp(c, q0, p0, dt, nsteps, lam_q, lam_p, stage);
+    return c->model == MD_HMF ? step_vjp_hmf(c, q0, p0, dt, nsteps, lam_q, lam_p, stage)
+                              : step_vjp(c, q0, p0, dt, nsteps, lam_q, lam_p, stage);
 }
 
 int md_destroy(md_ctx *c)

@@ -89,7 +89,7 @@ template <typename T, int W>
 __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restrict__ p,
                                                   const double *__restrict__ f_in, double *__restrict__ f_out,
                                                   const double *__restrict__ M, PassArgs a, int n,
-                                                  double *__restrict__ red)
+                                                  double *__restrict__ red, T *__restrict__ snap)
 {
     __shared__ double lds[2][4];
     const int flags = a.flags;
@@ -135,6 +135,10 @@ __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restr
                 reinterpret_cast<VT *>(th)[v] = t[u];
                 if (need_p) reinterpret_cast<VT *>(p)[v] = q[u];
             }
+            if (snap && (flags & HMF_DRIFT)) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) snap[v * W + w] = t[u].x[w];
+            }
         }
     }
     // the n mod W particles past the last full vector: block 0
@@ -149,6 +153,7 @@ __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restr
             th[i] = t;
             if (need_p) p[i] = pw;
         }
+        if (snap && (flags & HMF_DRIFT)) snap[i] = t;
     }
     if (flags & HMF_REDUCE) {
         const double bc = block_sum(sc, lds[0]);
@@ -205,6 +210,73 @@ __global__ __launch_bounds__(256) void k_hmf_convert(double *__restrict__ th, do
     }
 }
 
+// ------------------------------------------------------------------- adjoint --
+// HMF Hessian-vector product, O(N): phi''(d) = cos(d)/N gives
+//   (H w)_i = w_i (c_i Mx + s_i My) - (c_i Cw + s_i Sw),
+// Mx, My the magnetization (eq. 7), Cw = (1/N) sum c_j w_j, Sw = (1/N) sum s_j w_j.
+
+// Block partials of sum c, sum s, sum c w, sum s w (grid-stride, fixed grid).
+__global__ __launch_bounds__(256) void k_hmf_hvp_sums(const double *__restrict__ th, const double *__restrict__ w,
+                                                      int n, double *__restrict__ red)
+{
+    __shared__ double lds[4][4];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double s, c;
+        sincos64(th[i], &s, &c);
+        const double wi = w[i];
+        a[0] += c;
+        a[1] += s;
+        a[2] += c * wi;
+        a[3] += s * wi;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double b = block_sum(a[k], lds[k]);
+        if (threadIdx.x == 0) red[4 * blockIdx.x + k] = b;
+    }
+}
+
+// sums[0..3] = (Mx, My, Cw, Sw): the g partial quadruples added in a fixed order.
+__global__ __launch_bounds__(256) void k_hmf_hvp_finalize(const double *__restrict__ red, int g, int n,
+                                                          double *__restrict__ sums)
+{
+    __shared__ double lds[4][4];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < g; b += blockDim.x)
+        for (int k = 0; k < 4; ++k) a[k] += red[4 * b + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double t = block_sum(a[k], lds[k]);
+        if (threadIdx.x == 0) sums[k] = t / (double)n;
+    }
+}
+
+// Elementwise, with the sums of H(th) lp: hw = (H lp)_i; out = hw; lq -= h hw
+// [; lq -= h2 hw]; lp += a lq.  Flags as the pair-model adjoint update.
+__global__ __launch_bounds__(256) void k_hmf_adj_update(const double *__restrict__ th, const double *__restrict__ sums,
+                                                        int flags, double h, double h2, double a, int n,
+                                                        double *__restrict__ lq, double *__restrict__ lp,
+                                                        double *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (flags & (ADJ_OUT | ADJ_KICK)) {
+        double s, c;
+        sincos64(th[i], &s, &c);
+        const double w = lp[i];
+        const double hw = w * (c * sums[0] + s * sums[1]) - (c * sums[2] + s * sums[3]);
+        if (flags & ADJ_OUT) out[i] = hw;
+        if (flags & ADJ_KICK) {
+            double l = lq[i] - h * hw;
+            if (flags & ADJ_KICK2) l -= h2 * hw;
+            lq[i] = l;
+        }
+    }
+    if (flags & ADJ_DRIFT) lp[i] += a * lq[i];
+}
+
 }  // namespace
 
 // Vector width of the accesses for this context (1 when a pointer is not 16-byte aligned).
@@ -225,7 +297,7 @@ int hmf_grid(int64_t n)
 const double *hmf_partials(const md_ctx *c) { return c->red; }
 
 hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, double drift, double *th,
-                           double *p, const double *f_in, double *f_out, bool f32state)
+                           double *p, const double *f_in, double *f_out, bool f32state, double *snap)
 {
     const int n = (int)c->n;
     const int g = hmf_grid(c->n);
@@ -234,18 +306,18 @@ hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, dou
         const int w = vec_width(true, c->th32, c->p32, f_in, f_out);
         if (w == 4)
             hipLaunchKernelGGL((k_hmf_pass<float, 4>), dim3(g), dim3(256), 0, c->stream, c->th32, c->p32, f_in,
-                               f_out, c->scal, a, n, c->red);
+                               f_out, c->scal, a, n, c->red, (float *)nullptr);
         else
             hipLaunchKernelGGL((k_hmf_pass<float, 1>), dim3(g), dim3(256), 0, c->stream, c->th32, c->p32, f_in,
-                               f_out, c->scal, a, n, c->red);
+                               f_out, c->scal, a, n, c->red, (float *)nullptr);
     } else {
-        const int w = vec_width(false, th, p, f_in, f_out);
+        const int w = vec_width(false, th, p, f_in, f_out);  // snap: element stores, any alignment
         if (w == 2)
             hipLaunchKernelGGL((k_hmf_pass<double, 2>), dim3(g), dim3(256), 0, c->stream, th, p, f_in, f_out,
-                               c->scal, a, n, c->red);
+                               c->scal, a, n, c->red, snap);
         else
             hipLaunchKernelGGL((k_hmf_pass<double, 1>), dim3(g), dim3(256), 0, c->stream, th, p, f_in, f_out,
-                               c->scal, a, n, c->red);
+                               c->scal, a, n, c->red, snap);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && (flags & HMF_REDUCE)) {
@@ -266,6 +338,28 @@ hipError_t launch_hmf_convert(md_ctx *c, double *th, double *p, bool to_f32)
     const int n = (int)c->n;
     hipLaunchKernelGGL(k_hmf_convert, dim3((n + 255) / 256), dim3(256), 0, c->stream, th, p, c->th32, c->p32,
                        n, to_f32 ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Sums (Mx, My, Cw, Sw) of H(th) w into the context scalars c->scal[4..7].
+hipError_t launch_hmf_hvp_sums(md_ctx *c, const double *th, const double *w)
+{
+    const int n = (int)c->n;
+    int g = (int)((c->n + 255) / 256);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_hmf_hvp_sums, dim3(g), dim3(256), 0, c->stream, th, w, n, c->red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hmf_hvp_finalize, dim3(1), dim3(256), 0, c->stream, c->red, g, n, c->scal + 4);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmf_adj_update(md_ctx *c, const double *th, int flags, double h, double h2, double a, double *lq,
+                                 double *lp, double *out)
+{
+    const int n = (int)c->n;
+    hipLaunchKernelGGL(k_hmf_adj_update, dim3((n + 255) / 256), dim3(256), 0, c->stream, th, c->scal + 4, flags, h, h2,
+                       a, n, lq, lp, out);
     return hipGetLastError();
 }
 

@@ -39,6 +39,10 @@ constexpr int kMaxJSplit = 64;
 constexpr int kRedSlots = 1 << 16;   // doubles of reduction scratch
 constexpr int kHmfGrid = 16384;      // most blocks of an HMF pass (2 FP64 partials each)
 constexpr int kEnergyBlock = 256;
+constexpr int64_t kFusedMaxN = 65536;   // contexts up to this n carry the fused stage's operand buffers
+constexpr int kFusedMaxSplit = 16;      // wavefronts per fused block (one per j range)
+constexpr int kFusedMaxLds = 64;        // j ranges x i per lane x d (LDS: 512 B each)
+constexpr int64_t kFusedAutoN = 16384;  // MD_LAUNCH_AUTO takes the fused form up to this n
 
 struct Tiles {
     int ipl = 0;     // i per lane
@@ -85,6 +89,8 @@ struct md_ctx {
     double *scal = nullptr;   // small device scalars (HMF magnetization, ...)
     float *th32 = nullptr;    // HMF FP32 state
     float *p32 = nullptr;
+    void *fops[2] = {nullptr, nullptr};  // fused stage operands, alternating (n <= kFusedMaxN): [2][npad] of T
+    int launch = 0;                      // md_launch: auto / staged / fused
     md::Tiles tiles;
     md::Batch *batch = nullptr;  // non-null for a batched ensemble (owned)
     std::string err;
@@ -113,10 +119,20 @@ hipError_t launch_pair(md_ctx *c, const double *q);
 // snap (nullable): with UPD_DRIFT, the drifted positions are also written there.
 hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift,
                          double *q, double *p, double *f, double *snap = nullptr);
+// Fused small-N stages: the update writing the fused operand form into ops, and
+// one pair + update launch reading operands `in`, writing the new ones to `out`.
+hipError_t launch_update_fused(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q,
+                               double *p, double *f, void *ops, double *snap);
+hipError_t launch_fused(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
+                        double *f, const void *in, void *out, double *snap);
 // hmf.hip
+// snap (nullable, FP64 state only): with HMF_DRIFT, the drifted angles are also written there.
 hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, double drift,
                            double *th, double *p, const double *f_in, double *f_out,
-                           bool f32state);
+                           bool f32state, double *snap = nullptr);
+hipError_t launch_hmf_hvp_sums(md_ctx *c, const double *th, const double *w);
+hipError_t launch_hmf_adj_update(md_ctx *c, const double *th, int flags, double h, double h2, double a,
+                                 double *lq, double *lp, double *out);
 hipError_t launch_hmf_magnetization(md_ctx *c, double *out2);
 const double *hmf_partials(const md_ctx *c);  // block partials of the latest reducing pass
 hipError_t launch_hmf_convert(md_ctx *c, double *th, double *p, bool to_f32);

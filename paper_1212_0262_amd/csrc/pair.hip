@@ -29,27 +29,14 @@ using namespace pairs;
 
 // ---------------------------------------------------------------- pair kernels --
 
-// part[(s*2 + c)*npad + i] = sum over j in the s-th j range of the 2D pair term.
+// Adds the 2D pair terms of j in [j0, j1) to each lane's IPL accumulators, j
+// ascending, the FP32 partials folded every jtile j (the order every 2D kernel
+// shares, so they agree bit for bit).  xs, ys: the j operands (wave-uniform).
 template <typename T, typename A, int IPL>
-__global__ __launch_bounds__(256) void k_pair_2d(const T *__restrict__ xs, const T *__restrict__ ys,
-                                                 int n, int npad, int jlen, int jtile, T eps,
-                                                 double *__restrict__ part)
+__device__ __forceinline__ void grav_range(const T *__restrict__ xs, const T *__restrict__ ys, int j0, int j1,
+                                           int jtile, T eps, const T (&xi)[IPL], const T (&yi)[IPL], A (&ax)[IPL],
+                                           A (&ay)[IPL])
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const int ibase = (blockIdx.x * (blockDim.x / kWave) + wave) * (kWave * IPL) + lane;
-    const int s = blockIdx.y;
-    const int j0 = s * jlen;
-    const int j1 = min(n, j0 + jlen);
-
-    T xi[IPL], yi[IPL];
-    A ax[IPL], ay[IPL];
-#pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const int i = min(ibase + kWave * k, n - 1);
-        xi[k] = xs[i];
-        yi[k] = ys[i];
-    }
     for (int jt = j0; jt < j1; jt += jtile) {
         const int je = min(j1, jt + jtile);
         int j = jt;
@@ -74,6 +61,30 @@ __global__ __launch_bounds__(256) void k_pair_2d(const T *__restrict__ xs, const
             ay[k].fold();
         }
     }
+}
+
+// part[(s*2 + c)*npad + i] = sum over j in the s-th j range of the 2D pair term.
+template <typename T, typename A, int IPL>
+__global__ __launch_bounds__(256) void k_pair_2d(const T *__restrict__ xs, const T *__restrict__ ys,
+                                                 int n, int npad, int jlen, int jtile, T eps,
+                                                 double *__restrict__ part)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int ibase = (blockIdx.x * (blockDim.x / kWave) + wave) * (kWave * IPL) + lane;
+    const int s = blockIdx.y;
+    const int j0 = s * jlen;
+    const int j1 = min(n, j0 + jlen);
+
+    T xi[IPL], yi[IPL];
+    A ax[IPL], ay[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = min(ibase + kWave * k, n - 1);
+        xi[k] = xs[i];
+        yi[k] = ys[i];
+    }
+    grav_range<T, A, IPL>(xs, ys, j0, j1, jtile, eps, xi, yi, ax, ay);
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int i = ibase + kWave * k;
@@ -91,6 +102,37 @@ __device__ __forceinline__ void ring_term(T c0, T s0, T c1, T s1, T e, A &a)
 {
     if constexpr (sizeof(T) == 8) pair_ring(c0, s0, c1, s1, e, a);
     else pair_ring_half(s0, c0, s1, c1, e, a);
+}
+
+// Adds the Ring pair terms of j in [j0, j1) to each lane's IPL accumulators, in
+// the order every Ring kernel shares (j ascending, folds every jtile j).
+// cc, ss: the j operand rows (wave-uniform).
+template <typename T, typename A, int IPL>
+__device__ __forceinline__ void ring_range(const T *__restrict__ cc, const T *__restrict__ ss, int j0, int j1,
+                                           int jtile, T one_eps, const T (&ci)[IPL], const T (&si)[IPL],
+                                           A (&a)[IPL])
+{
+    for (int jt = j0; jt < j1; jt += jtile) {
+        const int je = min(j1, jt + jtile);
+        int j = jt;
+        for (; j + 8 <= je; j += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T cj = cc[j + u];
+                const T sj = ss[j + u];
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, one_eps, a[k]);
+            }
+        }
+        for (; j < je; ++j) {
+            const T cj = cc[j];
+            const T sj = ss[j];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, one_eps, a[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) a[k].fold();
+    }
 }
 
 // part[s*npad + i] = sum over j in the s-th j range of the Ring pair term.
@@ -116,27 +158,7 @@ __global__ __launch_bounds__(256) void k_pair_ring(const T *__restrict__ cs, int
         ci[k] = cc[i];
         si[k] = ss[i];
     }
-    for (int jt = j0; jt < j1; jt += jtile) {
-        const int je = min(j1, jt + jtile);
-        int j = jt;
-        for (; j + 8 <= je; j += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const T cj = cc[j + u];
-                const T sj = ss[j + u];
-#pragma unroll
-                for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, one_eps, a[k]);
-            }
-        }
-        for (; j < je; ++j) {
-            const T cj = cc[j];
-            const T sj = ss[j];
-#pragma unroll
-            for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, one_eps, a[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < IPL; ++k) a[k].fold();
-    }
+    ring_range<T, A, IPL>(cc, ss, j0, j1, jtile, one_eps, ci, si, a);
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int i = ibase + kWave * k;
@@ -146,8 +168,51 @@ __global__ __launch_bounds__(256) void k_pair_ring(const T *__restrict__ cs, int
 
 // --------------------------------------------------------------- update kernel --
 
-// Operand refresh after a drift.
-enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_HALF32 = 2, PREP_SINCOS64 = 3 };
+// Operand refresh after a drift.  COPY64: an FP64 copy of q (2D FP64 operands of
+// the fused stage, which cannot read q while other blocks drift it).
+enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_HALF32 = 2, PREP_SINCOS64 = 3, PREP_COPY64 = 4 };
+
+// The stage's work on coordinate d of particle i, given its force component fd:
+// store f, p += kick * f, q += drift * p, then the pair operands of the new q.
+template <int PREP>
+__device__ __forceinline__ void stage_elem(int d, int i, int n, int npad, double fd, int flags,
+                                           double *__restrict__ f, double *__restrict__ p, double *__restrict__ q,
+                                           void *__restrict__ ops, double kick1, double kick2, double drift,
+                                           double *__restrict__ snap)
+{
+    const size_t k = (size_t)d * n + i;
+    if (flags & UPD_STORE_F) f[k] = fd;
+    double qd = 0.0;
+    if (flags & (UPD_DRIFT | UPD_PREP)) qd = q[k];
+    if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_DRIFT)) {
+        double pd = p[k];
+        if (flags & UPD_KICK1) pd += kick1 * fd;
+        if (flags & UPD_KICK2) pd += kick2 * fd;
+        if (flags & (UPD_KICK1 | UPD_KICK2)) p[k] = pd;
+        if (flags & UPD_DRIFT) {
+            qd += drift * pd;
+            q[k] = qd;
+            if (snap) snap[k] = qd;
+        }
+    }
+    if (flags & UPD_PREP) {
+        if (PREP == PREP_CAST32) {
+            static_cast<float *>(ops)[(size_t)d * npad + i] = (float)qd;
+        } else if (PREP == PREP_COPY64) {
+            static_cast<double *>(ops)[(size_t)d * npad + i] = qd;
+        } else if (PREP == PREP_HALF32) {
+            double sn, cn;
+            sincos64(0.5 * qd, &sn, &cn);
+            static_cast<float *>(ops)[i] = (float)(1.4142135623730951 * cn);
+            static_cast<float *>(ops)[npad + i] = (float)(1.4142135623730951 * sn);
+        } else if (PREP == PREP_SINCOS64) {
+            double sn, cn;
+            sincos64(qd, &sn, &cn);
+            static_cast<double *>(ops)[i] = cn;
+            static_cast<double *>(ops)[npad + i] = sn;
+        }
+    }
+}
 
 // One kick-drift stage, elementwise over particles (eq. 4 and the step list of
 // Sec. 3): f from the pair partials (times the model prefactor), p += kick * f,
@@ -161,79 +226,140 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ part,
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const bool need_p = flags & (UPD_KICK1 | UPD_KICK2 | UPD_DRIFT);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const size_t k = (size_t)d * n + i;
         double fd = 0.0;
         if (flags & UPD_F_FROM_PART) {
             double s = 0.0;
             for (int b = 0; b < S; ++b) s += part[(size_t)(b * D + d) * npad + i];
             fd = pref * s;
         } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
-            fd = f[k];
+            fd = f[(size_t)d * n + i];
         }
-        if (flags & UPD_STORE_F) f[k] = fd;
-        double qd = 0.0;
-        if (flags & (UPD_DRIFT | UPD_PREP)) qd = q[k];
-        if (need_p) {
-            double pd = p[k];
-            if (flags & UPD_KICK1) pd += kick1 * fd;
-            if (flags & UPD_KICK2) pd += kick2 * fd;
-            if (flags & (UPD_KICK1 | UPD_KICK2)) p[k] = pd;
-            if (flags & UPD_DRIFT) {
-                qd += drift * pd;
-                q[k] = qd;
-                if (snap) snap[k] = qd;
-            }
+        stage_elem<PREP>(d, i, n, npad, fd, flags, f, p, q, ops, kick1, kick2, drift, snap);
+    }
+}
+
+// ------------------------------------------------------------- fused stage --
+// Small N: one launch per force evaluation.  A block owns the 64 IPL particles
+// of one i tile; its S = blockDim / 64 wavefronts take the S j ranges the staged
+// path gives to grid.y (same jlen, same folds), leave their partials in LDS, and
+// the block adds them in the staged order and runs the stage on its own
+// particles -- bit for bit the staged pair + update.  The j operands come from
+// `in`; the refreshed ones go to `out` (another buffer: other blocks still read
+// `in`), so the two alternate between stages.
+template <int MODEL, typename T, typename A, int IPL, int PREP>
+__global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *__restrict__ out, int n, int npad,
+                                                int jlen, int jtile, T e, double pref, double *__restrict__ f,
+                                                double *__restrict__ p, double *__restrict__ q, double kick1,
+                                                double kick2, double drift, int flags, double *__restrict__ snap)
+{
+    constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
+    extern __shared__ double red[];  // [S][IPL * D][64]
+    const int S = blockDim.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int i0 = blockIdx.x * (kWave * IPL);
+    const int j0 = w * jlen;
+    const int j1 = min(n, j0 + jlen);
+    const T *__restrict__ r0 = in;
+    const T *__restrict__ r1 = in + npad;
+    T a0[IPL], a1[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = min(i0 + kWave * k + lane, n - 1);
+        a0[k] = r0[i];
+        a1[k] = r1[i];
+    }
+    if constexpr (MODEL == MD_GRAV2D) {
+        A ax[IPL], ay[IPL];
+        grav_range<T, A, IPL>(r0, r1, j0, j1, jtile, e, a0, a1, ax, ay);
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            red[(w * IPL * D + k * D + 0) * kWave + lane] = ax[k].get();
+            red[(w * IPL * D + k * D + 1) * kWave + lane] = ay[k].get();
         }
-        if (flags & UPD_PREP) {
-            if (PREP == PREP_CAST32) {
-                static_cast<float *>(ops)[(size_t)d * npad + i] = (float)qd;
-            } else if (PREP == PREP_HALF32) {
-                double sn, cn;
-                sincos64(0.5 * qd, &sn, &cn);
-                static_cast<float *>(ops)[i] = (float)(1.4142135623730951 * cn);
-                static_cast<float *>(ops)[npad + i] = (float)(1.4142135623730951 * sn);
-            } else if (PREP == PREP_SINCOS64) {
-                double sn, cn;
-                sincos64(qd, &sn, &cn);
-                static_cast<double *>(ops)[i] = cn;
-                static_cast<double *>(ops)[npad + i] = sn;
+    } else {
+        A a[IPL];
+        ring_range<T, A, IPL>(r0, r1, j0, j1, jtile, e, a0, a1, a);
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) red[(w * IPL * D + k) * kWave + lane] = a[k].get();
+    }
+    __syncthreads();
+    for (int kd = w; kd < IPL * D; kd += S) {
+        const int k = kd / D, d = kd % D;
+        const int i = i0 + kWave * k + lane;
+        if (i < n) {
+            double fd = 0.0;
+            if (flags & UPD_F_FROM_PART) {
+                double s = 0.0;
+                for (int b = 0; b < S; ++b) s += red[(b * IPL * D + kd) * kWave + lane];
+                fd = pref * s;
+            } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
+                fd = f[(size_t)d * n + i];
             }
+            stage_elem<PREP>(d, i, n, npad, fd, flags, f, p, q, out, kick1, kick2, drift, snap);
         }
     }
 }
 
 // ------------------------------------------------------------------ launchers --
 
-int prep_kind(const md_ctx *c)
+int prep_kind(const md_ctx *c, bool fused)
 {
-    if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? PREP_NONE : PREP_CAST32;
+    if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? (fused ? PREP_COPY64 : PREP_NONE) : PREP_CAST32;
     return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_HALF32;
 }
 
+// ops: where UPD_PREP writes the operands (c->ops for the staged path).
 hipError_t update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
-                  double *f, double *snap)
+                  double *f, double *snap, void *ops, bool fused)
 {
     const int n = (int)c->n;
     const dim3 block(256), grid((unsigned)((n + 255) / 256));
     const double pref = force_prefactor(c->model, c->prec, n);
     const int S = c->tiles.jsplit;
     const int npad = (int)c->npad;
-    const int pk = prep_kind(c);
+    const int pk = prep_kind(c, fused);
     if (pk == PREP_NONE) flags &= ~UPD_PREP;
 #define MD_UPD(D_, P_)                                                                                    \
     hipLaunchKernelGGL((k_update<D_, P_>), grid, block, 0, c->stream, c->part, S, n, npad, pref, f, p, q, \
-                       c->ops, kick1, kick2, drift, flags, snap)
+                       ops, kick1, kick2, drift, flags, snap)
     if (c->model == MD_GRAV2D) {
         if (pk == PREP_CAST32) MD_UPD(2, PREP_CAST32);
+        else if (pk == PREP_COPY64) MD_UPD(2, PREP_COPY64);
         else MD_UPD(2, PREP_NONE);
     } else {
         if (pk == PREP_HALF32) MD_UPD(1, PREP_HALF32);
         else MD_UPD(1, PREP_SINCOS64);
     }
 #undef MD_UPD
+    return hipGetLastError();
+}
+
+template <int MODEL, typename T, typename A, int PREP>
+hipError_t fused_ipl(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
+                     double *f, const void *in, void *out, double *snap, T e)
+{
+    const Tiles &t = c->tiles;
+    const int n = (int)c->n, npad = (int)c->npad, S = t.jsplit;
+    constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
+    int jlen = (n + S - 1) / S;
+    jlen = (jlen + 15) / 16 * 16;
+    const double pref = force_prefactor(c->model, c->prec, n);
+    const dim3 block((unsigned)(kWave * S));
+    const dim3 grid((unsigned)((n + kWave * t.ipl - 1) / (kWave * t.ipl)));
+    const size_t lds = (size_t)S * t.ipl * D * kWave * sizeof(double);
+    const T *src = static_cast<const T *>(in);
+#define MD_FUSED(I_)                                                                                             \
+    hipLaunchKernelGGL((k_fused<MODEL, T, A, I_, PREP>), grid, block, lds, c->stream, src, out, n, npad, jlen, \
+                       t.jtile, e, pref, f, p, q, kick1, kick2, drift, flags, snap)
+    switch (t.ipl) {
+    case 1: MD_FUSED(1); break;
+    case 2: MD_FUSED(2); break;
+    default: MD_FUSED(4); break;
+    }
+#undef MD_FUSED
     return hipGetLastError();
 }
 
@@ -266,14 +392,56 @@ hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
 
 hipError_t launch_prep(md_ctx *c, const double *q)
 {
-    if (prep_kind(c) == PREP_NONE) return hipSuccess;
-    return update(c, UPD_PREP, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr, nullptr);
+    if (prep_kind(c, false) == PREP_NONE) return hipSuccess;
+    return update(c, UPD_PREP, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr, nullptr, c->ops, false);
 }
 
 hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
                          double *f, double *snap)
 {
-    return update(c, flags, kick1, kick2, drift, q, p, f, snap);
+    return update(c, flags, kick1, kick2, drift, q, p, f, snap, c->ops, false);
+}
+
+hipError_t launch_update_fused(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
+                               double *f, void *ops, double *snap)
+{
+    return update(c, flags, kick1, kick2, drift, q, p, f, snap, ops, true);
+}
+
+hipError_t launch_fused(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
+                        double *f, const void *in, void *out, double *snap)
+{
+    const double eps = c->eps;
+    if (c->model == MD_GRAV2D) {
+        switch (c->prec) {
+        case MD_FP64:
+            return fused_ipl<MD_GRAV2D, double, AccF64, PREP_COPY64>(c, flags, kick1, kick2, drift, q, p, f, in, out,
+                                                                     snap, eps);
+        case MD_MIXED:
+            return fused_ipl<MD_GRAV2D, float, AccTile, PREP_CAST32>(c, flags, kick1, kick2, drift, q, p, f, in, out,
+                                                                     snap, (float)eps);
+        case MD_MIXED_KAHAN:
+            return fused_ipl<MD_GRAV2D, float, AccKahan, PREP_CAST32>(c, flags, kick1, kick2, drift, q, p, f, in,
+                                                                      out, snap, (float)eps);
+        default:
+            return fused_ipl<MD_GRAV2D, float, AccPair64, PREP_CAST32>(c, flags, kick1, kick2, drift, q, p, f, in,
+                                                                       out, snap, (float)eps);
+        }
+    }
+    switch (c->prec) {
+    case MD_FP64:
+        return fused_ipl<MD_RING, double, AccF64, PREP_SINCOS64>(c, flags, kick1, kick2, drift, q, p, f, in, out,
+                                                                 snap, 1.0 + eps);
+    case MD_MIXED:
+        return fused_ipl<MD_RING, float, AccTile, PREP_HALF32>(c, flags, kick1, kick2, drift, q, p, f, in, out, snap,
+                                                               (float)(2.0 * eps));
+    case MD_MIXED_KAHAN:
+        return fused_ipl<MD_RING, float, AccKahan, PREP_HALF32>(c, flags, kick1, kick2, drift, q, p, f, in, out,
+                                                                snap, (float)(2.0 * eps));
+    default:
+        return fused_ipl<MD_RING, float, AccPair64, PREP_HALF32>(c, flags, kick1, kick2, drift, q, p, f, in, out,
+                                                                 snap, (float)(2.0 * eps));
+    }
 }
 
 // Pair partials of the current operands.  For FP64 2D the operands are q itself.

@@ -24,6 +24,7 @@ import torch  # noqa: F401  (must precede loading libmd: shared HIP runtime)
 HMF, RING, GRAV2D = 0, 1, 2
 FP64, MIXED, MIXED_KAHAN, MIXED_PAIRF64, MIXED_F32STATE = 0, 1, 2, 3, 4
 OK, EINVAL, EDEVICE, ENOMEM, ESTATE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+LAUNCH_AUTO, LAUNCH_STAGED, LAUNCH_FUSED = 0, 1, 2
 
 MODEL_NAMES = {HMF: "hmf", RING: "ring", GRAV2D: "grav2d"}
 PREC_NAMES = {FP64: "fp64", MIXED: "mixed", MIXED_KAHAN: "mixed_kahan",
@@ -42,6 +43,8 @@ SIGNATURES = {
     "md_set_stream": (_I, [_V, _V]),
     "md_set_tiles": (_I, [_V, _I, _I, _I, _I]),
     "md_get_tiles": (_I, [_V, ctypes.POINTER(_I)]),
+    "md_set_launch": (_I, [_V, _I]),
+    "md_get_launch": (_I, [_V]),
     "md_max_j_split": (_I, [_I64]),
     "md_force": (_I, [_V, _V, _V]),
     "md_step": (_I, [_V, _V, _V, _V, _D, _I64]),
@@ -214,6 +217,18 @@ def md_get_tiles(ctx: Context) -> tuple:
     out = (ctypes.c_int * 4)()
     ctx._check(load().md_get_tiles(ctx.handle, out), "md_get_tiles")
     return tuple(int(v) for v in out)
+
+
+def md_set_launch(ctx: Context, mode: int) -> None:
+    """LAUNCH_AUTO, LAUNCH_STAGED or LAUNCH_FUSED (md_step's launch form)."""
+    ctx._check(load().md_set_launch(ctx.handle, int(mode)), "md_set_launch")
+
+
+def md_get_launch(ctx: Context) -> int:
+    """The form md_step takes: LAUNCH_STAGED or LAUNCH_FUSED."""
+    r = int(load().md_get_launch(ctx.handle))
+    ctx._check(min(r, 0), "md_get_launch")
+    return r
 
 
 def md_force(ctx: Context, q: torch.Tensor, f: torch.Tensor) -> torch.Tensor:

@@ -13,6 +13,8 @@ Tolerances (max-norm relative to the largest oracle value):
     + eps is formed with an error proportional to |d| and enters as u^{-5/2};
     measured 2e-7 to 1.3e-6.
   * FP64 reverse sweeps: 1e-9 (10 steps of products and axpys).
+  * HMF products: 1e-11 -- the mean-field form (eqs. 6, 7) reorders an O(N) sum of
+    O(1) terms against the oracle's pair sum; both are FP64.
 """
 import os
 
@@ -29,7 +31,7 @@ md = pytest.importorskip("paper_1212_0262_amd.md")
 from paper_1212_0262_amd import autograd as mdgrad  # noqa: E402
 from gpu_helpers import dev, host, rel_inf  # noqa: E402
 
-RING, GRAV2D = md.RING, md.GRAV2D
+HMF, RING, GRAV2D = md.HMF, md.RING, md.GRAV2D
 HVP_TOL = {(GRAV2D, md.FP64): 1e-10, (RING, md.FP64): 1e-10, (GRAV2D, md.MIXED): 1e-4, (RING, md.MIXED): 3e-5,
            (GRAV2D, md.MIXED_KAHAN): 1e-4, (RING, md.MIXED_KAHAN): 3e-5}
 
@@ -41,6 +43,8 @@ def _oracle_threads():
 
 
 def _state(model, n, seed):
+    if model == HMF:
+        return inputs.hmf_waterbag(n, seed=seed)
     return inputs.grav2d_disk(n, seed=seed) if model == GRAV2D else inputs.ring_waterbag(n, seed=seed)
 
 
@@ -61,7 +65,25 @@ def test_hvp_matches_oracle(model, eps, prec, n):
     assert err < HVP_TOL[(model, prec)], err
 
 
-@pytest.mark.parametrize("model,eps,dt", [(GRAV2D, 1e-3, 0.01), (RING, 0.01, 0.05)])
+@pytest.mark.parametrize("n", [1, 2, 65, 1001, 5003])
+@pytest.mark.parametrize("prec", [md.FP64, md.MIXED_F32STATE])
+def test_hmf_hvp_matches_oracle(prec, n):
+    """The O(N) mean-field product against the oracle's O(N^2) pair sum; it runs in
+    FP64 whatever the context's state precision."""
+    q, _ = _state(HMF, n, seed=70 + n)
+    w = np.random.default_rng(n + 1).normal(size=q.shape)
+    ho = oracle.hvp(HMF, q, w, 0.0)
+    ctx = md.md_init(HMF, prec, n, 0.0)
+    hg = host(md.md_hvp(ctx, dev(q), dev(w)))
+    if n == 1:
+        assert np.abs(hg).max() < 1e-15  # w (c^2 + s^2) - (c^2 + s^2) w
+        return
+    err = rel_inf(hg, ho)
+    print(f"hvp model=HMF prec={prec} n={n} rel_err={err:.3e}")
+    assert err < 1e-11, err
+
+
+@pytest.mark.parametrize("model,eps,dt", [(GRAV2D, 1e-3, 0.01), (RING, 0.01, 0.05), (HMF, 0.0, 0.1)])
 def test_step_vjp_matches_oracle(model, eps, dt):
     n, nst = 300, 10
     q0, p0 = _state(model, n, seed=61)
@@ -90,11 +112,13 @@ def test_step_vjp_mixed_close_to_oracle():
     assert rel_inf(host(lq), oq) < 1e-3 and rel_inf(host(lp), op) < 1e-3
 
 
-def test_step_vjp_composes_over_segments():
-    """Checkpointed segments: 9 steps at once == 5 then 4, bit for bit."""
-    n, eps, dt = 500, 1e-3, 0.01
-    q0, p0 = _state(GRAV2D, n, seed=63)
-    ctx = md.md_init(GRAV2D, md.MIXED, n, eps)
+@pytest.mark.parametrize("model,prec,eps,dt,n", [(GRAV2D, md.MIXED, 1e-3, 0.01, 500), (GRAV2D, md.FP64, 1e-3, 0.01, 501),
+                                                 (HMF, md.FP64, 0.0, 0.1, 500), (HMF, md.FP64, 0.0, 0.1, 20_001)])
+def test_step_vjp_composes_over_segments(model, prec, eps, dt, n):
+    """Checkpointed segments: 9 steps at once == 5 then 4, bit for bit (odd n: the
+    padded stage slots keep the recomputed trajectory identical to md_step's)."""
+    q0, p0 = _state(model, n, seed=63)
+    ctx = md.md_init(model, prec, n, eps)
     qd, pd = dev(q0), dev(p0)
     f = torch.empty_like(qd)
     md.md_force(ctx, qd, f)
@@ -117,12 +141,16 @@ def test_step_vjp_rejects_small_stage_buffer():
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(md.MDError):
         md.md_step_vjp(ctx, q, q.clone(), 0.01, 3, q.clone(), q.clone(), small)
-    hmf = md.md_init(md.HMF, md.FP64, 100, 0.0)
+    hmf = md.md_init(HMF, md.MIXED_F32STATE, 100, 0.0)
+    h = q[:1].contiguous()
+    with pytest.raises(md.MDError):  # the FP32-state trajectory has no FP64 snapshots
+        md.md_step_vjp(hmf, h, h.clone(), 0.01, 3, h.clone(), h.clone())
+    batch = md.md_batch_init(RING, md.FP64, [0, 50, 100], 0.01)
     with pytest.raises(md.MDError):
-        md.md_hvp(hmf, q[:1].contiguous(), q[:1].contiguous())
+        md.md_hvp(batch, h, h.clone())
 
 
-@pytest.mark.parametrize("model,eps,dt", [(GRAV2D, 1e-2, 0.01), (RING, 0.02, 0.02)])
+@pytest.mark.parametrize("model,eps,dt", [(GRAV2D, 1e-2, 0.01), (RING, 0.02, 0.02), (HMF, 0.0, 0.1)])
 def test_kinetic_energy_gradient_matches_finite_differences(model, eps, dt):
     """d K_T / d(q0, p0) through the autograd Function (checkpoints every 7 steps)
     against central differences of the FP64 forward map along 4 random directions."""
@@ -147,3 +175,40 @@ def test_kinetic_energy_gradient_matches_finite_differences(model, eps, dt):
         ad = float(np.sum(gq * vq) + np.sum(gp * vp))
         print(f"grad model={model} ad={ad:.12e} fd={fd:.12e}")
         assert abs(ad - fd) < 1e-6 * max(1.0, abs(fd)), (ad, fd)
+
+
+@pytest.mark.parametrize("model,eps,dt", [(HMF, 0.0, 0.1), (RING, 0.02, 0.02)])
+def test_magnetization_gradient_matches_oracle_and_finite_differences(model, eps, dt):
+    """d M_T / d(q0, p0), M_T = |(mean cos q_T, mean sin q_T)|, through the autograd
+    Function: against the oracle's reverse sweep seeded with the observable's
+    derivative at the oracle's final state, and against central differences of the
+    GPU FP64 forward map along 4 random directions."""
+    n, nst = 256, 30
+    q0, p0 = _state(model, n, seed=65)
+    ctx = md.md_init(model, md.FP64, n, eps)
+    M, gq, gp = mdgrad.magnetization_gradient(ctx, dev(q0), dev(p0), dt, nst, checkpoint_every=7)
+    gq, gp = host(gq), host(gp)
+    # oracle gradient
+    f0 = oracle.force(model, q0, eps)
+    qT, _, _ = oracle.step(model, q0, p0, f0, dt, nst, eps)
+    mx, my = np.cos(qT).mean(), np.sin(qT).mean()
+    Mo = np.hypot(mx, my)
+    assert abs(float(M) - Mo) < 1e-12
+    lq = (-mx * np.sin(qT) + my * np.cos(qT)) / (n * Mo)
+    oq, op = oracle.step_vjp(model, q0, p0, dt, nst, lq, np.zeros_like(p0), eps)
+    assert rel_inf(gq, oq) < 1e-9 and rel_inf(gp, op) < 1e-9
+
+    def J(q, p):
+        qd, pd = dev(q), dev(p)
+        f = torch.empty_like(qd)
+        md.md_force(ctx, qd, f)
+        md.md_step(ctx, qd, pd, f, dt, nst)
+        return float(torch.sqrt(torch.cos(qd).mean() ** 2 + torch.sin(qd).mean() ** 2))
+    rng = np.random.default_rng(11)
+    for _ in range(4):
+        vq, vp = rng.normal(size=q0.shape), rng.normal(size=p0.shape)
+        h = 1e-6
+        fd = (J(q0 + h * vq, p0 + h * vp) - J(q0 - h * vq, p0 - h * vp)) / (2 * h)
+        ad = float(np.sum(gq * vq) + np.sum(gp * vp))
+        print(f"magnetization grad model={model} ad={ad:.12e} fd={fd:.12e}")
+        assert abs(ad - fd) < 1e-7 * max(1.0, abs(fd)), (ad, fd)

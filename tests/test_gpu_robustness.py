@@ -1,0 +1,125 @@
+"""GPU robustness: code paths the workload tests do not reach -- HMF with
+unaligned arrays (scalar accesses) and ragged N (vector tails), the tile
+autotuner, and randomized small systems over every model, precision and tile
+configuration (hypothesis), each against the FP64 oracle with the tolerances of
+test_gpu_parity.py."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_0262_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+md = pytest.importorskip("paper_1212_0262_amd.md")
+hypothesis = pytest.importorskip("hypothesis")
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+from gpu_helpers import dev, host, rel_inf  # noqa: E402
+from test_gpu_parity import FORCE_TOL  # noqa: E402
+
+HMF, RING, GRAV2D = md.HMF, md.RING, md.GRAV2D
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_threads():
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def _offset_view(a: np.ndarray) -> torch.Tensor:
+    """A contiguous device view of `a` whose data pointer is 8-byte but not
+    16-byte aligned."""
+    d, n = a.shape
+    big = torch.zeros((d, n + 1), dtype=torch.float64, device="cuda")
+    flat = big.reshape(-1)[1:1 + d * n].view(d, n)
+    flat.copy_(torch.from_numpy(a))
+    assert flat.data_ptr() % 16 == 8 and flat.is_contiguous()
+    return flat
+
+
+@pytest.mark.parametrize("n", [1, 3, 1001, 20_003])
+def test_hmf_unaligned_arrays_take_the_scalar_path(n):
+    q, p = inputs.hmf_waterbag(n, seed=90)
+    f0 = oracle.force(HMF, q)
+    qo, po, fo = oracle.step(HMF, q, p, f0, 0.1, 5, 0.0)
+    ctx = md.md_init(HMF, md.FP64, n, 0.0)
+    qd, pd = _offset_view(q), _offset_view(p)
+    f = _offset_view(np.zeros_like(q))
+    md.md_force(ctx, qd, f)
+    assert np.abs(host(f) - f0).max() < 1e-13
+    md.md_step(ctx, qd, pd, f, 0.1, 5)
+    assert np.abs(host(qd) - qo).max() < 1e-12 and np.abs(host(pd) - po).max() < 1e-12
+    assert np.abs(host(f) - fo).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 4097, 20_003])
+def test_hmf_f32state_ragged_tails(n):
+    """FP32 state moves 4 particles per vector access; the n mod 4 others take the
+    scalar tail path.  Energies match the oracle to the FP32-state bar."""
+    q, p = inputs.hmf_waterbag(n, seed=91)
+    f = oracle.force(HMF, q)
+    qo, po, _ = oracle.step(HMF, q, p, f, 0.1, 10, 0.0)
+    e0 = oracle.energy(HMF, q, p)
+    eo = oracle.energy(HMF, qo, po)
+    ctx = md.md_init(HMF, md.MIXED_F32STATE, n, 0.0)
+    qd, pd = dev(q), dev(p)
+    fd = torch.empty_like(qd)
+    md.md_force(ctx, qd, fd)
+    md.md_step(ctx, qd, pd, fd, 0.1, 10)
+    eg = host(md.md_energy(ctx, qd, pd))
+    scale = abs(e0[0]) + abs(e0[1]) + n / 2
+    assert abs(eg[2] - eo[2]) < 1e-5 * scale
+    d = host(qd) - qo
+    assert np.abs(d - 2 * np.pi * np.round(d / (2 * np.pi))).max() < 1e-3
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    from paper_1212_0262_amd import autotune
+    n = 5000
+    q, _ = inputs.grav2d_disk(n, seed=92)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, 1e-3)
+    qd = dev(q)
+    cache = str(tmp_path / "tiles.json")
+    configs = [(1, 4, 8, 128), (2, 2, 4, 128), (1, 1, 16, 64)]
+    best, table = autotune.tune(ctx, qd, configs=configs, reps=2, cache=cache)
+    assert len(table) == 3 and tuple(best) == tuple(table[0][0])
+    assert md.md_get_tiles(ctx) == tuple(best)
+    data = json.load(open(cache))
+    assert list(data.values())[0]["tiles"] == list(best)
+    other = md.md_init(GRAV2D, md.MIXED, n, 1e-3)
+    assert autotune.apply_cached(other, cache) == tuple(best)
+    assert md.md_get_tiles(other) == tuple(best)
+    # the tuned context computes the same forces (to rounding)
+    f1, f2 = torch.empty_like(qd), torch.empty_like(qd)
+    md.md_force(ctx, qd, f1)
+    md.md_set_tiles(other, 1, 4, 1, 128)
+    md.md_force(other, qd, f2)
+    assert rel_inf(host(f1), host(f2)) < 1e-5
+
+
+@settings(max_examples=40, deadline=None, derandomize=True)
+@given(model=st.sampled_from([RING, GRAV2D]),
+       prec=st.sampled_from([md.FP64, md.MIXED, md.MIXED_KAHAN, md.MIXED_PAIRF64]),
+       n=st.integers(min_value=1, max_value=700),
+       ipl=st.sampled_from([1, 2, 4]), waves=st.sampled_from([1, 2, 4]),
+       split=st.integers(min_value=1, max_value=64), jtile=st.sampled_from([16, 48, 128, 4096]),
+       seed=st.integers(min_value=0, max_value=10_000))
+def test_random_small_systems_match_oracle(model, prec, n, ipl, waves, split, jtile, seed):
+    eps = 1e-3 if model == GRAV2D else 0.01
+    q, _ = inputs.grav2d_disk(n, seed=seed) if model == GRAV2D else inputs.ring_waterbag(n, seed=seed)
+    ctx = md.md_init(model, prec, n, eps)
+    md.md_set_tiles(ctx, ipl, waves, min(split, md.md_max_j_split(n)), jtile)
+    qd = dev(q)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    fo = oracle.force(model, q, eps)
+    fg = host(f)
+    if n == 1:
+        assert np.all(fg == 0.0)
+    else:
+        assert rel_inf(fg, fo) < FORCE_TOL[(model, prec)]
