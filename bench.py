@@ -465,13 +465,36 @@ def adjoint_workload(md, torch, args):
         fd = (J(q0 + hbest * v[:2], p0 + hbest * v[2:]) - J(q0 - hbest * v[:2], p0 - hbest * v[2:])) / (2 * hbest)
         rel.append(abs(ad - fd) / max(abs(fd), 1e-300))
     ctx.close()
+    cpu = None
+    if not args.no_cpu:
+        # the oracle's gradient at reduced N beside the GPU's (same map, FP64)
+        import oracle
+        oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+        n_s, st_s = 1024, 20
+        qs, ps = inputs.grav2d_disk(n_s, seed=5)
+        cs = md.md_init(md.GRAV2D, md.FP64, n_s, ADJ_EPS)
+        _, gqs, gps = mdgrad.kinetic_energy_gradient(cs, torch.from_numpy(qs).cuda(), torch.from_numpy(ps).cuda(),
+                                                     ADJ_DT, st_s, 5)
+        cs.close()
+        t0 = time.perf_counter()
+        f = oracle.force(oracle.GRAV2D, qs, ADJ_EPS)
+        _, pT, _ = oracle.step(oracle.GRAV2D, qs, ps, f, ADJ_DT, st_s, ADJ_EPS)
+        oq, op = oracle.step_vjp(oracle.GRAV2D, qs, ps, ADJ_DT, st_s, np.zeros_like(qs), pT.copy(), ADJ_EPS)
+        t_cpu = time.perf_counter() - t0
+        g_gpu = np.concatenate([gqs.cpu().numpy().ravel(), gps.cpu().numpy().ravel()])
+        g_cpu = np.concatenate([oq.ravel(), op.ravel()])
+        cpu = {"value": round(t_cpu, 4), "unit": "s", "cores": oracle.get_threads(), "kind": "oracle",
+               "sample": f"one FP64 gradient of K_T at N={n_s}, {st_s} steps (forward, then the reverse sweep)",
+               "gpu_vs_oracle_gradient_rel_err": float(np.abs(g_gpu - g_cpu).max() / np.abs(g_cpu).max())}
+        log(f"bench: adjoint oracle gradient N={n_s}: {t_cpu:.2f} s, GPU vs oracle "
+            f"{cpu['gpu_vs_oracle_gradient_rel_err']:.2e}")
     pairs_fwd = 3.0 * ADJ_N ** 2 * nst
     return {
         "metric": "s per gradient of K_T w.r.t. (q0, p0) (2D adjoint N=32768, 1000 steps, FP64)",
         "value": round(t_grad, 4), "unit": "s", "ms_per_step": round(1e3 * t_grad / nst, 4), "dtype": "f64",
         "config": {"workload": "grav2d adjoint N=32768 eps=1e-3 dt=0.01 uniform disk seed=5, checkpoints every 50",
                    "model": "grav2d", "n": ADJ_N, "steps": nst, "checkpoint_every": ADJ_CKPT, "precision": "fp64"},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": None, "cpu_baseline": cpu,
         "adjoint": {"K_T": float(K), "forward_s": t_fwd, "gradient_s": t_grad,
                     "gradient_over_forward": t_grad / t_fwd,
                     "forward_gpairs_per_s": pairs_fwd / t_fwd / 1e9,
@@ -491,9 +514,12 @@ def paper_errors_workload(md, torch, args):
     for a bounded prefix (its cost grows as N^2)."""
     import numpy as np
 
-    import oracle
     from paper_1212_0262_amd import inputs
-    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    oracle = None
+    if not args.no_cpu:
+        import oracle
+        oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    cpu_runs = {}
     runs = [("hmf", md.HMF, 1_000_000, 0.0, 0.1, 1000, 20, 200),
             ("ring", md.RING, 16384, 1e-3, 0.005, 2000, 20, 20),
             ("grav2d", md.GRAV2D, 16384, 1e-3, 0.005, 2000, 20, 40)]
@@ -516,43 +542,53 @@ def paper_errors_workload(md, torch, args):
                 es.append(md.md_energy(ctx, q, p).cpu().numpy())
             curves[label] = np.array(es)
             ctx.close()
-        # oracle prefix
-        t0 = time.perf_counter()
-        f = oracle.force(model, q0, eps)
-        qo, po = q0, p0
-        eo = [oracle.energy(model, qo, po, eps)]
-        for _ in range(cpu_steps // every):
-            qo, po, f = oracle.step(model, qo, po, f, dt, every, eps)
-            eo.append(oracle.energy(model, qo, po, eps))
-        cpu_s = time.perf_counter() - t0
-        eo = np.array(eo)
-        E0 = eo[0, 2]
-        k = len(eo)
+        E0 = float(curves["gpu_fp64"][0, 2])
         rel = {lab: np.abs(c[:, 2] - E0) / abs(E0) for lab, c in curves.items()}
-        rel["cpu_fp64"] = np.abs(eo[:, 2] - E0) / abs(E0)
         out[name] = {
-            "n": n, "dt": dt, "eps": eps, "steps": nsteps, "report_every": every, "cpu_steps": cpu_steps,
-            "E0": float(E0), "K_end_gpu_fp64": float(curves["gpu_fp64"][-1, 0]),
+            "n": n, "dt": dt, "eps": eps, "steps": nsteps, "report_every": every, "E0": E0,
+            "K_end_gpu_fp64": float(curves["gpu_fp64"][-1, 0]),
             "max_rel_err": {lab: float(r.max()) for lab, r in rel.items()},
-            "max_rel_err_prefix": {lab: float(r[:k].max()) for lab, r in rel.items()},
-            "gpu_fp64_vs_cpu_max_dE_over_absE0": float(np.abs(curves["gpu_fp64"][:k, 2] - eo[:, 2]).max() / abs(E0)),
-            "gpu_mixed_vs_cpu_max_dE_over_absE0": float(np.abs(curves["gpu_mixed"][:k, 2] - eo[:, 2]).max()
-                                                        / abs(E0)),
             "gpu_mixed_vs_gpu_fp64_max_dE_over_absE0": float(np.abs(curves["gpu_mixed"][:, 2]
                                                                     - curves["gpu_fp64"][:, 2]).max() / abs(E0)),
             "curve_t": [float(dt * every * i) for i in range(len(rel["gpu_fp64"]))][::5],
             "curve_gpu_fp64": [float(x) for x in rel["gpu_fp64"][::5]],
             "curve_gpu_mixed": [float(x) for x in rel["gpu_mixed"][::5]],
-            "cpu_seconds": cpu_s,
         }
         log(f"bench: paper errors {name}: max eps fp64 {out[name]['max_rel_err']['gpu_fp64']:.2e} "
-            f"mixed {out[name]['max_rel_err']['gpu_mixed']:.2e} cpu(prefix) {out[name]['max_rel_err']['cpu_fp64']:.2e}")
+            f"mixed {out[name]['max_rel_err']['gpu_mixed']:.2e}")
+        if oracle is not None:
+            # the CPU oracle on a bounded prefix of the same run, beside the GPU curves
+            t0 = time.perf_counter()
+            f = oracle.force(model, q0, eps)
+            qo, po = q0, p0
+            eo = [oracle.energy(model, qo, po, eps)]
+            for _ in range(cpu_steps // every):
+                qo, po, f = oracle.step(model, qo, po, f, dt, every, eps)
+                eo.append(oracle.energy(model, qo, po, eps))
+            cpu_s = time.perf_counter() - t0
+            eo = np.array(eo)
+            k = len(eo)
+            cpu_runs[name] = {
+                "steps": cpu_steps, "seconds": cpu_s,
+                "max_rel_err_prefix": {"cpu_fp64": float((np.abs(eo[:, 2] - eo[0, 2]) / abs(eo[0, 2])).max()),
+                                       **{lab: float(r[:k].max()) for lab, r in rel.items()}},
+                "gpu_fp64_vs_cpu_max_dE_over_absE0": float(np.abs(curves["gpu_fp64"][:k, 2] - eo[:, 2]).max()
+                                                           / abs(E0)),
+                "gpu_mixed_vs_cpu_max_dE_over_absE0": float(np.abs(curves["gpu_mixed"][:k, 2] - eo[:, 2]).max()
+                                                            / abs(E0)),
+            }
     worst = max(v["gpu_mixed_vs_gpu_fp64_max_dE_over_absE0"] for v in out.values())
     return {
         "metric": "max |E_mixed - E_fp64| / |E0| over the paper's accuracy runs (HMF, Ring, 2D shell)",
         "value": worst, "unit": "relative", "ms_per_step": None, "dtype": "f64+f32",
         "config": {"workload": "accuracy runs of Sec. 4: homogeneous at rest (HMF, Ring), shell at rest (2D)"},
-        "roofline": None, "cpu_baseline": None, "paper_errors": out,
+        "roofline": None,
+        "cpu_baseline": None if oracle is None else {
+            "value": round(sum(r["seconds"] for r in cpu_runs.values()), 3), "unit": "s",
+            "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": "the same three runs on the CPU FP64 oracle for a bounded prefix (HMF 200, Ring 20, "
+                      "2D 40 steps), energies at the same report times", "runs": cpu_runs},
+        "paper_errors": out,
     }
 
 

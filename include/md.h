@@ -168,16 +168,21 @@ int md_max_j_split(int64_t n);
  *                     (i block, j range) tiles, then an elementwise kernel that
  *                     adds the j-range partials and kicks, drifts and refreshes
  *                     the pair operands;
- *   MD_LAUNCH_FUSED   one launch per force evaluation (small N, where launch
- *                     latency dominates): a block owns one i tile, its j_split
- *                     wavefronts take the j ranges, the partials are added in LDS
- *                     and the same block runs the stage on its own particles.
+ *   MD_LAUNCH_FUSED   one launch per force evaluation (small N, where latency
+ *                     dominates): a block owns one i tile and all its j ranges,
+ *                     the partials are added in LDS and the same block runs the
+ *                     stage on its own particles.
  *                     The j ranges, folds and order of additions are the staged
  *                     ones, so both forms give bit-identical results for the same
- *                     tiles.  Needs n <= 65536, j_split <= 16 and
- *                     j_split * i_per_lane * d <= 64 (MD_EUNSUPPORTED otherwise;
- *                     md_set_tiles then refuses tiles outside that range);
- *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 16384.
+ *                     tiles.  Needs n <= 65536 and tiles a block can hold:
+ *                     the j ranges are j_split / L wavefronts of L lane groups
+ *                     (L the largest power of two <= 8 dividing j_split), at
+ *                     most 16 wavefronts, and i_per_lane * d * 512 bytes of
+ *                     partials per wavefront within 48 KiB / wavefronts
+ *                     (MD_EUNSUPPORTED otherwise; md_set_tiles then refuses
+ *                     tiles outside that range);
+ *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 8192 (the
+ *                     built-in tiles there are the fused form's).
  * md_get_launch returns the form md_step will take (STAGED or FUSED), or a
  * negative status.  HMF and batch contexts are always STAGED.
  */

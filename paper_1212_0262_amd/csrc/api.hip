@@ -146,8 +146,10 @@ hipError_t update_(md_ctx *c, int flags, double kick1, double kick2, double drif
 // whose j ranges fit one block's wavefronts and LDS.
 bool fused_ok(const md_ctx *c, const Tiles &t)
 {
-    return !c->batch && c->model != MD_HMF && c->fops[0] && t.jsplit <= kFusedMaxSplit &&
-           t.jsplit * t.ipl * dims(c->model) <= kFusedMaxLds;
+    if (c->batch || c->model == MD_HMF || !c->fops[0]) return false;
+    const int S = t.jsplit / fused_groups(t.jsplit);
+    // each wavefront's LDS slice holds its partials (i_per_lane * d * 64 doubles)
+    return S <= kFusedMaxWaves && t.ipl * dims(c->model) * kWave * 8 <= kFusedLdsBytes / S;
 }
 
 // md_step's launch form for this context: MD_LAUNCH_STAGED or MD_LAUNCH_FUSED.
@@ -500,6 +502,14 @@ Tiles default_tiles(int model, int prec, int64_t n)
     (void)prec;
     Tiles t;
     t.waves = 4;
+    t.jtile = 128;
+    if (n <= kFusedAutoN) {
+        // the automatic fused launch: the most j ranges (8 lane groups x 8 wavefronts
+        // per block) measured fastest from N = 512 to 8192; two i per lane above 4096
+        t.ipl = n > 4096 ? 2 : 1;
+        t.jsplit = max_j_split(n) < 64 ? max_j_split(n) : 64;
+        return t;
+    }
     t.ipl = n >= 65536 ? 2 : 1;
     t.jtile = 128;
     const int64_t wi = (n + kWave * t.ipl - 1) / (kWave * t.ipl);
@@ -510,8 +520,6 @@ Tiles default_tiles(int model, int prec, int64_t n)
     if (s > cap) s = cap;
     int64_t p2 = 1;
     while (p2 * 2 <= s) p2 *= 2;
-    // up to the automatic fused-launch size the j ranges are one block's wavefronts
-    if (n <= kFusedAutoN && p2 > kFusedMaxSplit) p2 = kFusedMaxSplit;
     t.jsplit = (int)p2;
     return t;
 }
@@ -678,8 +686,8 @@ int md_set_tiles(md_ctx *c, int i_per_lane, int waves, int j_split, int j_tile)
     if (t.jtile < 16 || t.jtile > 4096 || t.jtile % 16)
         return fail(c, MD_EINVAL, "j_tile must be a multiple of 16 in [16, 4096] (got %d)", t.jtile);
     if (c->launch == MD_LAUNCH_FUSED && !fused_ok(c, t))
-        return fail(c, MD_EUNSUPPORTED, "the fused launch needs j_split <= %d and j_split * i_per_lane * d <= %d",
-                    kFusedMaxSplit, kFusedMaxLds);
+        return fail(c, MD_EUNSUPPORTED, "the fused launch needs j_split / (lane groups) <= %d wavefronts and "
+                    "i_per_lane * d * 512 <= %d / wavefronts LDS bytes", kFusedMaxWaves, kFusedLdsBytes);
     c->tiles = t;
     if (c->batch) {
         build_lists(*c->batch, t);
@@ -698,9 +706,9 @@ int md_set_launch(md_ctx *c, int mode)
         return fail(c, MD_EINVAL, "md_set_launch: unknown mode %d", mode);
     if (mode == MD_LAUNCH_FUSED && !fused_ok(c, c->tiles))
         return fail(c, MD_EUNSUPPORTED,
-                    "md_set_launch: the fused launch needs a single Ring or 2D system with n <= %lld, j_split <= %d "
-                    "and j_split * i_per_lane * d <= %d",
-                    (long long)kFusedMaxN, kFusedMaxSplit, kFusedMaxLds);
+                    "md_set_launch: the fused launch needs a single Ring or 2D system with n <= %lld and tiles it "
+                    "can hold (j_split / lane groups <= %d wavefronts, their partials within %d LDS bytes)",
+                    (long long)kFusedMaxN, kFusedMaxWaves, kFusedLdsBytes);
     c->launch = mode;
     return MD_OK;
 }

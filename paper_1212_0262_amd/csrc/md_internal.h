@@ -40,9 +40,18 @@ constexpr int kRedSlots = 1 << 16;   // doubles of reduction scratch
 constexpr int kHmfGrid = 16384;      // most blocks of an HMF pass (2 FP64 partials each)
 constexpr int kEnergyBlock = 256;
 constexpr int64_t kFusedMaxN = 65536;   // contexts up to this n carry the fused stage's operand buffers
-constexpr int kFusedMaxSplit = 16;      // wavefronts per fused block (one per j range)
-constexpr int kFusedMaxLds = 64;        // j ranges x i per lane x d (LDS: 512 B each)
-constexpr int64_t kFusedAutoN = 16384;  // MD_LAUNCH_AUTO takes the fused form up to this n
+constexpr int kFusedMaxWaves = 16;      // wavefronts per fused block
+constexpr int kFusedLdsBytes = 49152;   // LDS per fused block (split evenly between its wavefronts)
+constexpr int64_t kFusedAutoN = 8192;   // MD_LAUNCH_AUTO takes the fused form up to this n
+
+// Lane groups per wavefront of the fused stage for j_split j ranges: the largest
+// power of two <= 8 dividing j_split (more, smaller i tiles: more blocks).
+inline int fused_groups(int jsplit)
+{
+    int L = 1;
+    while (L < 8 && jsplit % (2 * L) == 0) L *= 2;
+    return L;
+}
 
 struct Tiles {
     int ipl = 0;     // i per lane

@@ -241,60 +241,122 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ part,
 }
 
 // ------------------------------------------------------------- fused stage --
-// Small N: one launch per force evaluation.  A block owns the 64 IPL particles
-// of one i tile; its S = blockDim / 64 wavefronts take the S j ranges the staged
-// path gives to grid.y (same jlen, same folds), leave their partials in LDS, and
-// the block adds them in the staged order and runs the stage on its own
-// particles -- bit for bit the staged pair + update.  The j operands come from
-// `in`; the refreshed ones go to `out` (another buffer: other blocks still read
-// `in`), so the two alternate between stages.
-template <int MODEL, typename T, typename A, int IPL, int PREP>
+
+// Makes a wavefront's LDS writes visible to all its lanes' later reads.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Small N: one launch per force evaluation.  A block owns an i tile and all of
+// its j ranges: S wavefronts, each split into L lane groups of 64 / L lanes; lane
+// (group g, slot il) of wavefront w holds the IPL particles i0 + il + k 64/L and
+// sums the pair terms of j range b = w L + g (the staged path's range b: same
+// jlen, j ascending, folds every jtile j from the range start).  The j operands
+// stream through a private LDS window per wavefront (coalesced vector loads, one
+// round trip per window, then reads broadcast within each group; at small N too
+// few wavefronts share a SIMD to hide the latency of the pair kernels'
+// wave-uniform scalar loads).  The window's slice then holds the wavefront's
+// partials; the block adds the S L partials of each particle in the staged
+// order and runs the stage on its own particles: bit for bit the staged pair +
+// update launches.  The j operands come from `in`; the refreshed ones go to
+// `out` (another buffer: other blocks still read `in`), so the two alternate.
+template <int MODEL, typename T, typename A, int IPL, int PREP, int L>
 __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *__restrict__ out, int n, int npad,
                                                 int jlen, int jtile, T e, double pref, double *__restrict__ f,
                                                 double *__restrict__ p, double *__restrict__ q, double kick1,
                                                 double kick2, double drift, int flags, double *__restrict__ snap)
 {
     constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
-    extern __shared__ double red[];  // [S][IPL * D][64]
+    constexpr int IL = kWave / L;          // i slots per lane group
+    constexpr int PAD = L > 1 ? 1 : 0;     // group windows one element apart: no LDS bank conflicts
+    extern __shared__ double lds[];
     const int S = blockDim.x / kWave;
+    const int slice_bytes = kFusedLdsBytes / S;
+    const int CHL = ((slice_bytes / (2 * (int)sizeof(T) * L)) - PAD) / 16 * 16;  // j per group per window
+    const int WS = CHL + PAD;              // window row stride per group
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const int i0 = blockIdx.x * (kWave * IPL);
-    const int j0 = w * jlen;
-    const int j1 = min(n, j0 + jlen);
+    const int g = lane / IL, il = lane % IL;
+    char *slice = reinterpret_cast<char *>(lds) + (size_t)w * slice_bytes;
+    T *win = reinterpret_cast<T *>(slice);  // [2][L][WS]
+    const int i0 = blockIdx.x * (IL * IPL);
+    const int b = w * L + g;
+    const int j0 = b * jlen;
+    const int len = max(0, min(n - j0, jlen));                 // this lane's range length
+    const int wlen = max(0, min(n - w * L * jlen, jlen));      // the wavefront's longest (its group 0)
     const T *__restrict__ r0 = in;
     const T *__restrict__ r1 = in + npad;
     T a0[IPL], a1[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        const int i = min(i0 + kWave * k + lane, n - 1);
+        const int i = min(i0 + IL * k + il, n - 1);
         a0[k] = r0[i];
         a1[k] = r1[i];
     }
-    if constexpr (MODEL == MD_GRAV2D) {
-        A ax[IPL], ay[IPL];
-        grav_range<T, A, IPL>(r0, r1, j0, j1, jtile, e, a0, a1, ax, ay);
+    A acc0[IPL], acc1[IPL];
+    auto term = [&](T x, T y) {
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
-            red[(w * IPL * D + k * D + 0) * kWave + lane] = ax[k].get();
-            red[(w * IPL * D + k * D + 1) * kWave + lane] = ay[k].get();
+            if constexpr (MODEL == MD_GRAV2D) pair_2d(a0[k], a1[k], x, y, e, acc0[k], acc1[k]);
+            else ring_term(a0[k], a1[k], x, y, e, acc0[k]);
         }
-    } else {
-        A a[IPL];
-        ring_range<T, A, IPL>(r0, r1, j0, j1, jtile, e, a0, a1, a);
+    };
+    for (int t = 0; t < wlen; t += 16) {
+        const int off = t % CHL;
+        if (off == 0) {
+            wave_sync();  // the previous window's reads are done
+            for (int idx = lane; idx < L * CHL; idx += kWave) {
+                const int gg = idx / CHL, ee = idx % CHL;
+                const int jb = (w * L + gg) * jlen;
+                const int j = jb + t + ee;
+                if (t + ee < jlen && j < n) {
+                    win[gg * WS + ee] = r0[j];
+                    win[(L + gg) * WS + ee] = r1[j];
+                }
+            }
+            wave_sync();
+        }
+        const T *w0 = win + g * WS + off;
+        const T *w1 = win + (L + g) * WS + off;
+        if (t + 16 <= len) {
 #pragma unroll
-        for (int k = 0; k < IPL; ++k) red[(w * IPL * D + k) * kWave + lane] = a[k].get();
+            for (int u = 0; u < 16; ++u) term(w0[u], w1[u]);
+        } else {
+            for (int u = 0; u < len - t; ++u) term(w0[u], w1[u]);
+        }
+        if (t < len && ((t + 16) % jtile == 0 || t + 16 >= len)) {
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) {
+                acc0[k].fold();
+                if constexpr (MODEL == MD_GRAV2D) acc1[k].fold();
+            }
+        }
+    }
+    wave_sync();  // window reads done before the slice takes the partials
+    double *part = reinterpret_cast<double *>(slice);  // [L][IPL * D][IL]
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        part[(g * IPL * D + k * D) * IL + il] = acc0[k].get();
+        if constexpr (MODEL == MD_GRAV2D) part[(g * IPL * D + k * D + 1) * IL + il] = acc1[k].get();
     }
     __syncthreads();
-    for (int kd = w; kd < IPL * D; kd += S) {
+    for (int it = threadIdx.x; it < IPL * D * IL; it += blockDim.x) {
+        const int s2 = it % IL, kd = it / IL;
         const int k = kd / D, d = kd % D;
-        const int i = i0 + kWave * k + lane;
+        const int i = i0 + IL * k + s2;
         if (i < n) {
             double fd = 0.0;
             if (flags & UPD_F_FROM_PART) {
-                double s = 0.0;
-                for (int b = 0; b < S; ++b) s += red[(b * IPL * D + kd) * kWave + lane];
-                fd = pref * s;
+                double sum = 0.0;
+                for (int bb = 0; bb < S * L; ++bb) {
+                    const double *pb =
+                        reinterpret_cast<const double *>(reinterpret_cast<const char *>(lds) + (size_t)(bb / L) * slice_bytes);
+                    sum += pb[((bb % L) * IPL * D + kd) * IL + s2];
+                }
+                fd = pref * sum;
             } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
                 fd = f[(size_t)d * n + i];
             }
@@ -342,23 +404,32 @@ hipError_t fused_ipl(md_ctx *c, int flags, double kick1, double kick2, double dr
                      double *f, const void *in, void *out, double *snap, T e)
 {
     const Tiles &t = c->tiles;
-    const int n = (int)c->n, npad = (int)c->npad, S = t.jsplit;
-    constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
-    int jlen = (n + S - 1) / S;
+    const int n = (int)c->n, npad = (int)c->npad, js = t.jsplit;
+    const int L = fused_groups(js), S = js / L;
+    int jlen = (n + js - 1) / js;
     jlen = (jlen + 15) / 16 * 16;
     const double pref = force_prefactor(c->model, c->prec, n);
+    const int itile = kWave / L * t.ipl;
     const dim3 block((unsigned)(kWave * S));
-    const dim3 grid((unsigned)((n + kWave * t.ipl - 1) / (kWave * t.ipl)));
-    const size_t lds = (size_t)S * t.ipl * D * kWave * sizeof(double);
+    const dim3 grid((unsigned)((n + itile - 1) / itile));
+    const size_t lds = (size_t)(kFusedLdsBytes / S) * S;
     const T *src = static_cast<const T *>(in);
-#define MD_FUSED(I_)                                                                                             \
-    hipLaunchKernelGGL((k_fused<MODEL, T, A, I_, PREP>), grid, block, lds, c->stream, src, out, n, npad, jlen, \
+#define MD_FUSED(I_, L_)                                                                                              \
+    hipLaunchKernelGGL((k_fused<MODEL, T, A, I_, PREP, L_>), grid, block, lds, c->stream, src, out, n, npad, jlen, \
                        t.jtile, e, pref, f, p, q, kick1, kick2, drift, flags, snap)
-    switch (t.ipl) {
-    case 1: MD_FUSED(1); break;
-    case 2: MD_FUSED(2); break;
-    default: MD_FUSED(4); break;
+#define MD_FUSED_L(I_)                          \
+    switch (L) {                                \
+    case 1: MD_FUSED(I_, 1); break;             \
+    case 2: MD_FUSED(I_, 2); break;             \
+    case 4: MD_FUSED(I_, 4); break;             \
+    default: MD_FUSED(I_, 8); break;            \
     }
+    switch (t.ipl) {
+    case 1: MD_FUSED_L(1); break;
+    case 2: MD_FUSED_L(2); break;
+    default: MD_FUSED_L(4); break;
+    }
+#undef MD_FUSED_L
 #undef MD_FUSED
     return hipGetLastError();
 }

@@ -31,6 +31,20 @@ def _state(model, n, seed):
     return inputs.grav2d_disk(n, seed=seed) if model == GRAV2D else inputs.ring_waterbag(n, seed=seed)
 
 
+def _groups(split):
+    g = 1
+    while g < 8 and split % (2 * g) == 0:
+        g *= 2
+    return g
+
+
+def _fused_fits(model, ipl, split):
+    """The library's rule: split / lane groups <= 16 wavefronts, and each
+    wavefront's LDS slice (48 KiB / wavefronts) holds its partials."""
+    S = split // _groups(split)
+    return S <= 16 and ipl * (2 if model == GRAV2D else 1) * 64 * 8 <= 49152 // S
+
+
 def _run(model, prec, n, eps, dt, nsteps, tiles, launch, seed):
     q0, p0 = _state(model, n, seed)
     ctx = md.md_init(model, prec, n, eps)
@@ -48,20 +62,24 @@ def _run(model, prec, n, eps, dt, nsteps, tiles, launch, seed):
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("model,eps,dt", [(RING, 0.01, 0.05), (GRAV2D, 1e-3, 0.01)])
 def test_fused_equals_staged_bitwise(model, eps, dt, prec, n):
-    split = min(16, md.md_max_j_split(n))
-    tiles = (1, 4, split, 128)
-    a = _run(model, prec, n, eps, dt, 3, tiles, md.LAUNCH_STAGED, seed=80 + n)
-    b = _run(model, prec, n, eps, dt, 3, tiles, md.LAUNCH_FUSED, seed=80 + n)
-    for x, y in zip(a, b):
-        np.testing.assert_array_equal(x, y)
+    """Default tiles, and the most j ranges (8 lane groups of 8 wavefronts)."""
+    for split in (0, min(64, md.md_max_j_split(n))):
+        tiles = (1, 4, split, 128)
+        a = _run(model, prec, n, eps, dt, 3, tiles, md.LAUNCH_STAGED, seed=80 + n)
+        b = _run(model, prec, n, eps, dt, 3, tiles, md.LAUNCH_FUSED, seed=80 + n)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
 
 
-@pytest.mark.parametrize("ipl,split,jtile", [(1, 1, 16), (2, 3, 48), (4, 8, 4096), (2, 16, 128), (1, 5, 64)])
+@pytest.mark.parametrize("ipl,split,jtile", [(1, 1, 16), (2, 3, 48), (4, 8, 4096), (2, 16, 128), (1, 5, 64),
+                                             (1, 2, 32), (2, 6, 16), (1, 12, 48), (4, 24, 128), (2, 40, 64),
+                                             (1, 64, 16), (4, 13, 128)])
 @pytest.mark.parametrize("model,eps,dt", [(RING, 0.01, 0.05), (GRAV2D, 1e-3, 0.01)])
 def test_fused_tile_shapes(model, eps, dt, ipl, split, jtile):
-    """Every accepted tile shape, ragged n: still bit for bit the staged result."""
+    """Tile shapes over 1, 2, 4 and 8 lane groups, ragged n: still bit for bit the
+    staged result."""
     n = 3001
-    if split * ipl * (2 if model == GRAV2D else 1) > 64:
+    if not _fused_fits(model, ipl, split):
         pytest.skip("outside the fused LDS budget")
     tiles = (ipl, 4, split, jtile)
     for prec in (md.FP64, md.MIXED):
@@ -73,24 +91,25 @@ def test_fused_tile_shapes(model, eps, dt, ipl, split, jtile):
 
 def test_auto_launch_form_and_validation():
     small = md.md_init(RING, md.FP64, 2048, 0.01)
-    assert md.md_get_launch(small) == md.LAUNCH_FUSED          # default tiles fit, n <= 16384
+    assert md.md_get_launch(small) == md.LAUNCH_FUSED          # n <= 8192 and the built-in tiles fit
+    assert md.md_get_tiles(small) == (1, 4, 64, 128)
     big = md.md_init(GRAV2D, md.MIXED, 32768, 1e-3)
     assert md.md_get_launch(big) == md.LAUNCH_STAGED           # above the automatic size
-    assert md.md_get_tiles(big)[2] == 32
-    with pytest.raises(md.MDError):                             # 32 j ranges: more than a block's waves
-        md.md_set_launch(big, md.LAUNCH_FUSED)
-    md.md_set_tiles(big, 1, 4, 16, 128)
-    assert md.md_get_launch(big) == md.LAUNCH_STAGED           # auto: still above the automatic size
     md.md_set_launch(big, md.LAUNCH_FUSED)
     assert md.md_get_launch(big) == md.LAUNCH_FUSED
-    with pytest.raises(md.MDError):                             # 17 j ranges: more than a block's waves
+    with pytest.raises(md.MDError):                             # 17 wavefronts (odd split: one lane group)
         md.md_set_tiles(big, 1, 4, 17, 128)
-    assert md.md_get_tiles(big)[2] == 16
+    with pytest.raises(md.MDError):                             # 13 wavefronts x 4 KiB of partials > 48 KiB
+        md.md_set_tiles(big, 4, 4, 13, 128)
+    assert md.md_get_tiles(big)[2] == 32                        # unchanged by the refused calls
     md.md_set_launch(big, md.LAUNCH_STAGED)
-    md.md_set_tiles(big, 1, 4, 32, 128)
+    md.md_set_tiles(big, 1, 4, 17, 128)
+    assert md.md_get_launch(big) == md.LAUNCH_STAGED
+    with pytest.raises(md.MDError):
+        md.md_set_launch(big, md.LAUNCH_FUSED)
+    md.md_set_launch(big, md.LAUNCH_AUTO)
     assert md.md_get_launch(big) == md.LAUNCH_STAGED
     huge = md.md_init(GRAV2D, md.FP64, 70000, 1e-3)              # no fused operand buffers
-    md.md_set_tiles(huge, 1, 4, 8, 128)
     with pytest.raises(md.MDError):
         md.md_set_launch(huge, md.LAUNCH_FUSED)
     hmf = md.md_init(md.HMF, md.FP64, 1000, 0.0)
