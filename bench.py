@@ -433,6 +433,18 @@ def adjoint_workload(md, torch, args):
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0
 
+    # the same gradient with every kick position recorded (no recomputation)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Kr, gqr, gpr = mdgrad.kinetic_energy_gradient(ctx, qd, pd, ADJ_DT, nst, 0)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    rec_same = bool(torch.equal(gqr, gq) and torch.equal(gpr, gp) and float(Kr) == float(K))
+    rec_bytes = md.md_record_stage_bytes(ctx, nst)
+    del gqr, gpr
+    log(f"bench: adjoint gradient {t_grad:.3f} s (checkpoints every {ADJ_CKPT}), {t_rec:.3f} s recorded "
+        f"({rec_bytes / 2**30:.2f} GiB), identical: {rec_same}")
+
     def J(q, p):
         qq, pp = torch.from_numpy(q).cuda(), torch.from_numpy(p).cuda()
         f = torch.empty_like(qq)
@@ -497,6 +509,8 @@ def adjoint_workload(md, torch, args):
         "roofline": None, "cpu_baseline": cpu,
         "adjoint": {"K_T": float(K), "forward_s": t_fwd, "gradient_s": t_grad,
                     "gradient_over_forward": t_grad / t_fwd,
+                    "recorded_gradient_s": t_rec, "recorded_over_forward": t_rec / t_fwd,
+                    "recorded_stage_bytes": rec_bytes, "recorded_equals_checkpointed": rec_same,
                     "forward_gpairs_per_s": pairs_fwd / t_fwd / 1e9,
                     "fd_step": hbest, "fd_sweep_dir0": {str(k): v for k, v in sweep.items()},
                     "rel_err_16_dirs_max": max(rel), "rel_err_16_dirs_median": float(np.median(rel)),

@@ -248,6 +248,28 @@ size_t md_vjp_stage_bytes(const md_ctx *c, int64_t nsteps);
 int md_step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps,
                 double *lam_q, double *lam_p, double *stage, size_t stage_bytes);
 
+/*
+ * The reverse sweep without recomputation, for callers that can hold every kick
+ * position of a run (3 nsteps slots of [d][n] FP64, each rounded up to an even
+ * count of doubles: md_record_stage_bytes; e.g. 1.6 GB for the 2D system at
+ * n = 32768 over 1000 steps).
+ *
+ * md_step_record: md_step (same arguments, same results bit for bit) that also
+ * writes the positions after each of its 3 nsteps drifts into `stage` (caller
+ * device memory of at least md_record_stage_bytes(c, nsteps) bytes).  HMF needs
+ * an MD_FP64 context.
+ *
+ * md_step_vjp_recorded: the reverse sweep of md_step_vjp over a run recorded by
+ * md_step_record from positions q0 with the same dt and nsteps on this context:
+ * (lam_q, lam_p) go from the adjoints at the end of the run to those at its
+ * start.  stage is only read.
+ */
+size_t md_record_stage_bytes(const md_ctx *c, int64_t nsteps);
+int md_step_record(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps,
+                   double *stage, size_t stage_bytes);
+int md_step_vjp_recorded(md_ctx *c, const double *q0, double dt, int64_t nsteps, double *lam_q,
+                         double *lam_p, const double *stage, size_t stage_bytes);
+
 /* Destroy a context (does not touch the workspace).  NULL is accepted. */
 int md_destroy(md_ctx *c);
 

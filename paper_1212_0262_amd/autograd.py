@@ -7,7 +7,9 @@ respect to q0 and p0.  The forward pass runs ``md_step`` in segments of
 backward pass walks the segments in reverse, and for each one ``md_step_vjp``
 recomputes the segment from its checkpoint and sweeps the adjoints back through
 it (Hessian-vector products of the potential for the kicks).  Memory: one
-checkpoint per segment plus the stage buffer of one segment.
+checkpoint per segment plus the stage buffer of one segment.  With
+``checkpoint_every = 0`` the forward records every kick position instead and the
+backward needs no recomputation (3 nsteps position arrays of device memory).
 
 Gradients are those of the discrete map (the integrator as computed), not of the
 exact flow.
@@ -17,6 +19,31 @@ from __future__ import annotations
 import torch
 
 from . import md
+
+
+class _RecordedTrajectory(torch.autograd.Function):
+    """No recomputation: the forward records every kick position (md_step_record)
+    and the backward sweeps over them (md_step_vjp_recorded)."""
+
+    @staticmethod
+    def forward(fctx, q0, p0, ctx, dt, nsteps):
+        q = q0.detach().clone()
+        p = p0.detach().clone()
+        f = torch.empty_like(q)
+        md.md_force(ctx, q, f)
+        start = q.clone()
+        stage = md.md_step_record(ctx, q, p, f, dt, nsteps)
+        fctx.save_for_backward(start, stage)
+        fctx.mdctx, fctx.dt, fctx.nsteps = ctx, dt, nsteps
+        return q, p
+
+    @staticmethod
+    def backward(fctx, gq, gp):
+        start, stage = fctx.saved_tensors
+        lq = (gq.detach().clone() if gq is not None else torch.zeros_like(start)).contiguous()
+        lp = (gp.detach().clone() if gp is not None else torch.zeros_like(start)).contiguous()
+        md.md_step_vjp_recorded(fctx.mdctx, start, fctx.dt, fctx.nsteps, lq, lp, stage)
+        return lq, lp, None, None, None
 
 
 class _Trajectory(torch.autograd.Function):
@@ -57,9 +84,15 @@ class _Trajectory(torch.autograd.Function):
 
 def trajectory(ctx: md.Context, q0: torch.Tensor, p0: torch.Tensor, dt: float, nsteps: int,
                checkpoint_every: int = 50):
-    """(q, p) after nsteps steps from (q0, p0); differentiable in q0 and p0."""
-    if checkpoint_every < 1:
-        raise ValueError("checkpoint_every must be >= 1")
+    """(q, p) after nsteps steps from (q0, p0); differentiable in q0 and p0.
+
+    checkpoint_every = k >= 1 keeps the state every k steps and recomputes each
+    segment in the backward pass; checkpoint_every = 0 records every kick position
+    instead (md_record_stage_bytes(ctx, nsteps) of device memory, no recompute)."""
+    if checkpoint_every < 0:
+        raise ValueError("checkpoint_every must be >= 0")
+    if checkpoint_every == 0:
+        return _RecordedTrajectory.apply(q0, p0, ctx, float(dt), int(nsteps))
     return _Trajectory.apply(q0, p0, ctx, float(dt), int(nsteps), int(checkpoint_every))
 
 

@@ -213,26 +213,15 @@ int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t ns
 // the same reduction order, as md_step on aligned arrays).
 size_t vjp_slot(const md_ctx *c) { return ((size_t)dims(c->model) * (size_t)c->n + 1) & ~(size_t)1; }
 
-// Reverse sweep of nsteps steps (see md_step_vjp).  stage = [q | p | f | P_1 .. P_3n],
-// each a slot holding [d][n]; P_m are the positions at which the kicks evaluate the
-// force (P_0 = q0).
-int step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps, double *lq, double *lp,
-             double *stage)
+// Reverse sweep over nsteps recorded steps: pos(m) are the positions at which the
+// kicks evaluated the force (pos(0) = q0, then P_1 .. P_3n, slot doubles apart).
+int reverse_pairs(md_ctx *c, const double *q0, const double *P, size_t slot, double dt, int64_t nsteps, double *lq,
+                  double *lp)
 {
     double B0, B1, D0, D1;
     yoshida(&B0, &B1, &D0, &D1);
-    const size_t len = (size_t)dims(c->model) * c->n, slot = vjp_slot(c);
-    double *qw = stage, *pw = stage + slot, *fw = stage + 2 * slot, *P = stage + 3 * slot;
     auto pos = [&](int64_t m) -> const double * { return m == 0 ? q0 : P + (size_t)(m - 1) * slot; };
-    MD_TRY(hipMemcpyAsync(qw, q0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy q");
-    MD_TRY(hipMemcpyAsync(pw, p0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy p");
-    // forward recompute, keeping the kick positions
-    MD_TRY(update_(c, UPD_PREP, 0.0, 0.0, 0.0, qw, nullptr, nullptr), "vjp: operands");
-    MD_TRY(pair_(c, qw), "vjp: pair kernel");
-    MD_TRY(update_(c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, fw), "vjp: force");
-    int st = step_pairs(c, qw, pw, fw, dt, nsteps, P, slot);
-    if (st != MD_OK) return st;
-    // reverse: pending product at P_3n, kick weight B0 dt
+    // pending product at P_3n, kick weight B0 dt
     const int prep = ADJ_PREPQ | ADJ_PREPW;
     MD_TRY(launch_adj_update(c, prep, 0.0, 0.0, 0.0, lq, lp, nullptr, pos(3 * nsteps)), "vjp: operands");
     MD_TRY(launch_hvp_pair(c, pos(3 * nsteps), lp), "vjp: hvp");
@@ -254,6 +243,33 @@ int step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t n
         kick = s > 0 ? (ADJ_KICK | ADJ_KICK2) : ADJ_KICK;
     }
     MD_TRY(launch_adj_update(c, kick, B0 * dt, B0 * dt, 0.0, lq, lp, nullptr, nullptr), "vjp: last kick");
+    return MD_OK;
+}
+
+// HMF reverse sweep: as reverse_pairs, with the O(N) product -- per kick one pass
+// of sums over (P_m, lambda_p) and one elementwise pass that applies the kick and
+// the preceding drift.
+int reverse_hmf(md_ctx *c, const double *q0, const double *P, size_t slot, double dt, int64_t nsteps, double *lq,
+                double *lp)
+{
+    double B0, B1, D0, D1;
+    yoshida(&B0, &B1, &D0, &D1);
+    auto pos = [&](int64_t m) -> const double * { return m == 0 ? q0 : P + (size_t)(m - 1) * slot; };
+    MD_TRY(launch_hmf_hvp_sums(c, pos(3 * nsteps), lp), "vjp: sums");
+    int kick = ADJ_KICK;
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 3), kick | ADJ_DRIFT, B0 * dt, B0 * dt, D0 * dt, lq, lp, nullptr),
+               "vjp: update");
+        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s + 2), lp), "vjp: sums");
+        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 2), ADJ_KICK | ADJ_DRIFT, B1 * dt, 0.0, D1 * dt, lq, lp, nullptr),
+               "vjp: update");
+        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s + 1), lp), "vjp: sums");
+        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 1), ADJ_KICK | ADJ_DRIFT, B1 * dt, 0.0, D0 * dt, lq, lp, nullptr),
+               "vjp: update");
+        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s), lp), "vjp: sums");
+        kick = s > 0 ? (ADJ_KICK | ADJ_KICK2) : ADJ_KICK;
+    }
+    MD_TRY(launch_hmf_adj_update(c, q0, kick, B0 * dt, B0 * dt, 0.0, lq, lp, nullptr), "vjp: last kick");
     return MD_OK;
 }
 
@@ -288,39 +304,29 @@ int step_hmf(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nste
     return MD_OK;
 }
 
-// HMF reverse sweep: as step_vjp, with the O(N) product -- per kick one pass of
-// sums over (P_m, lambda_p) and one elementwise pass that applies the kick and the
-// preceding drift.  stage = [q | p | f | P_1 .. P_3n], one slot each.
-int step_vjp_hmf(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps, double *lq, double *lp,
-                 double *stage)
+// md_step_vjp: recompute the steps from (q0, p0) into stage = [q | p | f | P_1 .. P_3n]
+// (one slot each), then sweep back.
+int step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t nsteps, double *lq, double *lp,
+             double *stage)
 {
-    double B0, B1, D0, D1;
-    yoshida(&B0, &B1, &D0, &D1);
-    const size_t len = (size_t)c->n, slot = vjp_slot(c);
+    const size_t len = (size_t)dims(c->model) * c->n, slot = vjp_slot(c);
     double *qw = stage, *pw = stage + slot, *fw = stage + 2 * slot, *P = stage + 3 * slot;
-    auto pos = [&](int64_t m) -> const double * { return m == 0 ? q0 : P + (size_t)(m - 1) * slot; };
     MD_TRY(hipMemcpyAsync(qw, q0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy q");
     MD_TRY(hipMemcpyAsync(pw, p0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy p");
-    MD_TRY(launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, qw, nullptr, nullptr, nullptr, false), "vjp: reduce");
-    MD_TRY(launch_hmf_pass(c, HMF_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, nullptr, fw, false), "vjp: force");
-    int st = step_hmf(c, qw, pw, fw, dt, nsteps, P, slot);
-    if (st != MD_OK) return st;
-    MD_TRY(launch_hmf_hvp_sums(c, pos(3 * nsteps), lp), "vjp: sums");
-    int kick = ADJ_KICK;
-    for (int64_t s = nsteps - 1; s >= 0; --s) {
-        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 3), kick | ADJ_DRIFT, B0 * dt, B0 * dt, D0 * dt, lq, lp, nullptr),
-               "vjp: update");
-        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s + 2), lp), "vjp: sums");
-        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 2), ADJ_KICK | ADJ_DRIFT, B1 * dt, 0.0, D1 * dt, lq, lp, nullptr),
-               "vjp: update");
-        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s + 1), lp), "vjp: sums");
-        MD_TRY(launch_hmf_adj_update(c, pos(3 * s + 1), ADJ_KICK | ADJ_DRIFT, B1 * dt, 0.0, D0 * dt, lq, lp, nullptr),
-               "vjp: update");
-        MD_TRY(launch_hmf_hvp_sums(c, pos(3 * s), lp), "vjp: sums");
-        kick = s > 0 ? (ADJ_KICK | ADJ_KICK2) : ADJ_KICK;
+    int st;
+    if (c->model == MD_HMF) {
+        MD_TRY(launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, qw, nullptr, nullptr, nullptr, false), "vjp: reduce");
+        MD_TRY(launch_hmf_pass(c, HMF_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, nullptr, fw, false), "vjp: force");
+        st = step_hmf(c, qw, pw, fw, dt, nsteps, P, slot);
+        if (st != MD_OK) return st;
+        return reverse_hmf(c, q0, P, slot, dt, nsteps, lq, lp);
     }
-    MD_TRY(launch_hmf_adj_update(c, q0, kick, B0 * dt, B0 * dt, 0.0, lq, lp, nullptr), "vjp: last kick");
-    return MD_OK;
+    MD_TRY(update_(c, UPD_PREP, 0.0, 0.0, 0.0, qw, nullptr, nullptr), "vjp: operands");
+    MD_TRY(pair_(c, qw), "vjp: pair kernel");
+    MD_TRY(update_(c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, fw), "vjp: force");
+    st = step_pairs(c, qw, pw, fw, dt, nsteps, P, slot);
+    if (st != MD_OK) return st;
+    return reverse_pairs(c, q0, P, slot, dt, nsteps, lq, lp);
 }
 
 // ------------------------------------------------------------ batched ensembles --
@@ -833,8 +839,57 @@ int md_step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_
     if (nsteps == 0) return MD_OK;
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_step_vjp: set device");
-    return c->model == MD_HMF ? step_vjp_hmf(c, q0, p0, dt, nsteps, lam_q, lam_p, stage)
-                              : step_vjp(c, q0, p0, dt, nsteps, lam_q, lam_p, stage);
+    return step_vjp(c, q0, p0, dt, nsteps, lam_q, lam_p, stage);
+}
+
+size_t md_record_stage_bytes(const md_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return 0;
+    return (size_t)(3 * nsteps) * vjp_slot(c) * sizeof(double);
+}
+
+int md_step_record(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps, double *stage,
+                   size_t stage_bytes)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (c->batch) return fail(c, MD_EUNSUPPORTED, "md_step_record: single systems only");
+    if (c->model == MD_HMF && c->prec != MD_FP64)
+        return fail(c, MD_EUNSUPPORTED, "md_step_record: HMF needs an FP64-state context");
+    if (!q || !p || !f || !stage || !aligned8(q) || !aligned8(p) || !aligned8(f) || !aligned8(stage))
+        return fail(c, MD_EINVAL, "md_step_record: null or misaligned pointer");
+    if (!isfinite(dt)) return fail(c, MD_EINVAL, "md_step_record: dt must be finite");
+    if (nsteps < 0) return fail(c, MD_EINVAL, "md_step_record: nsteps must be >= 0");
+    if (stage_bytes < md_record_stage_bytes(c, nsteps))
+        return fail(c, MD_ENOMEM, "md_step_record: stage buffer needs %zu bytes", md_record_stage_bytes(c, nsteps));
+    if (nsteps == 0) return MD_OK;
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_step_record: set device");
+    const size_t slot = vjp_slot(c);
+    return c->model == MD_HMF ? step_hmf(c, q, p, f, dt, nsteps, stage, slot)
+                              : step_pairs(c, q, p, f, dt, nsteps, stage, slot);
+}
+
+int md_step_vjp_recorded(md_ctx *c, const double *q0, double dt, int64_t nsteps, double *lam_q, double *lam_p,
+                         const double *stage, size_t stage_bytes)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (c->batch) return fail(c, MD_EUNSUPPORTED, "md_step_vjp_recorded: single systems only");
+    if (!q0 || !lam_q || !lam_p || !stage || !aligned8(q0) || !aligned8(lam_q) || !aligned8(lam_p) ||
+        !aligned8(stage))
+        return fail(c, MD_EINVAL, "md_step_vjp_recorded: null or misaligned pointer");
+    if (!isfinite(dt)) return fail(c, MD_EINVAL, "md_step_vjp_recorded: dt must be finite");
+    if (nsteps < 0) return fail(c, MD_EINVAL, "md_step_vjp_recorded: nsteps must be >= 0");
+    if (stage_bytes < md_record_stage_bytes(c, nsteps))
+        return fail(c, MD_ENOMEM, "md_step_vjp_recorded: stage buffer needs %zu bytes",
+                    md_record_stage_bytes(c, nsteps));
+    if (nsteps == 0) return MD_OK;
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_step_vjp_recorded: set device");
+    const size_t slot = vjp_slot(c);
+    return c->model == MD_HMF ? reverse_hmf(c, q0, stage, slot, dt, nsteps, lam_q, lam_p)
+                              : reverse_pairs(c, q0, stage, slot, dt, nsteps, lam_q, lam_p);
 }
 
 int md_destroy(md_ctx *c)

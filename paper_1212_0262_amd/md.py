@@ -53,6 +53,9 @@ SIGNATURES = {
     "md_hvp": (_I, [_V, _V, _V, _V]),
     "md_vjp_stage_bytes": (_SZ, [_V, _I64]),
     "md_step_vjp": (_I, [_V, _V, _V, _D, _I64, _V, _V, _V, _SZ]),
+    "md_record_stage_bytes": (_SZ, [_V, _I64]),
+    "md_step_record": (_I, [_V, _V, _V, _V, _D, _I64, _V, _SZ]),
+    "md_step_vjp_recorded": (_I, [_V, _V, _D, _I64, _V, _V, _V, _SZ]),
     "md_destroy": (_I, [_V]),
     "md_strerror": (ctypes.c_char_p, [_I]),
     "md_last_error": (ctypes.c_char_p, [_V]),
@@ -282,6 +285,31 @@ def md_step_vjp(ctx: Context, q0: torch.Tensor, p0: torch.Tensor, dt: float, nst
     ctx._check(load().md_step_vjp(ctx.handle, ctx._arr(q0, "q0"), ctx._arr(p0, "p0"), float(dt), int(nsteps),
                                   ctx._arr(lam_q, "lam_q"), ctx._arr(lam_p, "lam_p"), stage.data_ptr(),
                                   stage.numel() * stage.element_size()), "md_step_vjp")
+
+
+def md_record_stage_bytes(ctx: Context, nsteps: int) -> int:
+    return int(load().md_record_stage_bytes(ctx.handle, int(nsteps)))
+
+
+def md_step_record(ctx: Context, q: torch.Tensor, p: torch.Tensor, f: torch.Tensor, dt: float, nsteps: int,
+                   stage: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """md_step that also records every kick position into stage (allocated here
+    if None); returns stage for md_step_vjp_recorded."""
+    need = md_record_stage_bytes(ctx, nsteps)
+    if stage is None:
+        stage = torch.empty(max(need, 8), dtype=torch.uint8, device=q.device)
+    ctx._check(load().md_step_record(ctx.handle, ctx._arr(q, "q"), ctx._arr(p, "p"), ctx._arr(f, "f"), float(dt),
+                                     int(nsteps), stage.data_ptr(), stage.numel() * stage.element_size()),
+               "md_step_record")
+    return stage
+
+
+def md_step_vjp_recorded(ctx: Context, q0: torch.Tensor, dt: float, nsteps: int, lam_q: torch.Tensor,
+                         lam_p: torch.Tensor, stage: torch.Tensor) -> None:
+    """In place: the reverse sweep over a run recorded by md_step_record from q0."""
+    ctx._check(load().md_step_vjp_recorded(ctx.handle, ctx._arr(q0, "q0"), float(dt), int(nsteps),
+                                           ctx._arr(lam_q, "lam_q"), ctx._arr(lam_p, "lam_p"), stage.data_ptr(),
+                                           stage.numel() * stage.element_size()), "md_step_vjp_recorded")
 
 
 def md_destroy(ctx: Context) -> None:

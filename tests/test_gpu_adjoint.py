@@ -212,3 +212,59 @@ def test_magnetization_gradient_matches_oracle_and_finite_differences(model, eps
         ad = float(np.sum(gq * vq) + np.sum(gp * vp))
         print(f"magnetization grad model={model} ad={ad:.12e} fd={fd:.12e}")
         assert abs(ad - fd) < 1e-7 * max(1.0, abs(fd)), (ad, fd)
+
+
+@pytest.mark.parametrize("model,prec,eps,dt,n,launch", [
+    (GRAV2D, md.FP64, 1e-3, 0.01, 501, md.LAUNCH_FUSED), (GRAV2D, md.MIXED, 1e-3, 0.01, 501, md.LAUNCH_STAGED),
+    (RING, md.FP64, 0.01, 0.05, 2048, md.LAUNCH_FUSED), (RING, md.MIXED_KAHAN, 0.01, 0.05, 300, md.LAUNCH_STAGED),
+    (HMF, md.FP64, 0.0, 0.1, 20_001, md.LAUNCH_AUTO)])
+def test_recorded_run_matches_md_step_and_vjp(model, prec, eps, dt, n, launch):
+    """md_step_record = md_step bit for bit; the sweep over the recording =
+    md_step_vjp (which recomputes the same steps) bit for bit."""
+    nst = 7
+    q0, p0 = _state(model, n, seed=66)
+    ctx = md.md_init(model, prec, n, eps)
+    md.md_set_launch(ctx, launch)
+    qd, pd = dev(q0), dev(p0)
+    f0 = torch.empty_like(qd)
+    md.md_force(ctx, qd, f0)
+    qa, pa, fa = qd.clone(), pd.clone(), f0.clone()
+    md.md_step(ctx, qa, pa, fa, dt, nst)
+    qb, pb, fb = qd.clone(), pd.clone(), f0.clone()
+    stage = md.md_step_record(ctx, qb, pb, fb, dt, nst)
+    for x, y in ((qa, qb), (pa, pb), (fa, fb)):
+        np.testing.assert_array_equal(host(x), host(y))
+    rng = np.random.default_rng(12)
+    l0q, l0p = rng.normal(size=q0.shape), rng.normal(size=p0.shape)
+    aq, ap = dev(l0q), dev(l0p)
+    md.md_step_vjp(ctx, qd, pd, dt, nst, aq, ap)
+    bq, bp = dev(l0q), dev(l0p)
+    md.md_step_vjp_recorded(ctx, qd, dt, nst, bq, bp, stage)
+    np.testing.assert_array_equal(host(aq), host(bq))
+    np.testing.assert_array_equal(host(ap), host(bp))
+
+
+def test_recorded_gradient_equals_checkpointed():
+    n, nst, eps, dt = 1000, 40, 1e-2, 0.01
+    q0, p0 = _state(GRAV2D, n, seed=67)
+    ctx = md.md_init(GRAV2D, md.FP64, n, eps)
+    Ka, gqa, gpa = mdgrad.kinetic_energy_gradient(ctx, dev(q0), dev(p0), dt, nst, checkpoint_every=7)
+    Kb, gqb, gpb = mdgrad.kinetic_energy_gradient(ctx, dev(q0), dev(p0), dt, nst, checkpoint_every=0)
+    assert float(Ka) == float(Kb)
+    np.testing.assert_array_equal(host(gqa), host(gqb))
+    np.testing.assert_array_equal(host(gpa), host(gpb))
+
+
+def test_record_rejections():
+    hmf = md.md_init(HMF, md.MIXED_F32STATE, 100, 0.0)
+    h = torch.zeros((1, 100), dtype=torch.float64, device="cuda")
+    with pytest.raises(md.MDError):
+        md.md_step_record(hmf, h, h.clone(), h.clone(), 0.1, 2)
+    ctx = md.md_init(GRAV2D, md.FP64, 100, 1e-3)
+    q = torch.zeros((2, 100), dtype=torch.float64, device="cuda")
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(md.MDError):
+        md.md_step_record(ctx, q, q.clone(), q.clone(), 0.01, 2, small)
+    with pytest.raises(md.MDError):
+        md.md_step_vjp_recorded(ctx, q, 0.01, 2, q.clone(), q.clone(), small)
+    assert md.md_record_stage_bytes(ctx, 5) == 15 * 200 * 8
