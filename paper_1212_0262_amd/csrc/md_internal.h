@@ -123,7 +123,6 @@ inline double force_prefactor(int model, int prec, int64_t n)
 
 // Launchers return hipSuccess or the launch error.  All enqueue on c->stream.
 // pair.hip
-hipError_t launch_prep(md_ctx *c, const double *q);
 hipError_t launch_pair(md_ctx *c, const double *q);
 // snap (nullable): with UPD_DRIFT, the drifted positions are also written there.
 hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift,

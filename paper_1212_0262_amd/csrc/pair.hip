@@ -461,12 +461,6 @@ hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
 
 }  // namespace
 
-hipError_t launch_prep(md_ctx *c, const double *q)
-{
-    if (prep_kind(c, false) == PREP_NONE) return hipSuccess;
-    return update(c, UPD_PREP, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr, nullptr, c->ops, false);
-}
-
 hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
                          double *f, double *snap)
 {

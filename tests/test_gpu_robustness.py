@@ -123,3 +123,33 @@ def test_random_small_systems_match_oracle(model, prec, n, ipl, waves, split, jt
         assert np.all(fg == 0.0)
     else:
         assert rel_inf(fg, fo) < FORCE_TOL[(model, prec)]
+
+
+@settings(max_examples=30, deadline=None, derandomize=True)
+@given(model=st.sampled_from([RING, GRAV2D]),
+       prec=st.sampled_from([md.FP64, md.MIXED, md.MIXED_KAHAN, md.MIXED_PAIRF64]),
+       n=st.integers(min_value=1, max_value=3000),
+       ipl=st.sampled_from([1, 2, 4]),
+       split=st.integers(min_value=1, max_value=64), jtile=st.sampled_from([16, 32, 80, 128, 4096]),
+       seed=st.integers(min_value=0, max_value=10_000))
+def test_random_fused_equals_staged(model, prec, n, ipl, split, jtile, seed):
+    """Any tiles the fused launch accepts: md_step bit for bit equal to the staged
+    launch (two steps, so the alternating operand buffers are both used)."""
+    eps, dt = (1e-3, 0.01) if model == GRAV2D else (0.01, 0.05)
+    q0, p0 = inputs.grav2d_disk(n, seed=seed) if model == GRAV2D else inputs.ring_waterbag(n, seed=seed)
+    ctx = md.md_init(model, prec, n, eps)
+    md.md_set_tiles(ctx, ipl, 4, min(split, md.md_max_j_split(n)), jtile)
+    try:
+        md.md_set_launch(ctx, md.LAUNCH_FUSED)
+    except md.MDError:
+        return  # tiles the fused block cannot hold: covered by the validation test
+    outs = []
+    for launch in (md.LAUNCH_FUSED, md.LAUNCH_STAGED):
+        md.md_set_launch(ctx, launch)
+        q, p = dev(q0), dev(p0)
+        f = torch.empty_like(q)
+        md.md_force(ctx, q, f)
+        md.md_step(ctx, q, p, f, dt, 2)
+        outs.append((host(q), host(p), host(f)))
+    for x, y in zip(*outs):
+        np.testing.assert_array_equal(x, y)
