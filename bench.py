@@ -689,8 +689,8 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; run it with --gpus 1",
+              file=sys.stderr)
         return 2
     if args.steps is None:
         args.steps = {"grav2d": 100, "ring": 50, "hmf": 1000, "ensemble": 200, "adjoint": 1000,
