@@ -622,6 +622,13 @@ def grav2d_workload(md, torch, args):
         fp64 = run_variant(md, torch, md.FP64, q0, p0, args.steps, args.warmup)
         log(f"bench: fp64 {fp64['gpairs_per_s']:.1f} Gpairs/s, {fp64['ms_per_step']:.2f} ms/step, "
             f"dE/E={fp64['dE_E']:.2e}")
+    variants = {}
+    if fp64 is not None and not args.no_variants:
+        # the other accumulations of the FP32 pair terms
+        for name, prec in (("mixed_kahan", md.MIXED_KAHAN), ("mixed_pairf64", md.MIXED_PAIRF64)):
+            log(f"bench: {name}")
+            variants[name] = run_variant(md, torch, prec, q0, p0, args.steps, args.warmup)
+            log(f"bench: {name} {variants[name]['gpairs_per_s']:.1f} Gpairs/s")
     cpu = None
     if not args.no_cpu:
         log("bench: cpu baseline (oracle)")
@@ -674,6 +681,16 @@ def grav2d_workload(md, torch, args):
         }
         # precision gate: the energy error the mixed form adds to the FP64 run
         out["energy"]["gate_mixed_vs_fp64_dE_over_E0_le_1e-5"] = bool(prec_err <= 1e-5)
+        out["accumulation_variants"] = {
+            "mixed_tile_fold": {"value": round(mixed["gpairs_per_s"], 3), "energy_diff_over_absE0": prec_err,
+                                "gate_le_1e-5": bool(prec_err <= 1e-5)}}
+        for name, v in variants.items():
+            err = abs(v["E1"][2] - fp64["E1"][2]) / abs(fp64["E0"][2])
+            out["accumulation_variants"][name] = {
+                "value": round(v["gpairs_per_s"], 3), "ms_per_step": round(v["ms_per_step"], 4),
+                "pair_tflops": round(FLOPS_PER_PAIR * N * N / (v["pair_ms_avg"] * 1e-3) / 1e12, 3),
+                "dE_E": v["dE_E"], "energy_diff_over_absE0": err, "gate_le_1e-5": bool(err <= 1e-5),
+                "max_abs_dq_vs_fp64": (v["final_q"] - fp64["final_q"]).abs().max().item()}
     return out
 
 
@@ -686,6 +703,8 @@ def main() -> int:
                     default="grav2d")
     ap.add_argument("--no-fp64", action="store_true", help="grav2d: skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="grav2d: skip the Kahan and per-pair FP64 accumulation runs")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
