@@ -616,6 +616,10 @@ def grav2d_workload(md, torch, args):
     mixed = run_variant(md, torch, md.MIXED, q0, p0, args.steps, args.warmup)
     log(f"bench: mixed {mixed['gpairs_per_s']:.1f} Gpairs/s, {mixed['ms_per_step']:.2f} ms/step, "
         f"dE/E={mixed['dE_E']:.2e}")
+    K0, V0, E0 = mixed["E0"]
+    if abs(E0) < 0.01 * (abs(K0) + abs(V0)):
+        log(f"bench: warning: E0 = {E0:.6g} is {abs(E0) / (abs(K0) + abs(V0)):.2g} of K0 + |V0| "
+            f"(K0 = {K0:.6g}, V0 = {V0:.6g}): |E - E0|/|E0| is ill-conditioned; see dE/(K0+|V0|)")
     fp64 = None
     if not args.no_fp64:
         log("bench: fp64")
@@ -658,6 +662,9 @@ def grav2d_workload(md, torch, args):
         "energy": {
             "mixed_dE_E": mixed["dE_E"], "mixed_dE_over_K0_plus_absV0": mixed["dE_KV"],
             "E0": mixed["E0"],
+            # E0 = K0 + V0 nearly cancels for this state (the log potential's mean over the disk
+            # offsets the kinetic energy), which inflates |E - E0| / |E0|
+            "E0_ill_conditioned": bool(abs(mixed["E0"][2]) < 0.01 * (abs(mixed["E0"][0]) + abs(mixed["E0"][1]))),
         },
         "cpu_baseline": cpu,
     }
