@@ -1,0 +1,109 @@
+"""The largest inputs the library accepts: HMF at n = 2^30, the O(N^2) pair kernel
+at n = 2^23, and an ensemble of 2^24 particles in total.  At these sizes the oracle
+cannot integrate the whole system, so each check is either a property that holds
+at any size or the oracle's own value on sampled outputs:
+
+  * HMF on the uniform lattice theta_k = 2 pi k / N: the magnetization of eq. 7 is
+    zero, so the force of eq. 6 vanishes, V = N/2 by eq. 5, and a step with a
+    common momentum c is a free rotation theta -> theta + c dt (FP64 and FP32 state);
+  * the 2D mixed force at n = 2^23 on 16 sampled rows against the oracle's rows;
+  * 1024 Ring realizations of 16384 particles (2^24 in total) against the oracle on
+    the first, a middle and the last realization.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_0262_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+md = pytest.importorskip("paper_1212_0262_amd.md")
+from gpu_helpers import dev, host, rel_inf  # noqa: E402
+from test_gpu_parity import FORCE_TOL  # noqa: E402
+
+HMF, RING, GRAV2D = md.HMF, md.RING, md.GRAV2D
+MAX_HMF_N = 1 << 30
+MAX_PAIR_N = 1 << 23
+MAX_BATCH_TOTAL = 1 << 24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_threads():
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def _lattice(n):
+    return (torch.arange(n, dtype=torch.float64, device="cuda") * (2.0 * np.pi / n)).view(1, n)
+
+
+@pytest.mark.parametrize("prec", [md.FP64, md.MIXED_F32STATE])
+def test_hmf_at_the_maximum_size(prec):
+    n = MAX_HMF_N
+    ctx = md.md_init(HMF, prec, n, 0.0)
+    q = _lattice(n)
+    f = torch.empty_like(q)
+    md.md_force(ctx, q, f)
+    m = host(md.md_magnetization(ctx, q))
+    assert np.abs(m).max() < 1e-12, m
+    assert float(f.abs().max()) < 1e-12
+    c, dt = 0.3, 0.1
+    p = torch.full_like(q, c)
+    e = host(md.md_energy(ctx, q, p))
+    assert abs(e[0] - 0.5 * c * c * n) < 1e-9 * n
+    assert abs(e[1] - n / 2) < 1e-9 * n
+    md.md_step(ctx, q, p, f, dt, 1)
+    d = q - (_lattice(n) + c * dt)
+    d = d - (2.0 * np.pi) * torch.round(d / (2.0 * np.pi))  # the FP32 state wraps angles to [-pi, pi)
+    tol = 1e-12 if prec == md.FP64 else 2e-6
+    assert float(d.abs().max()) < tol * 2 * np.pi
+    assert float((p - c).abs().max()) < tol
+    ctx.close()
+
+
+def test_hmf_one_past_the_maximum_is_rejected():
+    q = torch.zeros((1, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(md.MDError):
+        md.md_init(HMF, md.FP64, MAX_HMF_N + 1, 0.0, workspace=q)
+    assert md.md_workspace_bytes(HMF, md.FP64, MAX_HMF_N + 1) == 0
+
+
+def test_grav2d_mixed_force_at_the_maximum_size():
+    n, eps = MAX_PAIR_N, 1e-3
+    q0, _ = inputs.grav2d_disk(n, seed=93)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, eps)
+    qd = dev(q0)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    rows = np.sort(np.random.default_rng(93).choice(n, size=16, replace=False))
+    fo = oracle.force_rows(GRAV2D, q0, rows, eps)
+    fg = host(f)[:, rows]
+    err = rel_inf(fg, fo)
+    print(f"grav2d mixed n=2^23 sampled-row rel_err={err:.3e}")
+    assert err < FORCE_TOL[(GRAV2D, md.MIXED)], err
+    ctx.close()
+
+
+def test_ensemble_at_the_maximum_total():
+    nb, nper, eps = 1024, 16384, 0.01
+    assert nb * nper == MAX_BATCH_TOTAL
+    offsets = np.arange(nb + 1, dtype=np.int64) * nper
+    members = [inputs.ensemble_member(b, nper) for b in range(nb)]
+    q0 = np.concatenate([m[0] for m in members], axis=1)
+    ctx = md.md_batch_init(RING, md.MIXED_KAHAN, offsets, eps)
+    qd = dev(q0)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    fg = host(f)
+    for b in (0, nb // 2, nb - 1):
+        fo = oracle.force(RING, members[b][0], eps)
+        err = rel_inf(fg[:, b * nper:(b + 1) * nper], fo)
+        print(f"ensemble member {b} rel_err={err:.3e}")
+        assert err < FORCE_TOL[(RING, md.MIXED_KAHAN)], err
+    with pytest.raises(md.MDError):
+        md.md_batch_init(RING, md.MIXED_KAHAN, np.append(offsets, offsets[-1] + 1), eps)
+    ctx.close()
