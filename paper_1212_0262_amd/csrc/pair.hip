@@ -172,20 +172,22 @@ __global__ __launch_bounds__(256) void k_pair_ring(const T *__restrict__ cs, int
 // the fused stage, which cannot read q while other blocks drift it).
 enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_HALF32 = 2, PREP_SINCOS64 = 3, PREP_COPY64 = 4 };
 
-// The stage's work on coordinate d of particle i, given its force component fd:
-// store f, p += kick * f, q += drift * p, then the pair operands of the new q.
+// Which of q, p a stage reads.
+__host__ __device__ constexpr bool stage_reads_q(int flags) { return flags & (UPD_DRIFT | UPD_PREP); }
+__host__ __device__ constexpr bool stage_reads_p(int flags) { return flags & (UPD_KICK1 | UPD_KICK2 | UPD_DRIFT); }
+
+// The stage's work on coordinate d of particle i, given its force component fd
+// and its current q, p (read by the caller when the flags need them): store f,
+// p += kick * f, q += drift * p, then the pair operands of the new q.
 template <int PREP>
-__device__ __forceinline__ void stage_elem(int d, int i, int n, int npad, double fd, int flags,
-                                           double *__restrict__ f, double *__restrict__ p, double *__restrict__ q,
-                                           void *__restrict__ ops, double kick1, double kick2, double drift,
-                                           double *__restrict__ snap)
+__device__ __forceinline__ void stage_elem_v(int d, int i, int n, int npad, double fd, double qd, double pd,
+                                             int flags, double *__restrict__ f, double *__restrict__ p,
+                                             double *__restrict__ q, void *__restrict__ ops, double kick1,
+                                             double kick2, double drift, double *__restrict__ snap)
 {
     const size_t k = (size_t)d * n + i;
     if (flags & UPD_STORE_F) f[k] = fd;
-    double qd = 0.0;
-    if (flags & (UPD_DRIFT | UPD_PREP)) qd = q[k];
-    if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_DRIFT)) {
-        double pd = p[k];
+    if (stage_reads_p(flags)) {
         if (flags & UPD_KICK1) pd += kick1 * fd;
         if (flags & UPD_KICK2) pd += kick2 * fd;
         if (flags & (UPD_KICK1 | UPD_KICK2)) p[k] = pd;
@@ -212,6 +214,18 @@ __device__ __forceinline__ void stage_elem(int d, int i, int n, int npad, double
             static_cast<double *>(ops)[npad + i] = sn;
         }
     }
+}
+
+template <int PREP>
+__device__ __forceinline__ void stage_elem(int d, int i, int n, int npad, double fd, int flags,
+                                           double *__restrict__ f, double *__restrict__ p, double *__restrict__ q,
+                                           void *__restrict__ ops, double kick1, double kick2, double drift,
+                                           double *__restrict__ snap)
+{
+    const size_t k = (size_t)d * n + i;
+    const double qd = stage_reads_q(flags) ? q[k] : 0.0;
+    const double pd = stage_reads_p(flags) ? p[k] : 0.0;
+    stage_elem_v<PREP>(d, i, n, npad, fd, qd, pd, flags, f, p, q, ops, kick1, kick2, drift, snap);
 }
 
 // One kick-drift stage, elementwise over particles (eq. 4 and the step list of
@@ -296,6 +310,19 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
         a0[k] = r0[i];
         a1[k] = r1[i];
     }
+    // The stage's own q, p, fetched now so that their latency hides under the pair
+    // loop (the block owns these particles: nothing else writes them meanwhile).
+    const bool one_pass = IPL * D * IL <= (int)blockDim.x;
+    double q_pre = 0.0, p_pre = 0.0;
+    if (one_pass && (int)threadIdx.x < IPL * D * IL) {
+        const int it = threadIdx.x, s2 = it % IL, kd = it / IL;
+        const int i = i0 + IL * (kd / D) + s2;
+        if (i < n) {
+            const size_t kk = (size_t)(kd % D) * n + i;
+            if (stage_reads_q(flags)) q_pre = q[kk];
+            if (stage_reads_p(flags)) p_pre = p[kk];
+        }
+    }
     A acc0[IPL], acc1[IPL];
     auto term = [&](T x, T y) {
 #pragma unroll
@@ -360,7 +387,10 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
             } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
                 fd = f[(size_t)d * n + i];
             }
-            stage_elem<PREP>(d, i, n, npad, fd, flags, f, p, q, out, kick1, kick2, drift, snap);
+            if (one_pass)
+                stage_elem_v<PREP>(d, i, n, npad, fd, q_pre, p_pre, flags, f, p, q, out, kick1, kick2, drift, snap);
+            else
+                stage_elem<PREP>(d, i, n, npad, fd, flags, f, p, q, out, kick1, kick2, drift, snap);
         }
     }
 }
