@@ -1,6 +1,8 @@
 // api.hip -- the C ABI of libmd (md.h): argument validation, workspace carve-up,
-// tile configuration, and the driver of the fourth-order Yoshida composition
-// (Sec. 3, eq. 4) that sequences the kernels of pair.hip and hmf.hip.
+// tile configuration and launch form (staged or fused), the driver of the
+// fourth-order Yoshida composition (Sec. 3, eq. 4) that sequences the kernels of
+// pair.hip and hmf.hip, its reverse sweep over adjoint.hip's products, and the
+// batched-ensemble work lists of batch.hip.
 //
 // The Yoshida step (eq. 4 and the step list after it) as a kick-drift sequence,
 // with the force at the new positions used for the final kick and carried into

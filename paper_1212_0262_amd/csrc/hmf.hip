@@ -16,8 +16,11 @@
 //
 // Memory access: each lane moves W consecutive elements (16-byte vector loads and
 // stores: W = 2 in FP64, 4 in FP32), U vectors per grid-stride iteration, over a
-// grid of up to 16384 blocks; with two sincos per element this streams at about
-// 6.5 TB/s on MI355X.  Pointers that are not 16-byte aligned take W = 1.
+// grid of one block per 2048 particles (at most 16384 blocks).  Pointers that are
+// not 16-byte aligned take W = 1.
+//
+// Also here: the O(N) Hessian-vector product of the HMF potential (the mean-field
+// form of eqs. 6-7) and the elementwise stage of its reverse sweep.
 #include "device.h"
 #include "md_internal.h"
 

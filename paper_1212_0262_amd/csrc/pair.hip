@@ -2,7 +2,7 @@
 // 2D self-gravitating model (gradient of eq. 3), and the O(N) kick/drift stages
 // of the Yoshida composition (eq. 4) that surround them.
 //
-// Pair kernel design (gfx950, wave64):
+// Staged pair kernel design (gfx950, wave64):
 //   * i-tile in registers: each lane owns i_per_lane particles i, 64 apart.
 //   * j-stream broadcast: every lane of a wavefront walks the same j, so the j
 //     operands are wave-uniform loads that the compiler places in scalar
@@ -11,6 +11,9 @@
 //   * j-split: the j range is cut into j_split pieces computed by different
 //     blocks (grid.y) so that small N still fills 256 CUs; the partial sums are
 //     added in a fixed order by the update kernel (deterministic).
+// The fused small-N stage (k_fused, below) keeps the same j ranges and order but
+// moves them into one block per i tile, streams j through LDS, and adds the
+// partials and runs the update in the same launch.
 //   * self pair: contributes exactly zero (2D: dx = dy = 0; Ring: the numerator
 //     sin(ti)cos(tj) - cos(ti)sin(tj) is formed from rounded products, without
 //     fused multiply-add, so it is exactly 0 at j = i), so no mask is needed.
