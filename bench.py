@@ -316,9 +316,9 @@ def ensemble_workload(md, torch, args):
     torch.cuda.synchronize()
     default_tiles = md.md_get_tiles(ctx)
     with torch.cuda.stream(stream):
-        t_default = autotune.time_force(ctx, q)
+        t_default = autotune.time_step(ctx, q)
         best, table = autotune.tune(ctx, q, cache=None)
-    log(f"bench: ensemble tiles default {default_tiles} {t_default:.3f} ms/force, tuned {best} {table[0][1]:.3f} ms")
+    log(f"bench: ensemble tiles default {default_tiles} {t_default:.3f} ms/step, tuned {best} {table[0][1]:.3f} ms/step")
     with torch.cuda.stream(stream):
         e0 = md.md_energy(ctx, q, p).cpu().numpy()
         md.md_force(ctx, q, f)
@@ -394,7 +394,7 @@ def ensemble_workload(md, torch, args):
                    "precision": "mixed_kahan", "tiles": list(best), "tiles_default": list(default_tiles)},
         "roofline": None, "cpu_baseline": cpu,
         "ensemble": {"graph_ms": graph_ms, "eager_ms": eager_ms, "graph_equals_eager": same,
-                     "force_ms_default_tiles": t_default, "force_ms_tuned": table[0][1],
+                     "step_ms_default_tiles": t_default, "step_ms_tuned": table[0][1],
                      "tune_table_top5": [[list(t), ms] for t, ms in table[:5]],
                      "dE_E_max": float(dE.max()), "dE_E_median": float(np.median(dE)),
                      "fp64_dE_E_max": float(dE64.max()), "fp64_dE_E_median": float(np.median(dE64)),
@@ -606,6 +606,75 @@ def paper_errors_workload(md, torch, args):
     }
 
 
+# Seconds per step on one GK104 (half of a GTX 690), from the paper's Tables 1-3:
+# context for the MI355X numbers at the same N, not a target (other hardware,
+# initial conditions and eps not stated).
+PAPER_1GPU_S = {
+    "hmf": {100_000: 6.3e-4, 1_000_000: 4.0e-3, 10_000_000: 3.7e-2, 50_000_000: 1.81e-1},
+    "ring": {10_240: 0.04, 51_200: 0.95, 102_400: 3.9, 512_000: 97.5},
+    "grav2d": {10_240: 0.023, 20_480: 0.047, 102_400: 0.99, 512_000: 26.8, 1_024_000: 106.5},
+}
+
+
+def paper_tables_workload(md, torch, args):
+    """md_step time per step at every N of the paper's timing tables (Sec. 4,
+    Tables 1-3), FP64 and mixed, on synthetic states of the configurations'
+    shapes (HMF and Ring waterbags, 2D uniform disk; eps = 0.01 Ring, 1e-3 2D),
+    with the paper's single-GPU time beside each as context."""
+    from paper_1212_0262_amd import inputs
+    rows = []
+    budget_s = 1.5  # timed seconds per (model, precision, N)
+    for model_name, model in (("hmf", md.HMF), ("ring", md.RING), ("grav2d", md.GRAV2D)):
+        precs = (("fp64", md.FP64), ("mixed", md.MIXED_F32STATE if model == md.HMF else md.MIXED))
+        eps = {"hmf": 0.0, "ring": 0.01, "grav2d": 1e-3}[model_name]
+        dt = {"hmf": 0.1, "ring": 0.05, "grav2d": 0.01}[model_name]
+        for n, paper_s in PAPER_1GPU_S[model_name].items():
+            if model == md.HMF:
+                q0, p0 = inputs.hmf_waterbag(n, seed=2)
+            elif model == md.RING:
+                q0, p0 = inputs.ring_waterbag(n, seed=1)
+            else:
+                q0, p0 = inputs.grav2d_disk(n, seed=3)
+            row = {"model": model_name, "n": n, "paper_1gpu_s_per_step": paper_s}
+            for pname, prec in precs:
+                ctx = md.md_init(model, prec, n, eps)
+                q, p = torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda()
+                f = torch.empty_like(q)
+                md.md_force(ctx, q, f)
+                md.md_step(ctx, q, p, f, dt, 1)
+                torch.cuda.synchronize()
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                md.md_step(ctx, q, p, f, dt, 1)
+                ev1.record()
+                torch.cuda.synchronize()
+                one = ev0.elapsed_time(ev1) * 1e-3
+                steps = max(1, min(200, int(budget_s / max(one, 1e-6))))
+                ev0.record()
+                md.md_step(ctx, q, p, f, dt, steps)
+                ev1.record()
+                torch.cuda.synchronize()
+                t = ev0.elapsed_time(ev1) * 1e-3 / steps
+                row[pname + "_s_per_step"] = t
+                row[pname + "_speedup_vs_paper_1gpu"] = paper_s / t
+                if model != md.HMF:
+                    row[pname + "_gpairs_per_s"] = 3.0 * n * n / t / 1e9
+                row[pname + "_tiles"] = list(md.md_get_tiles(ctx))
+                ctx.close()
+            log(f"bench: {model_name} N={n}: fp64 {row['fp64_s_per_step']:.3e} s, mixed {row['mixed_s_per_step']:.3e} s "
+                f"per step (paper 1 GPU {paper_s:g} s)")
+            rows.append(row)
+    d2 = [r for r in rows if r["model"] == "grav2d"]
+    return {
+        "metric": "Gpair-interactions/s (2D gravity N=1,024,000, mixed), and every N of the paper's Tables 1-3",
+        "value": round(d2[-1]["mixed_gpairs_per_s"], 3), "unit": "Gpair-interactions/s",
+        "ms_per_step": round(1e3 * d2[-1]["mixed_s_per_step"], 4), "dtype": "f32",
+        "config": {"workload": "the N of the paper's timing tables: HMF 1e5-5e7, Ring 10,240-512,000, "
+                               "2D 10,240-1,024,000; FP64 and mixed"},
+        "roofline": None, "cpu_baseline": None, "paper_tables": rows,
+    }
+
+
 def grav2d_workload(md, torch, args):
     import numpy as np
 
@@ -706,7 +775,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 100 grav2d, 50 ring, 1000 hmf)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["grav2d", "ring", "hmf", "ensemble", "adjoint", "paper_errors"],
+    ap.add_argument("--workload", choices=["grav2d", "ring", "hmf", "ensemble", "adjoint", "paper_errors",
+                                           "paper_tables"],
                     default="grav2d")
     ap.add_argument("--no-fp64", action="store_true", help="grav2d: skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -720,7 +790,7 @@ def main() -> int:
         return 2
     if args.steps is None:
         args.steps = {"grav2d": 100, "ring": 50, "hmf": 1000, "ensemble": 200, "adjoint": 1000,
-                      "paper_errors": 0}[args.workload]
+                      "paper_errors": 0, "paper_tables": 0}[args.workload]
 
     import torch
 
@@ -732,7 +802,7 @@ def main() -> int:
     md.load()
     fn = {"grav2d": grav2d_workload, "ring": ring_workload, "hmf": hmf_workload,
           "ensemble": ensemble_workload, "adjoint": adjoint_workload,
-          "paper_errors": paper_errors_workload}[args.workload]
+          "paper_errors": paper_errors_workload, "paper_tables": paper_tables_workload}[args.workload]
     out = fn(md, torch, args)
     hib = out["unit"] not in ("s", "relative")
     line = {"metric": out.pop("metric"), "value": out.pop("value"), "unit": out.pop("unit"), "n_gpus": 1,

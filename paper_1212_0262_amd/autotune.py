@@ -1,10 +1,12 @@
 """Tile autotuner for the pair kernels of libmd.
 
-Times ``md_force`` (through the C ABI) for a set of tile configurations
-(i_per_lane, waves, j_split, j_tile) of a context on its actual input, keeps the
-fastest, and caches the choice in a JSON file keyed by the device architecture,
-model, precision and the problem's shape (N, or the realization sizes of a batch),
-so a later run can apply it with :func:`apply_cached` without timing again.
+Times one ``md_step`` with dt = 0 (every kernel of a step runs; the state does not
+change) for a set of tile configurations (i_per_lane, waves, j_split, j_tile) of a
+context on its actual input -- so each configuration is timed in the launch form
+``md_step`` takes with it (staged or fused) -- keeps the fastest, and caches the
+choice in a JSON file keyed by the device architecture, model, precision and the
+problem's shape (N, or the realization sizes of a batch), so a later run can apply
+it with :func:`apply_cached` without timing again.
 
 All configurations compute the same sums in different orders, so the choice
 changes results only at rounding level; it never changes what is computed.
@@ -56,6 +58,24 @@ def candidates(ctx: md.Context) -> list:
     return out
 
 
+def time_step(ctx: md.Context, q: torch.Tensor, reps: int = 3) -> float:
+    """Mean time in ms of one md_step with dt = 0 on the context's current tiles
+    (on copies: q is not modified)."""
+    qs = q.clone()
+    p = torch.zeros_like(q)
+    f = torch.empty_like(q)
+    md.md_force(ctx, qs, f)
+    md.md_step(ctx, qs, p, f, 0.0, 1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        md.md_step(ctx, qs, p, f, 0.0, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def time_force(ctx: md.Context, q: torch.Tensor, reps: int = 3) -> float:
     """Mean md_force time in ms on the context's current tiles."""
     f = torch.empty_like(q)
@@ -71,16 +91,18 @@ def time_force(ctx: md.Context, q: torch.Tensor, reps: int = 3) -> float:
 
 
 def tune(ctx: md.Context, q: torch.Tensor, configs: Optional[Iterable] = None, reps: int = 3,
-         cache: Optional[str] = DEFAULT_CACHE) -> tuple:
-    """Time every configuration, leave the fastest applied to ctx, record it in the
-    cache (if given); returns (best_tiles, [(tiles, ms), ...] sorted by time)."""
+         cache: Optional[str] = DEFAULT_CACHE, measure: str = "step") -> tuple:
+    """Time every configuration (one md_step, or md_force with measure="force"),
+    leave the fastest applied to ctx, record it in the cache (if given); returns
+    (best_tiles, [(tiles, ms), ...] sorted by time)."""
+    timer = time_step if measure == "step" else time_force
     table = []
     for t in (configs if configs is not None else candidates(ctx)):
         try:
             md.md_set_tiles(ctx, *t)
         except md.MDError:
             continue
-        table.append((md.md_get_tiles(ctx), time_force(ctx, q, reps)))
+        table.append((md.md_get_tiles(ctx), timer(ctx, q, reps)))
     table.sort(key=lambda r: r[1])
     best = table[0][0]
     md.md_set_tiles(ctx, *best)

@@ -500,10 +500,11 @@ int max_j_split(int64_t n)
     return s < 1 ? 1 : (int)s;
 }
 
-// Built-in tile choice (measured on MI355X, md_force at N = 2048 .. 262144): the
-// pair kernels are VALU-issue bound, so the aim is enough independent wavefronts
-// (several rounds of 8 per SIMD over 1024 SIMDs, which evens out the tail) while
-// each block keeps a j range long enough to amortise its i loads and its output.
+// Built-in tile choice (measured on MI355X, md_step at N = 512 .. 262144): the
+// pair kernels are VALU-issue bound at large N, so the aim there is enough
+// independent wavefronts (several rounds of 8 per SIMD over 1024 SIMDs, which
+// evens out the tail) while each block keeps a j range long enough to amortise
+// its i loads and its output; below that, fixed choices found by the autotuner.
 Tiles default_tiles(int model, int prec, int64_t n)
 {
     (void)model;
@@ -519,7 +520,12 @@ Tiles default_tiles(int model, int prec, int64_t n)
         return t;
     }
     t.ipl = n >= 65536 ? 2 : 1;
-    t.jtile = 128;
+    if (n < 131072) {
+        // staged, N = 8193 .. 131071: 32 j ranges measured best or within 3% for both
+        // models and both precisions (autotuner at N = 10240, 20480, 51200, 102400)
+        t.jsplit = max_j_split(n) < 32 ? max_j_split(n) : 32;
+        return t;
+    }
     const int64_t wi = (n + kWave * t.ipl - 1) / (kWave * t.ipl);
     const int64_t target = n >= 65536 ? 32768 : 16384;
     int64_t s = target / wi;
