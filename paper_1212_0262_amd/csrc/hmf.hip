@@ -16,7 +16,7 @@
 //
 // Memory access: each lane moves W consecutive elements (16-byte vector loads and
 // stores: W = 2 in FP64, 4 in FP32), U vectors per grid-stride iteration, over a
-// grid of one block per 2048 particles (at most 16384 blocks).  Pointers that are
+// grid of one block per 2048 particles (at most 32768 blocks).  Pointers that are
 // not 16-byte aligned take W = 1.
 //
 // Also here: the O(N) Hessian-vector product of the HMF potential (the mean-field
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restr
 
 // M[0..1] = (sum of the g partial pairs) / n, in a fixed order (one block of
 // 1024 threads; thread t adds partials t, t + 1024, ... in that order).  All of a
-// thread's loads are issued before the adds (g <= kHmfGrid = 16 * 1024).
+// thread's loads are issued before the adds (g <= kHmfGrid = 32 * 1024).
 __global__ __launch_bounds__(1024) void k_hmf_finalize(const double *__restrict__ red, int g, int n,
                                                        double *__restrict__ M)
 {
@@ -292,7 +292,9 @@ static int vec_width(bool f32, const void *a, const void *b, const void *c, cons
 
 // Blocks of an HMF pass: 2048 particles per block (two grid-stride iterations of
 // W = 2 at kUnroll = 2); measured at N = 1e7 against 1024 (7% slower: each block's
-// closing reduction is amortised over fewer particles) and 4096 (2% slower).
+// closing reduction is amortised over fewer particles) and 4096 (2% slower).  At
+// most kHmfGrid blocks (N = 6.7e7); above that the grid strides.  Capping at 16384
+// instead made N = 5e7 8% slower.
 int hmf_grid(int64_t n)
 {
     const int64_t per_block = 256 * kUnroll * 2 * 2;

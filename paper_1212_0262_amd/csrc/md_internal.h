@@ -36,8 +36,8 @@ enum : int {
 
 constexpr int kWave = 64;           // lanes per wavefront (CDNA)
 constexpr int kMaxJSplit = 64;
-constexpr int kRedSlots = 1 << 16;   // doubles of reduction scratch
-constexpr int kHmfGrid = 16384;      // most blocks of an HMF pass (2 FP64 partials each)
+constexpr int kRedSlots = 1 << 17;   // doubles of reduction scratch (HMF pass partials: first half)
+constexpr int kHmfGrid = 32768;      // most blocks of an HMF pass (2 FP64 partials each)
 constexpr int kEnergyBlock = 256;
 constexpr int64_t kFusedMaxN = 65536;   // contexts up to this n carry the fused stage's operand buffers
 constexpr int kFusedMaxWaves = 16;      // wavefronts per fused block

@@ -277,6 +277,38 @@ def test_grav2d_full_size_sampled_rows(prec):
     assert rel_inf(fg[:, rows], fo) < tol
 
 
+@pytest.fixture(scope="module")
+def hmf_full_reference():
+    """The oracle's 10 FP64 steps of the HMF workload at its full size."""
+    n, nst = 10_000_000, 10
+    q, p = inputs.hmf_waterbag(n, seed=2)
+    f = oracle.force(HMF, q)
+    qo, po, fo = oracle.step(HMF, q, p, f, 0.1, nst, 0.0)
+    return q, p, qo, po, fo, oracle.energy(HMF, q, p), oracle.energy(HMF, qo, po), nst
+
+
+@pytest.mark.parametrize("prec", [md.FP64, md.MIXED_F32STATE])
+def test_hmf_config_full_size(prec, hmf_full_reference):
+    """HMF at the workload's size, N = 10^7 (waterbag theta in [-1, 1], p in
+    [-1.2, 1.2], dt = 0.1, the benchmark's grid): 10 steps against the oracle.
+    FP64 to rounding; the FP32 state to the FP32 energy bar (angles compared
+    modulo 2 pi: that state wraps them)."""
+    q, p, qo, po, fo, e0, eo, nst = hmf_full_reference
+    n = q.shape[-1]
+    qg, pg, fg, eg = gpu_run(HMF, prec, q, p, 0.0, 0.1, nst)
+    scale = abs(e0[0]) + abs(e0[1]) + n / 2
+    if prec == md.FP64:
+        assert np.abs(qg - qo).max() < 1e-10
+        assert np.abs(pg - po).max() < 1e-10
+        assert np.abs(fg - fo).max() < 1e-10
+        assert abs(eg[-1, 2] - eo[2]) < 1e-12 * scale
+    else:
+        d = qg - qo
+        assert np.abs(d - 2 * np.pi * np.round(d / (2 * np.pi))).max() < 1e-4
+        assert np.abs(pg - po).max() < 1e-4
+        assert abs(eg[-1, 2] - eo[2]) < 1e-5 * scale
+
+
 def test_hmf_config_reduced():
     """HMF waterbag (theta in [-1, 1], p in [-1.2, 1.2]), dt = 0.1, FP64 vs oracle
     on 10^5 particles, 30 steps."""
