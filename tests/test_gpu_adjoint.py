@@ -268,3 +268,32 @@ def test_record_rejections():
     with pytest.raises(md.MDError):
         md.md_step_vjp_recorded(ctx, q, 0.01, 2, q.clone(), q.clone(), small)
     assert md.md_record_stage_bytes(ctx, 5) == 15 * 200 * 8
+
+
+def test_adjoint_config_full_size_reduced_steps():
+    """The adjoint workload's system at its full size (2D, N = 32768, eps = 1e-3,
+    uniform disk, seed 5, dt = 0.01) over 50 steps with checkpoints every 10: the
+    gradient of K_T against FP64 central differences along 2 random unit
+    directions, and the recorded gradient equal to the checkpointed one."""
+    n, nst, eps, dt = 32768, 50, 1e-3, 0.01
+    q0, p0 = inputs.grav2d_disk(n, seed=5)
+    ctx = md.md_init(GRAV2D, md.FP64, n, eps)
+    K, gq, gp = mdgrad.kinetic_energy_gradient(ctx, dev(q0), dev(p0), dt, nst, checkpoint_every=10)
+    Kr, gqr, gpr = mdgrad.kinetic_energy_gradient(ctx, dev(q0), dev(p0), dt, nst, checkpoint_every=0)
+    assert float(K) == float(Kr) and torch.equal(gq, gqr) and torch.equal(gp, gpr)
+
+    def J(q, p):
+        qd, pd = dev(q), dev(p)
+        f = torch.empty_like(qd)
+        md.md_force(ctx, qd, f)
+        md.md_step(ctx, qd, pd, f, dt, nst)
+        return 0.5 * float((pd * pd).sum())
+    gq, gp = host(gq), host(gp)
+    for k in range(2):
+        v = np.random.default_rng([5, k]).normal(size=(4, n))
+        v /= np.linalg.norm(v)
+        h = 1e-4
+        fd = (J(q0 + h * v[:2], p0 + h * v[2:]) - J(q0 - h * v[:2], p0 - h * v[2:])) / (2 * h)
+        ad = float(np.sum(gq * v[:2]) + np.sum(gp * v[2:]))
+        print(f"adjoint full size dir {k}: ad={ad:.12e} fd={fd:.12e}")
+        assert abs(ad - fd) < 1e-6 * max(1.0, abs(fd)), (ad, fd)

@@ -144,6 +144,30 @@ def test_batch_trajectory_smallest_and_largest():
         assert np.abs(qg[b] - qo).max() < 1e-4 and np.abs(pg[b] - po).max() < 1e-4, b
 
 
+def test_ensemble_config_full_size():
+    """The ensemble workload at its full size: 256 Ring realizations, N_b drawn
+    log-uniform in [1000, 16384] (seed 4), eps = 0.01, Kahan-compensated FP32
+    pairs, the benchmark's tiles.  Forces of the 8 largest realizations and two
+    dt = 0.05 steps of the 8 smallest against the FP64 oracle."""
+    sizes = inputs.ensemble_sizes(256, seed=4)
+    q, p, off = ensemble(RING, sizes, seed=4)
+    ctx = md.md_batch_init(RING, md.MIXED_KAHAN, off, 0.01)
+    qd, pd = dev(q), dev(p)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    fg = split(host(f), off)
+    order = np.argsort(sizes)
+    for b in order[-8:]:
+        fo = oracle.force(RING, q[:, off[b]:off[b + 1]], 0.01)
+        assert rel_inf(fg[b], fo) < tol(md.MIXED_KAHAN, RING), b
+    md.md_step(ctx, qd, pd, f, 0.05, 2)
+    qg, pg = split(host(qd), off), split(host(pd), off)
+    for b in order[:8]:
+        qb, pb = q[:, off[b]:off[b + 1]], p[:, off[b]:off[b + 1]]
+        qo, po, _ = oracle.step(RING, qb, pb, oracle.force(RING, qb, 0.01), 0.05, 2, 0.01)
+        assert np.abs(qg[b] - qo).max() < 1e-5 and np.abs(pg[b] - po).max() < 1e-5, b
+
+
 def test_batch_graph_replay_matches_eager():
     """The whole multi-step update captured as one HIP graph: every replay (with
     eager work and synchronisation in between) equals the eager run, bit for bit."""
