@@ -309,6 +309,18 @@ def test_hmf_config_full_size(prec, hmf_full_reference):
         assert abs(eg[-1, 2] - eo[2]) < 1e-5 * scale
 
 
+@pytest.mark.parametrize("n", [131_071, 131_072])
+def test_ring_mixed_both_staged_kernels(n):
+    """The Ring FP32 forms use the LDS-window pair kernel below N = 131072 and the
+    scalar-load one from there on: sampled rows of both against the oracle."""
+    q, _ = inputs.ring_waterbag(n, seed=14)
+    rows = np.concatenate([np.random.default_rng(14).choice(n, size=48, replace=False), [0, n - 1]])
+    fo = oracle.force_rows(RING, q, rows, 0.01)
+    for prec in (md.MIXED, md.MIXED_KAHAN):
+        fg = gpu_force(RING, prec, q, 0.01)
+        assert rel_inf(fg[:, rows], fo) < FORCE_TOL[(RING, prec)], prec
+
+
 def test_hmf_config_reduced():
     """HMF waterbag (theta in [-1, 1], p in [-1.2, 1.2]), dt = 0.1, FP64 vs oracle
     on 10^5 particles, 30 steps."""
