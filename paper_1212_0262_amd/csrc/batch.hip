@@ -82,13 +82,6 @@ __global__ __launch_bounds__(256) void k_batch_pair_2d(const PairItem *__restric
     }
 }
 
-// Ring pair term: eq. 9 in FP64, the half-angle form in FP32 (see pair_terms.h).
-template <typename T, typename A>
-__device__ __forceinline__ void ring_term(T c0, T s0, T c1, T s1, T e, A &a)
-{
-    if constexpr (sizeof(T) == 8) pair_ring(c0, s0, c1, s1, e, a);
-    else pair_ring_half(s0, c0, s1, c1, e, a);
-}
 
 template <typename T, typename A, int IPL>
 __global__ __launch_bounds__(256) void k_batch_pair_ring(const PairItem *__restrict__ items, const T *__restrict__ cs,
@@ -279,6 +272,49 @@ __global__ __launch_bounds__(256) void k_batch_energy_finalize(const double *__r
     }
 }
 
+// Ring FP32 forms: the work item's j chunk through a block-shared LDS window (see
+// window_stream; the same terms in the same order as k_batch_pair_ring).
+constexpr int kWinJ = 512;
+
+template <typename T, typename A, int IPL>
+__global__ __launch_bounds__(256) void k_batch_pair_ring_win(const PairItem *__restrict__ items,
+                                                             const T *__restrict__ cs,
+                                                             const double *__restrict__ beps, int npad, int jtile,
+                                                             double *__restrict__ part)
+{
+    __shared__ T win[2][kWinJ];
+    const PairItem it = items[blockIdx.x];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int ibase = it.i0 + wave * (kWave * IPL) + lane;
+    const T e = (T)(2.0 * beps[it.b]);  // half-angle form: 2 eps
+    const T *__restrict__ cc = cs;
+    const T *__restrict__ ss = cs + npad;
+    T ci[IPL], si[IPL];
+    A a[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = min(ibase + kWave * k, it.i1 - 1);
+        ci[k] = cc[i];
+        si[k] = ss[i];
+    }
+    window_stream<kWinJ>(
+        cc, ss, it.j0, it.j1, jtile, win,
+        [&](T cj, T sj) {
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) ring_term(ci[k], si[k], cj, sj, e, a[k]);
+        },
+        [&]() {
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) a[k].fold();
+        });
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = ibase + kWave * k;
+        if (i < it.i1) part[(size_t)it.slot * npad + i] = a[k].get();
+    }
+}
+
 int prep_kind(const md_ctx *c)
 {
     if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? PREP_NONE : PREP_CAST32;
@@ -299,6 +335,13 @@ hipError_t pair_launch(md_ctx *c, const void *src)
         case 1: hipLaunchKernelGGL((k_batch_pair_2d<T, A, 1>), grid, block, 0, c->stream, items, x, y, B.d_eps, npad, jt, c->part); break;
         case 2: hipLaunchKernelGGL((k_batch_pair_2d<T, A, 2>), grid, block, 0, c->stream, items, x, y, B.d_eps, npad, jt, c->part); break;
         default: hipLaunchKernelGGL((k_batch_pair_2d<T, A, 4>), grid, block, 0, c->stream, items, x, y, B.d_eps, npad, jt, c->part); break;
+        }
+    } else if constexpr (sizeof(T) == 4) {
+        const T *cs = static_cast<const T *>(src);
+        switch (c->tiles.ipl) {
+        case 1: hipLaunchKernelGGL((k_batch_pair_ring_win<T, A, 1>), grid, block, 0, c->stream, items, cs, B.d_eps, npad, jt, c->part); break;
+        case 2: hipLaunchKernelGGL((k_batch_pair_ring_win<T, A, 2>), grid, block, 0, c->stream, items, cs, B.d_eps, npad, jt, c->part); break;
+        default: hipLaunchKernelGGL((k_batch_pair_ring_win<T, A, 4>), grid, block, 0, c->stream, items, cs, B.d_eps, npad, jt, c->part); break;
         }
     } else {
         const T *cs = static_cast<const T *>(src);

@@ -98,15 +98,6 @@ __global__ __launch_bounds__(256) void k_pair_2d(const T *__restrict__ xs, const
     }
 }
 
-// The Ring pair term of the context's precision: eq. 9 on (cos t, sin t) in FP64;
-// the half-angle form on sqrt2 (cos(t/2), sin(t/2)) in FP32 (then one_eps holds 2 eps).
-template <typename T, typename A>
-__device__ __forceinline__ void ring_term(T c0, T s0, T c1, T s1, T e, A &a)
-{
-    if constexpr (sizeof(T) == 8) pair_ring(c0, s0, c1, s1, e, a);
-    else pair_ring_half(s0, c0, s1, c1, e, a);
-}
-
 // Adds the Ring pair terms of j in [j0, j1) to each lane's IPL accumulators, in
 // the order every Ring kernel shares (j ascending, folds every jtile j).
 // cc, ss: the j operand rows (wave-uniform).
@@ -176,11 +167,12 @@ __global__ __launch_bounds__(256) void k_pair_ring(const T *__restrict__ cs, int
 // pipeline.  Same j ranges, order and folds as k_pair_2d / k_pair_ring, so the same
 // partials bit for bit.  r0, r1: the two operand rows.
 constexpr int kWinJ = 512;  // j per window
-// The staged launches that use it: the Ring FP32 forms below this n (measured 6-9%
-// faster at N = 10240 .. 102400).  The FP64 forms (8-byte operands) and the 2D
-// mixed form at large N measured 2-10% slower with the window; the 2D mixed form at
-// mid N within 2% either way.
-constexpr int kWinRingMaxN = 131072;
+// The Ring FP32 (half-angle) forms take this kernel at every N: measured 7-10%
+// faster than the scalar-load kernel with the per-tile fold and 13-14% with Kahan
+// (N = 10240 .. 512000).  Both j operands enter the same instructions there, and
+// the VALU takes few scalar operands, so scalar j operands cost extra moves; from
+// LDS they arrive in vector registers.  The FP64 forms (8-byte operands) and the
+// 2D forms measured 2-11% slower with the window.
 
 template <int MODEL, typename T, typename A, int IPL>
 __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, const T *__restrict__ r1, int n,
@@ -208,33 +200,13 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
             else ring_term(a0[k], a1[k], x, y, e, acc0[k]);
         }
     };
-    for (int g = j0; g < j1; g += 16) {
-        const int off = (g - j0) % kWinJ;
-        if (off == 0) {
-            __syncthreads();  // the previous window's reads are done
-            for (int m = threadIdx.x; m < kWinJ; m += blockDim.x) {
-                const int j = g + m;
-                if (j < j1) {
-                    win[0][m] = r0[j];
-                    win[1][m] = r1[j];
-                }
-            }
-            __syncthreads();
-        }
-        if (g + 16 <= j1) {
+    window_stream<kWinJ>(r0, r1, j0, j1, jtile, win, term, [&]() {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) term(win[0][off + u], win[1][off + u]);
-        } else {
-            for (int u = 0; u < j1 - g; ++u) term(win[0][off + u], win[1][off + u]);
+        for (int k = 0; k < IPL; ++k) {
+            acc0[k].fold();
+            if constexpr (MODEL == MD_GRAV2D) acc1[k].fold();
         }
-        if ((g + 16 - j0) % jtile == 0 || g + 16 >= j1) {
-#pragma unroll
-            for (int k = 0; k < IPL; ++k) {
-                acc0[k].fold();
-                if constexpr (MODEL == MD_GRAV2D) acc1[k].fold();
-            }
-        }
-    }
+    });
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int i = ibase + kWave * k;
@@ -551,23 +523,6 @@ template <typename T, typename A>
 hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
 {
     const int n = (int)c->n, npad = (int)c->npad, jt = c->tiles.jtile;
-    if constexpr (sizeof(T) == 4) {
-        if (c->model == MD_RING && n < kWinRingMaxN) {
-            const T *r0 = static_cast<const T *>(src);
-            const T *r1 = r0 + npad;
-            const T e = (T)(2.0 * c->eps);  // FP32 half-angle form
-#define MD_WIN(I_)                                                                                               \
-    hipLaunchKernelGGL((k_pair_win<MD_RING, T, A, I_>), grid, block, 0, c->stream, r0, r1, n, npad, jlen, jt, e, \
-                       c->part)
-            switch (c->tiles.ipl) {
-            case 1: MD_WIN(1); break;
-            case 2: MD_WIN(2); break;
-            default: MD_WIN(4); break;
-            }
-#undef MD_WIN
-            return hipGetLastError();
-        }
-    }
     if (c->model == MD_GRAV2D) {
         const T *x = static_cast<const T *>(src);
         const T *y = x + (src == c->ops ? npad : n);
@@ -577,9 +532,22 @@ hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
         case 2: hipLaunchKernelGGL((k_pair_2d<T, A, 2>), grid, block, 0, c->stream, x, y, n, npad, jlen, jt, eps, c->part); break;
         default: hipLaunchKernelGGL((k_pair_2d<T, A, 4>), grid, block, 0, c->stream, x, y, n, npad, jlen, jt, eps, c->part); break;
         }
+    } else if constexpr (sizeof(T) == 4) {
+        // Ring FP32 forms: the LDS-window kernel
+        const T *r0 = static_cast<const T *>(src);
+        const T e = (T)(2.0 * c->eps);  // half-angle form: 2 eps
+#define MD_WIN(I_)                                                                                                 \
+    hipLaunchKernelGGL((k_pair_win<MD_RING, T, A, I_>), grid, block, 0, c->stream, r0, r0 + npad, n, npad, jlen, jt, \
+                       e, c->part)
+        switch (c->tiles.ipl) {
+        case 1: MD_WIN(1); break;
+        case 2: MD_WIN(2); break;
+        default: MD_WIN(4); break;
+        }
+#undef MD_WIN
     } else {
         const T *cs = static_cast<const T *>(src);
-        const T one_eps = sizeof(T) == 8 ? (T)(1.0 + c->eps) : (T)(2.0 * c->eps);  // FP32 half-angle form: 2 eps
+        const T one_eps = (T)(1.0 + c->eps);
         switch (c->tiles.ipl) {
         case 1: hipLaunchKernelGGL((k_pair_ring<T, A, 1>), grid, block, 0, c->stream, cs, n, npad, jlen, jt, one_eps, c->part); break;
         case 2: hipLaunchKernelGGL((k_pair_ring<T, A, 2>), grid, block, 0, c->stream, cs, n, npad, jlen, jt, one_eps, c->part); break;

@@ -106,5 +106,48 @@ __device__ __forceinline__ void pair_ring_half(T ai, T bi, T aj, T bj, T eps2, A
     acc.add(a * b, r * r * r);
 }
 
+// The Ring pair term of the context's precision: eq. 9 on (cos t, sin t) in FP64;
+// the half-angle form on sqrt2 (cos(t/2), sin(t/2)) in FP32 (then e holds 2 eps).
+template <typename T, typename A>
+__device__ __forceinline__ void ring_term(T c0, T s0, T c1, T s1, T e, A &a)
+{
+    if constexpr (sizeof(T) == 8) pair_ring(c0, s0, c1, s1, e, a);
+    else pair_ring_half(s0, c0, s1, c1, e, a);
+}
+
+// Streams the j operands (rows r0, r1) of j in [j0, j1) through a block-shared
+// LDS window of WJ entries per row: the block loads each window with coalesced
+// vector loads between two barriers, and every lane reads the entries broadcast.
+// term(x, y) runs for every j in ascending order and fold() after every jtile j
+// counted from j0 and at j1 (jtile a multiple of 16): the order of the
+// scalar-load kernels, so the same sums bit for bit.  j0 and j1 must be uniform
+// across the block (every thread reaches the barriers).
+template <int WJ, typename T, typename Term, typename Fold>
+__device__ __forceinline__ void window_stream(const T *__restrict__ r0, const T *__restrict__ r1, int j0, int j1,
+                                              int jtile, T (*win)[WJ], Term &&term, Fold &&fold)
+{
+    for (int g = j0; g < j1; g += 16) {
+        const int off = (g - j0) % WJ;
+        if (off == 0) {
+            __syncthreads();  // the previous window's reads are done
+            for (int m = threadIdx.x; m < WJ; m += blockDim.x) {
+                const int j = g + m;
+                if (j < j1) {
+                    win[0][m] = r0[j];
+                    win[1][m] = r1[j];
+                }
+            }
+            __syncthreads();
+        }
+        if (g + 16 <= j1) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) term(win[0][off + u], win[1][off + u]);
+        } else {
+            for (int u = 0; u < j1 - g; ++u) term(win[0][off + u], win[1][off + u]);
+        }
+        if ((g + 16 - j0) % jtile == 0 || g + 16 >= j1) fold();
+    }
+}
+
 }  // namespace pairs
 }  // namespace md
