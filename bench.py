@@ -14,7 +14,8 @@ the relative energy error |E - E0| / |E0| (and the better conditioned
 |E - E0| / (K0 + |V0|)) is reported for both; the mixed figure counts only if
 its error is <= 1e-5.
 
-Also reported: the pair kernel's fraction of the FP32 VALU peak (roofline), and
+Also reported: the pair kernel's fraction of the FP32 vector peak (roofline), the
+SIMD cycles it spends per pair and wavefront, and
 the FP64 CPU oracle's pair throughput on a bounded sample of force rows of the
 same configuration (cpu_baseline).
 
@@ -42,9 +43,11 @@ DT = 0.01
 SEED = 3
 SIGMA = 0.5
 FLOPS_PER_PAIR = 10          # 2 sub, 2 FMA (r^2 + eps), 2 FMA (accumulate); plus one reciprocal
-PEAK_FP32_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32 (packed FP32 is not used)
-PEAK_FP32_PACKED_TFLOPS = 157.3
+VALU_PER_PAIR = 6            # the same six instructions, FP32, non-transcendental
+TRANS_PER_PAIR = 1           # v_rcp_f32
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (FMA = 2 flops)
 PEAK_FP64_TFLOPS = 78.6
+SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9   # 1024 SIMDs at 2.4 GHz
 PAIR_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("pair.hip", "pair_terms.h", "device.h")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "grav2d_pair_mixed_n262144_pmc.txt")
 
@@ -726,7 +729,9 @@ def grav2d_workload(md, torch, args):
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_from_profile(mixed["tiles"]),
             "kernel": "k_pair_2d<float, AccTile, ipl>",
             "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": N * N,
-            "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
+            "instr_per_pair": {"valu_fp32": VALU_PER_PAIR, "trans": TRANS_PER_PAIR},
+            # SIMD cycles each wavefront spends per pair (64 lanes, one pair each)
+            "cycles_per_pair_wave": round(SIMD_CYCLES_PER_S * 64 / (N * N / (mixed["pair_ms_avg"] * 1e-3)), 2),
         },
         "energy": {
             "mixed_dE_E": mixed["dE_E"], "mixed_dE_over_K0_plus_absV0": mixed["dE_KV"],
