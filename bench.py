@@ -48,6 +48,9 @@ TRANS_PER_PAIR = 1           # v_rcp_f32
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (FMA = 2 flops)
 PEAK_FP64_TFLOPS = 78.6
 SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9   # 1024 SIMDs at 2.4 GHz
+LAUNCH_NAMES = {1: "staged", 2: "fused", 3: "symmetric"}
+SYM_TILE = 1024              # particles per tile of the symmetric form
+SYM_FLOPS_PER_EVAL = 14      # symmetric form, per pair evaluated: 2 sub, 2 FMA (r^2), 2 FMA (i side), 2 FMA (j side)
 PAIR_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("pair.hip", "pair_terms.h", "device.h")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "grav2d_pair_mixed_n262144_pmc.txt")
 
@@ -65,19 +68,21 @@ def pair_kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(tiles):
-    """HBM bytes per pair-kernel launch from the committed counter summary, if it
-    was taken on the current kernel source with the same tiles; else None."""
+def traffic_from_profile(launch, tiles):
+    """HBM bytes per launch of the dominant pair kernel from the committed counter
+    summary, if it was taken on the current kernel source in the same launch form
+    (and, for the staged form, the same tiles); else None."""
     try:
         txt = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    f = re.search(r"launch:\s*(\w+)", txt)
     t = re.search(r"tiles_ipl_waves_jsplit_jtile:\s*([0-9, ]+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not (m and t and b) or m.group(1) != pair_kernel_hash():
+    if not (m and f and t and b) or m.group(1) != pair_kernel_hash() or f.group(1) != launch:
         return None
-    if [int(x) for x in t.group(1).replace(" ", "").split(",") if x] != list(tiles):
+    if launch == "staged" and [int(x) for x in t.group(1).replace(" ", "").split(",") if x] != list(tiles):
         return None
     return float(b.group(1))
 
@@ -107,6 +112,7 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup):
     ms = ev0.elapsed_time(ev1)
     e1 = md.md_energy(ctx, q, p).cpu().numpy()
     tiles = md.md_get_tiles(ctx)
+    launch = LAUNCH_NAMES[md.md_get_launch(ctx)]
     ctx.close()
     pairs = 3.0 * N * N * steps
     return {
@@ -117,7 +123,7 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup):
         "E0": e0.tolist(), "E1": e1.tolist(),
         "dE_E": abs(e1[2] - e0[2]) / abs(e0[2]),
         "dE_KV": abs(e1[2] - e0[2]) / (abs(e0[0]) + abs(e0[1])),
-        "tiles": list(tiles), "final_q": q, "final_p": p,
+        "tiles": list(tiles), "launch": launch, "final_q": q, "final_p": p,
     }
 
 
@@ -712,6 +718,21 @@ def grav2d_workload(md, torch, args):
         log(f"bench: cpu {cpu['value']:.3f} Gpairs/s on {cpu['cores']} threads")
 
     achieved = FLOPS_PER_PAIR * N * N / (mixed["pair_ms_avg"] * 1e-3) / 1e12
+    if mixed["launch"] == "symmetric":
+        # each pair is evaluated once for both particles; diagonal tiles take every ordered pair
+        nt = -(-N // SYM_TILE)
+        off = nt * (nt - 1) // 2 * SYM_TILE ** 2
+        diag = nt * SYM_TILE ** 2
+        executed = SYM_FLOPS_PER_EVAL * off + FLOPS_PER_PAIR * diag
+        kernel = "k_sym2d<true> (tile pairs) + k_sym2d<false> (diagonal tiles)"
+        instr = {"valu_fp32": 8, "trans": 1, "per": "pair evaluated (tile pairs: both particles)"}
+        evals = off + diag
+    else:
+        executed = FLOPS_PER_PAIR * N * N
+        kernel = "k_pair_2d<float, AccTile, ipl>"
+        instr = {"valu_fp32": VALU_PER_PAIR, "trans": TRANS_PER_PAIR, "per": "pair"}
+        evals = N * N
+    executed_tf = executed / (mixed["pair_ms_avg"] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": round(mixed["gpairs_per_s"], 3),
@@ -722,15 +743,19 @@ def grav2d_workload(md, torch, args):
             "workload": "grav2d uniform disk N=262144 eps=1e-3 dt=0.01 sigma=0.5 seed=3 (mixed: FP32 pairs, "
                         "FP64 fold per j-tile)",
             "model": "grav2d", "n": N, "eps": EPS, "dt": DT, "precision": "mixed",
-            "tiles_ipl_waves_jsplit_jtile": mixed["tiles"],
+            "launch": mixed["launch"], "tiles_ipl_waves_jsplit_jtile": mixed["tiles"],
         },
         "roofline": {
             "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_from_profile(mixed["tiles"]),
-            "kernel": "k_pair_2d<float, AccTile, ipl>",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": traffic_from_profile(mixed["launch"], mixed["tiles"]),
+            "kernel": kernel,
             "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": N * N,
-            "instr_per_pair": {"valu_fp32": VALU_PER_PAIR, "trans": TRANS_PER_PAIR},
-            # SIMD cycles each wavefront spends per pair (64 lanes, one pair each)
+            # what the kernels execute: the symmetric form evaluates each pair once
+            "executed_flops_per_launch": executed, "pair_evaluations_per_launch": evals,
+            "executed_tflops": round(executed_tf, 3), "frac_executed": round(executed_tf / PEAK_FP32_TFLOPS, 4),
+            "instr_per_evaluation": instr,
+            # SIMD cycles per interaction (pair of the N^2 count) and wavefront lane
             "cycles_per_pair_wave": round(SIMD_CYCLES_PER_S * 64 / (N * N / (mixed["pair_ms_avg"] * 1e-3)), 2),
         },
         "energy": {

@@ -45,6 +45,12 @@ bool prec_ok(int model, int prec)
 
 bool model_ok(int model) { return model == MD_HMF || model == MD_RING || model == MD_GRAV2D; }
 
+// Contexts that can take the symmetric 2D form (and carry its partial slots).
+bool sym_capable(int model, int prec, int64_t n)
+{
+    return model == MD_GRAV2D && prec == MD_MIXED && n >= kSymMinN && n <= kSymMaxN;
+}
+
 struct Layout {
     size_t red, scal, ops, wops, part, th32, p32, fops0, fops1, total;
 };
@@ -64,7 +70,11 @@ Layout layout(int model, int prec, int64_t n)
     L.wops = off;
     if (model != MD_HMF && prec != MD_FP64) off = align_up(off + (size_t)dims(model) * npad * sizeof(float));
     L.part = off;
-    if (model != MD_HMF) off = align_up(off + (size_t)max_j_split(n) * dims(model) * npad * sizeof(double));
+    if (model != MD_HMF) {
+        size_t slots = (size_t)max_j_split(n);
+        if (sym_capable(model, prec, n)) slots = std::max(slots, npad / kSymTile);
+        off = align_up(off + slots * dims(model) * npad * sizeof(double));
+    }
     L.th32 = off;
     if (model == MD_HMF && prec == MD_MIXED_F32STATE) off = align_up(off + npad * sizeof(float));
     L.p32 = off;
@@ -154,10 +164,15 @@ bool fused_ok(const md_ctx *c, const Tiles &t)
     return S <= kFusedMaxWaves && t.ipl * dims(c->model) * kWave * 8 <= kFusedLdsBytes / S;
 }
 
-// md_step's launch form for this context: MD_LAUNCH_STAGED or MD_LAUNCH_FUSED.
-int launch_form(const md_ctx *c)
+bool sym_ok(const md_ctx *c) { return !c->batch && sym_capable(c->model, c->prec, c->n); }
+
+// md_step's launch form for this context.
+int form_of(const md_ctx *c)
 {
-    if (c->launch == MD_LAUNCH_STAGED || !fused_ok(c, c->tiles)) return MD_LAUNCH_STAGED;
+    if (c->launch == MD_LAUNCH_SYMMETRIC || (c->launch == MD_LAUNCH_AUTO && c->n >= kSymAutoN))
+        if (sym_ok(c)) return MD_LAUNCH_SYMMETRIC;
+    if (c->launch == MD_LAUNCH_STAGED || c->launch == MD_LAUNCH_SYMMETRIC || !fused_ok(c, c->tiles))
+        return MD_LAUNCH_STAGED;
     if (c->launch == MD_LAUNCH_FUSED || c->n <= kFusedAutoN) return MD_LAUNCH_FUSED;
     return MD_LAUNCH_STAGED;
 }
@@ -170,7 +185,7 @@ int step_pairs(md_ctx *c, double *q, double *p, double *f, double dt, int64_t ns
     const int stage = UPD_F_FROM_PART | UPD_STORE_F | UPD_KICK1 | UPD_DRIFT | UPD_PREP;
     int64_t slot = 0;
     auto next = [&]() { return snap ? snap + (size_t)(slot++) * snap_stride : nullptr; };
-    if (launch_form(c) == MD_LAUNCH_FUSED) {
+    if (form_of(c) == MD_LAUNCH_FUSED) {
         // the same stage sequence as below, pair kernel and update in one launch;
         // the operand buffers alternate
         void *const buf[2] = {c->fops[0], c->fops[1]};
@@ -488,7 +503,9 @@ hipError_t upload_lists(md_ctx *c)
 
 }  // namespace
 
-int64_t pad_n(int64_t n) { return (n + 255) / 256 * 256; }
+int64_t pad_n(int64_t n) { return (n + kSymTile - 1) / kSymTile * kSymTile; }
+
+int launch_form(const md_ctx *c) { return form_of(c); }
 
 int dims(int model) { return model == MD_GRAV2D ? 2 : 1; }
 
@@ -716,8 +733,13 @@ int md_set_launch(md_ctx *c, int mode)
 {
     if (!c) return MD_EINVAL;
     c->err.clear();
-    if (mode != MD_LAUNCH_AUTO && mode != MD_LAUNCH_STAGED && mode != MD_LAUNCH_FUSED)
+    if (mode != MD_LAUNCH_AUTO && mode != MD_LAUNCH_STAGED && mode != MD_LAUNCH_FUSED &&
+        mode != MD_LAUNCH_SYMMETRIC)
         return fail(c, MD_EINVAL, "md_set_launch: unknown mode %d", mode);
+    if (mode == MD_LAUNCH_SYMMETRIC && !sym_ok(c))
+        return fail(c, MD_EUNSUPPORTED,
+                    "md_set_launch: the symmetric launch needs a single 2D system, MD_MIXED, %lld <= n <= %lld",
+                    (long long)kSymMinN, (long long)kSymMaxN);
     if (mode == MD_LAUNCH_FUSED && !fused_ok(c, c->tiles))
         return fail(c, MD_EUNSUPPORTED,
                     "md_set_launch: the fused launch needs a single Ring or 2D system with n <= %lld and tiles it "
@@ -731,7 +753,7 @@ int md_get_launch(const md_ctx *c)
 {
     if (!c) return MD_EINVAL;
     if (c->model == MD_HMF) return MD_LAUNCH_STAGED;
-    return launch_form(c);
+    return form_of(c);
 }
 
 int md_get_tiles(const md_ctx *c, int *out4)

@@ -43,6 +43,10 @@ constexpr int64_t kFusedMaxN = 65536;   // contexts up to this n carry the fused
 constexpr int kFusedMaxWaves = 16;      // wavefronts per fused block
 constexpr int kFusedLdsBytes = 49152;   // LDS per fused block (split evenly between its wavefronts)
 constexpr int64_t kFusedAutoN = 8192;   // MD_LAUNCH_AUTO takes the fused form up to this n
+constexpr int kSymTile = 1024;          // particles per tile of the symmetric 2D form (4 waves x 64 x 4 i)
+constexpr int64_t kSymMinN = 2048;      // the symmetric form needs two tiles at least
+constexpr int64_t kSymMaxN = 524288;    // and at most 512 tiles (its partial slots: 16 n^2 / 1024 bytes)
+constexpr int64_t kSymAutoN = MD_SYMMETRIC_AUTO_N;  // MD_LAUNCH_AUTO takes it from this n
 
 // Lane groups per wavefront of the fused stage for j_split j ranges: the largest
 // power of two <= 8 dividing j_split (more, smaller i tiles: more blocks).
@@ -93,13 +97,14 @@ struct md_ctx {
     // workspace carve-up
     void *ops = nullptr;      // pair operands: 2D [2][npad] FP32 copy; Ring [2][npad] cos,sin (FP32 or FP64)
     float *wops = nullptr;    // FP32 copy of the Hessian-vector product's vector (mixed forms)
-    double *part = nullptr;   // pair partials [jsplit][d][npad]
+    double *part = nullptr;   // pair partials [jsplit][d][npad]; symmetric form: [npad / kSymTile][d][npad]
     double *red = nullptr;    // reduction partials [kRedSlots]
     double *scal = nullptr;   // small device scalars (HMF magnetization, ...)
     float *th32 = nullptr;    // HMF FP32 state
     float *p32 = nullptr;
     void *fops[2] = {nullptr, nullptr};  // fused stage operands, alternating (n <= kFusedMaxN): [2][npad] of T
-    int launch = 0;                      // md_launch: auto / staged / fused
+    int launch = 0;                      // md_launch: auto / staged / fused / symmetric
+    bool sym_pad = false;                // the symmetric form's pad operands are written
     md::Tiles tiles;
     md::Batch *batch = nullptr;  // non-null for a batched ensemble (owned)
     std::string err;
@@ -108,8 +113,11 @@ struct md_ctx {
 
 namespace md {
 
-int64_t pad_n(int64_t n);
+int64_t pad_n(int64_t n);  // n rounded up to a multiple of kSymTile
 int dims(int model);
+// MD_LAUNCH_STAGED, MD_LAUNCH_FUSED or MD_LAUNCH_SYMMETRIC: the form the pair
+// stages of this context take now (launch mode, tiles and n).
+int launch_form(const md_ctx *c);
 int max_j_split(int64_t n);
 Tiles default_tiles(int model, int prec, int64_t n);
 int hmf_grid(int64_t n);  // blocks of the HMF passes (fixed per n: reproducible sums)
@@ -123,6 +131,7 @@ inline double force_prefactor(int model, int prec, int64_t n)
 
 // Launchers return hipSuccess or the launch error.  All enqueue on c->stream.
 // pair.hip
+// The pair partials of the context's launch form (staged or symmetric).
 hipError_t launch_pair(md_ctx *c, const double *q);
 // snap (nullable): with UPD_DRIFT, the drifted positions are also written there.
 hipError_t launch_update(md_ctx *c, int flags, double kick1, double kick2, double drift,

@@ -221,6 +221,146 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
     }
 }
 
+// ------------------------------------------------------ symmetric 2D kernels --
+
+// The 2D pair term of the gradient of eq. 3 is odd in r_i - r_j, so one
+// evaluation serves both particles (Newton's third law).  The particles are cut
+// into tiles of kSymTile = 4 wavefronts x 64 lanes x 4 i.  A block of k_sym2d<true>
+// owns a tile pair (a, b), a < b: its lanes hold the i of tile a in registers,
+// and tile b streams through in blocks of 64 j.  At step s of a 64-j block, lane
+// l pairs its 4 i with j = (l + s) mod 64: the j operands and the j-side sums
+// move one lane per step through ds_bpermute (the LDS crossbar, no VALU issue;
+// DPP lane moves measured 2-3x the cost of an FMA on gfx950), so every lane adds
+// to a different j and no atomics are needed.  Per pair: 2 differences, r^2 + eps
+// (2 FMA), 1 reciprocal, 2 FMA for the i side and 2 for the j side.
+//   i side: FP32 partial over 128 j, folded into FP64; the tile's sum goes to slot
+//           b of the i particles.
+//   j side: FP32 sum over the 256 i of a wavefront, the 4 wavefronts added in
+//           FP64 in a fixed order; the tile's sum goes to slot a of the j particles.
+// k_sym2d<false> takes a diagonal tile (a, a): every ordered pair of the tile, i
+// side only, into slot a.  Each particle thus receives one slot per tile and the
+// update kernel adds them in slot order: a fixed order, no atomics.
+// Pad particles (n .. npad - 1) sit at (1e30, 1e30): r^2 overflows to +inf for
+// any pair with a pad particle, the reciprocal is 0 and both terms are exactly
+// zero (a pad-pad pair has dx = dy = 0), so no mask is needed.
+constexpr int kSymIpl = 4, kSymWaves = kSymTile / (kWave * kSymIpl);
+constexpr float kSymPad = 1e30f;
+
+__device__ __forceinline__ float lane_next(int addr, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+
+// Tile pair (a, b), a < b, of linear index t in row-major order over a.
+__device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
+{
+    auto row0 = [ntile](int r) { return r * (2 * ntile - r - 1) / 2; };  // first index of row r
+    const double m = 2.0 * ntile - 1.0;
+    int r = (int)((m - sqrt(m * m - 8.0 * t)) * 0.5);
+    r = max(0, min(r, ntile - 2));
+    while (r > 0 && row0(r) > t) --r;
+    while (r + 1 <= ntile - 2 && row0(r + 1) <= t) ++r;
+    a = r;
+    b = r + 1 + (t - row0(r));
+}
+
+template <bool SYM>
+__global__ __launch_bounds__(kSymWaves * kWave) void k_sym2d(const float *__restrict__ xs,
+                                                             const float *__restrict__ ys, int npad, int ntile,
+                                                             float eps, double *__restrict__ part)
+{
+    constexpr int IPL = kSymIpl, NBLK = kSymTile / kWave;
+    __shared__ float jw[SYM ? kSymWaves : 1][2][SYM ? kSymTile : 1];
+    int a, b;
+    if (SYM) sym_tile_pair(blockIdx.x, ntile, a, b);
+    else a = b = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int i0 = a * kSymTile + wave * kWave * IPL + lane;
+    float xi[IPL], yi[IPL], ax[IPL], ay[IPL];
+    double tx[IPL], ty[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        xi[k] = xs[i0 + k * kWave];
+        yi[k] = ys[i0 + k * kWave];
+        ax[k] = ay[k] = 0.f;
+        tx[k] = ty[k] = 0.0;
+    }
+    const int next = ((lane + 1) & (kWave - 1)) * 4;  // ds_bpermute byte address of lane l + 1
+    const int jl = b * kSymTile + lane;
+    float xn = xs[jl], yn = ys[jl];
+    for (int blk = 0; blk < NBLK; ++blk) {
+        float xj = xn, yj = yn;
+        if (blk + 1 < NBLK) {
+            xn = xs[jl + (blk + 1) * kWave];
+            yn = ys[jl + (blk + 1) * kWave];
+        }
+        float sx = 0.f, sy = 0.f;  // j-side sums of the j this lane holds
+#pragma unroll 16
+        for (int s = 0; s < kWave; ++s) {
+            if (s) {
+                xj = lane_next(next, xj);
+                yj = lane_next(next, yj);
+                if (SYM) {
+                    sx = lane_next(next, sx);
+                    sy = lane_next(next, sy);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) {
+                const float dx = xj - xi[k], dy = yj - yi[k];
+                const float w = rcp32(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, eps)));
+                ax[k] = __builtin_fmaf(-dx, w, ax[k]);
+                ay[k] = __builtin_fmaf(-dy, w, ay[k]);
+                if (SYM) {
+                    sx = __builtin_fmaf(dx, w, sx);
+                    sy = __builtin_fmaf(dy, w, sy);
+                }
+            }
+        }
+        if (SYM) {  // after step 63 lane l holds j = l - 1 (mod 64) of the block
+            const int m = blk * kWave + ((lane + kWave - 1) & (kWave - 1));
+            jw[wave][0][m] = sx;
+            jw[wave][1][m] = sy;
+        }
+        if (blk & 1) {  // fold every 128 j
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) {
+                tx[k] += (double)ax[k];
+                ty[k] += (double)ay[k];
+                ax[k] = ay[k] = 0.f;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = i0 + k * kWave;
+        part[(size_t)(2 * b) * npad + i] = tx[k];
+        part[(size_t)(2 * b + 1) * npad + i] = ty[k];
+    }
+    if (SYM) {
+        __syncthreads();
+        for (int m = threadIdx.x; m < kSymTile; m += kSymWaves * kWave) {
+            double sx = 0.0, sy = 0.0;
+#pragma unroll
+            for (int w = 0; w < kSymWaves; ++w) {
+                sx += (double)jw[w][0][m];
+                sy += (double)jw[w][1][m];
+            }
+            part[(size_t)(2 * a) * npad + b * kSymTile + m] = sx;
+            part[(size_t)(2 * a + 1) * npad + b * kSymTile + m] = sy;
+        }
+    }
+}
+
+__global__ void k_fill_pad(float *__restrict__ ops, int n, int npad, float v)
+{
+    const int i = n + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npad) {
+        ops[i] = v;
+        ops[npad + i] = v;
+    }
+}
+
 // --------------------------------------------------------------- update kernel --
 
 // Operand refresh after a drift.  COPY64: an FP64 copy of q (2D FP64 operands of
@@ -465,7 +605,7 @@ hipError_t update(md_ctx *c, int flags, double kick1, double kick2, double drift
     const int n = (int)c->n;
     const dim3 block(256), grid((unsigned)((n + 255) / 256));
     const double pref = force_prefactor(c->model, c->prec, n);
-    const int S = c->tiles.jsplit;
+    const int S = !fused && launch_form(c) == MD_LAUNCH_SYMMETRIC ? (int)(c->npad / kSymTile) : c->tiles.jsplit;
     const int npad = (int)c->npad;
     const int pk = prep_kind(c, fused);
     if (pk == PREP_NONE) flags &= ~UPD_PREP;
@@ -610,6 +750,24 @@ hipError_t launch_fused(md_ctx *c, int flags, double kick1, double kick2, double
 // Pair partials of the current operands.  For FP64 2D the operands are q itself.
 hipError_t launch_pair(md_ctx *c, const double *q)
 {
+    if (launch_form(c) == MD_LAUNCH_SYMMETRIC) {
+        const int n = (int)c->n, npad = (int)c->npad, ntile = npad / kSymTile;
+        if (!c->sym_pad) {  // once per context: the update kernels never write past n
+            if (npad > n)
+                hipLaunchKernelGGL(k_fill_pad, dim3((unsigned)((npad - n + 255) / 256)), dim3(256), 0, c->stream,
+                                   static_cast<float *>(c->ops), n, npad, kSymPad);
+            c->sym_pad = true;
+        }
+        const float *xs = static_cast<const float *>(c->ops);
+        const dim3 block(kSymWaves * kWave);
+        const int noff = ntile * (ntile - 1) / 2;
+        if (noff > 0)
+            hipLaunchKernelGGL(k_sym2d<true>, dim3((unsigned)noff), block, 0, c->stream, xs, xs + npad, npad, ntile,
+                               (float)c->eps, c->part);
+        hipLaunchKernelGGL(k_sym2d<false>, dim3((unsigned)ntile), block, 0, c->stream, xs, xs + npad, npad, ntile,
+                           (float)c->eps, c->part);
+        return hipGetLastError();
+    }
     const Tiles &t = c->tiles;
     const int n = (int)c->n;
     const int per_block = kWave * t.ipl * t.waves;

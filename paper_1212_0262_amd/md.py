@@ -24,7 +24,8 @@ import torch  # noqa: F401  (must precede loading libmd: shared HIP runtime)
 HMF, RING, GRAV2D = 0, 1, 2
 FP64, MIXED, MIXED_KAHAN, MIXED_PAIRF64, MIXED_F32STATE = 0, 1, 2, 3, 4
 OK, EINVAL, EDEVICE, ENOMEM, ESTATE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-LAUNCH_AUTO, LAUNCH_STAGED, LAUNCH_FUSED = 0, 1, 2
+LAUNCH_AUTO, LAUNCH_STAGED, LAUNCH_FUSED, LAUNCH_SYMMETRIC = 0, 1, 2, 3
+SYMMETRIC_AUTO_N = 49152  # MD_SYMMETRIC_AUTO_N: LAUNCH_AUTO takes the symmetric 2D form from this n
 
 MODEL_NAMES = {HMF: "hmf", RING: "ring", GRAV2D: "grav2d"}
 PREC_NAMES = {FP64: "fp64", MIXED: "mixed", MIXED_KAHAN: "mixed_kahan",
@@ -223,12 +224,12 @@ def md_get_tiles(ctx: Context) -> tuple:
 
 
 def md_set_launch(ctx: Context, mode: int) -> None:
-    """LAUNCH_AUTO, LAUNCH_STAGED or LAUNCH_FUSED (md_step's launch form)."""
+    """LAUNCH_AUTO, LAUNCH_STAGED, LAUNCH_FUSED or LAUNCH_SYMMETRIC (md_step's launch form)."""
     ctx._check(load().md_set_launch(ctx.handle, int(mode)), "md_set_launch")
 
 
 def md_get_launch(ctx: Context) -> int:
-    """The form md_step takes: LAUNCH_STAGED or LAUNCH_FUSED."""
+    """The form md_step takes: LAUNCH_STAGED, LAUNCH_FUSED or LAUNCH_SYMMETRIC."""
     r = int(load().md_get_launch(ctx.handle))
     ctx._check(min(r, 0), "md_get_launch")
     return r

@@ -1,0 +1,187 @@
+"""The symmetric 2D launch form (MD_LAUNCH_SYMMETRIC): each pair evaluated once
+and added to both particles, the per-tile FP64 slots added in a fixed order.
+
+  * forces against the oracle at sizes that cover one and several tile pairs,
+    ragged last tiles (pad particles) and both sides of the form's size range,
+    with the mixed tolerance of the staged form (the pair terms are the same FP32
+    terms, grouped differently);
+  * agreement with the staged form to FP32 rounding, and bit-identical repeated
+    evaluations (no atomics);
+  * the total force vanishes to rounding: the i-side and j-side terms of a pair
+    are the same product with opposite signs;
+  * a short trajectory against the oracle's;
+  * the launch form md_get_launch reports, and the refusals of md_set_launch;
+  * a graph-captured step equal to the eager step on every replay.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_0262_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+md = pytest.importorskip("paper_1212_0262_amd.md")
+from gpu_helpers import dev, host, rel_inf  # noqa: E402
+from test_gpu_parity import FORCE_TOL  # noqa: E402
+
+GRAV2D, RING = md.GRAV2D, md.RING
+EPS = 1e-3
+TOL = FORCE_TOL[(GRAV2D, md.MIXED)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_threads():
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def _force(q, launch):
+    n = q.shape[-1]
+    ctx = md.md_init(GRAV2D, md.MIXED, n, EPS)
+    md.md_set_launch(ctx, launch)
+    assert md.md_get_launch(ctx) == launch
+    qd = dev(q)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    out = host(f)
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("n", [2048, 2049, 3000, 4096, 5120, 9999])
+def test_symmetric_force_matches_oracle(n):
+    q, _ = inputs.grav2d_disk(n, seed=300 + n)
+    fo = oracle.force(GRAV2D, q, EPS)
+    fg = _force(q, md.LAUNCH_SYMMETRIC)
+    err = rel_inf(fg, fo)
+    print(f"symmetric n={n} rel_err={err:.3e}")
+    assert err < TOL, err
+
+
+def test_symmetric_force_clustered_state():
+    """Two tight clusters far apart (large |F| from close pairs, and pairs that
+    cross tiles between the clusters)."""
+    n = 6000
+    rng = np.random.default_rng(17)
+    q = np.concatenate([rng.normal(-0.5, 0.02, size=(2, n // 2)), rng.normal(0.5, 0.02, size=(2, n - n // 2))], axis=1)
+    q = q[:, rng.permutation(n)]
+    fo = oracle.force(GRAV2D, q, EPS)
+    fg = _force(q, md.LAUNCH_SYMMETRIC)
+    err = rel_inf(fg, fo)
+    print(f"symmetric clustered n={n} rel_err={err:.3e}")
+    assert err < TOL, err
+
+
+@pytest.mark.parametrize("n", [40_000, 131_073])
+def test_symmetric_against_staged(n):
+    """Both forms sum the same FP32 pair terms in different groupings."""
+    q, _ = inputs.grav2d_disk(n, seed=7)
+    fs = _force(q, md.LAUNCH_SYMMETRIC)
+    ft = _force(q, md.LAUNCH_STAGED)
+    err = rel_inf(fs, ft)
+    print(f"symmetric vs staged n={n} rel_diff={err:.3e}")
+    assert err < TOL, err
+    rows = np.concatenate([np.random.default_rng(n).choice(n, size=16, replace=False), [0, n - 1]])
+    fo = oracle.force_rows(GRAV2D, q, rows, EPS)
+    assert rel_inf(fs[:, rows], fo) < TOL
+
+
+def test_symmetric_repeatable_and_momentum_free():
+    n = 70_001
+    q, _ = inputs.grav2d_disk(n, seed=11)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, EPS)
+    assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
+    qd = dev(q)
+    f1, f2 = torch.empty_like(qd), torch.empty_like(qd)
+    md.md_force(ctx, qd, f1)
+    md.md_force(ctx, qd, f2)
+    assert torch.equal(f1, f2)
+    fh = host(f1)
+    total = np.abs(fh.sum(axis=1)).max()
+    scale = np.abs(fh).sum(axis=1).max()
+    print(f"symmetric |sum f| = {total:.3e} of sum |f| = {scale:.3e}")
+    assert total < 1e-6 * scale
+    ctx.close()
+
+
+def test_symmetric_trajectory_matches_oracle():
+    n, nst, dt = 4096, 10, 0.01
+    q0, p0 = inputs.grav2d_disk(n, seed=21)
+    f0 = oracle.force(GRAV2D, q0, EPS)
+    qo, po, _ = oracle.step(GRAV2D, q0, p0, f0, dt, nst, EPS)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, EPS)
+    md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
+    qd, pd = dev(q0), dev(p0)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    md.md_step(ctx, qd, pd, f, dt, nst)
+    eq = np.abs(host(qd) - qo).max()
+    ep = np.abs(host(pd) - po).max()
+    e0 = oracle.energy(GRAV2D, q0, p0, EPS)
+    eg = host(md.md_energy(ctx, qd, pd))
+    eo = oracle.energy(GRAV2D, qo, po, EPS)
+    de = abs(eg[2] - eo[2]) / (abs(e0[0]) + abs(e0[1]))
+    print(f"symmetric trajectory: max|dq|={eq:.3e} max|dp|={ep:.3e} energy diff={de:.3e}")
+    assert eq < 1e-5 and ep < 1e-4 and de < 1e-5
+    ctx.close()
+
+
+def test_launch_form_and_refusals():
+    big = md.md_init(GRAV2D, md.MIXED, md.SYMMETRIC_AUTO_N, EPS)
+    assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
+    below = md.md_init(GRAV2D, md.MIXED, md.SYMMETRIC_AUTO_N - 1, EPS)
+    assert md.md_get_launch(below) != md.LAUNCH_SYMMETRIC
+    md.md_set_launch(below, md.LAUNCH_SYMMETRIC)
+    assert md.md_get_launch(below) == md.LAUNCH_SYMMETRIC
+    md.md_set_launch(big, md.LAUNCH_STAGED)
+    assert md.md_get_launch(big) == md.LAUNCH_STAGED
+    md.md_set_launch(big, md.LAUNCH_AUTO)
+    assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
+    for model, prec, n in [(GRAV2D, md.FP64, 50_000), (GRAV2D, md.MIXED_KAHAN, 50_000),
+                           (GRAV2D, md.MIXED_PAIRF64, 50_000), (RING, md.MIXED, 50_000),
+                           (GRAV2D, md.MIXED, 2047), (GRAV2D, md.MIXED, 524_289)]:
+        ctx = md.md_init(model, prec, n, EPS)
+        assert md.md_get_launch(ctx) != md.LAUNCH_SYMMETRIC
+        with pytest.raises(md.MDError):
+            md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
+        ctx.close()
+    batch = md.md_batch_init(GRAV2D, md.MIXED, [0, 3000, 6000], EPS)
+    with pytest.raises(md.MDError):
+        md.md_set_launch(batch, md.LAUNCH_SYMMETRIC)
+    for c in (big, below, batch):
+        c.close()
+
+
+def test_symmetric_step_graph_replays():
+    n, dt = 5000, 0.01
+    q0, p0 = inputs.grav2d_disk(n, seed=31)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, EPS)
+    md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
+    s = torch.cuda.Stream()
+    md.md_set_stream(ctx, s)
+    q, p = dev(q0), dev(p0)
+    f = torch.empty_like(q)
+    with torch.cuda.stream(s):
+        md.md_force(ctx, q, f)
+    s.synchronize()
+    qe, pe, fe = q.clone(), p.clone(), f.clone()
+    with torch.cuda.stream(s):
+        md.md_step(ctx, qe, pe, fe, dt, 4)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    qg, pg, fg = q.clone(), p.clone(), f.clone()
+    with torch.cuda.graph(g, stream=s):
+        md.md_step(ctx, qg, pg, fg, dt, 2)
+    for rep in range(3):
+        qg.copy_(q); pg.copy_(p); fg.copy_(f)
+        torch.cuda.synchronize()
+        g.replay(); g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(qg), host(qe))
+        np.testing.assert_array_equal(host(pg), host(pe))
+        np.testing.assert_array_equal(host(fg), host(fe))
+    ctx.close()
