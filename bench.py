@@ -9,7 +9,9 @@ state resident in HBM.  Throughput = 3 N^2 pair interactions per step (self
 pairs included, as in the paper's tiles) / elapsed time.
 
 The headline line is the mixed form (FP32 pair arithmetic, FP32 partials folded
-into FP64 per j-tile).  The FP64 form is timed beside it on the same steps, and
+into FP64) in md_step's automatic launch form, which at this N is the symmetric
+one (each pair evaluated once for both particles); the staged form (every ordered
+pair evaluated) is timed beside it.  The FP64 form is timed on the same steps, and
 the relative energy error |E - E0| / |E0| (and the better conditioned
 |E - E0| / (K0 + |V0|)) is reported for both; the mixed figure counts only if
 its error is <= 1e-5.
@@ -19,7 +21,8 @@ SIMD cycles it spends per pair and wavefront, and
 the FP64 CPU oracle's pair throughput on a bounded sample of force rows of the
 same configuration (cpu_baseline).
 
-Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-fp64] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-fp64] [--no-cpu] [--no-variants]
+                       [--launch auto|staged|symmetric]
        python bench.py --workload ring|hmf|ensemble|adjoint|paper_errors   (the other workloads)
 """
 from __future__ import annotations
@@ -87,10 +90,13 @@ def traffic_from_profile(launch, tiles):
     return float(b.group(1))
 
 
-def run_variant(md, torch, prec, q0, p0, steps, warmup):
-    """Time `steps` Yoshida steps of one precision form; returns a result dict."""
+def run_variant(md, torch, prec, q0, p0, steps, warmup, launch=None):
+    """Time `steps` Yoshida steps of one precision form (and launch form, if given);
+    returns a result dict."""
     stream = torch.cuda.current_stream()
     ctx = md.md_init(md.GRAV2D, prec, N, EPS, stream=stream)
+    if launch is not None:
+        md.md_set_launch(ctx, launch)
     q = torch.from_numpy(q0).cuda()
     p = torch.from_numpy(p0).cuda()
     f = torch.empty_like(q)
@@ -691,7 +697,8 @@ def grav2d_workload(md, torch, args):
     q0, p0 = inputs.grav2d_disk(N, seed=SEED, sigma=SIGMA)
 
     log(f"bench: mixed N={N} steps={args.steps} warmup={args.warmup}")
-    mixed = run_variant(md, torch, md.MIXED, q0, p0, args.steps, args.warmup)
+    launch = {"auto": md.LAUNCH_AUTO, "staged": md.LAUNCH_STAGED, "symmetric": md.LAUNCH_SYMMETRIC}[args.launch]
+    mixed = run_variant(md, torch, md.MIXED, q0, p0, args.steps, args.warmup, launch)
     log(f"bench: mixed {mixed['gpairs_per_s']:.1f} Gpairs/s, {mixed['ms_per_step']:.2f} ms/step, "
         f"dE/E={mixed['dE_E']:.2e}")
     K0, V0, E0 = mixed["E0"]
@@ -711,6 +718,12 @@ def grav2d_workload(md, torch, args):
             log(f"bench: {name}")
             variants[name] = run_variant(md, torch, prec, q0, p0, args.steps, args.warmup)
             log(f"bench: {name} {variants[name]['gpairs_per_s']:.1f} Gpairs/s")
+    staged = None
+    if not args.no_variants and mixed["launch"] == "symmetric":
+        # the staged form (each ordered pair evaluated) on the same steps, for comparison
+        log("bench: mixed, staged launch")
+        staged = run_variant(md, torch, md.MIXED, q0, p0, args.steps, args.warmup, md.LAUNCH_STAGED)
+        log(f"bench: mixed staged {staged['gpairs_per_s']:.1f} Gpairs/s")
     cpu = None
     if not args.no_cpu:
         log("bench: cpu baseline (oracle)")
@@ -767,6 +780,14 @@ def grav2d_workload(md, torch, args):
         },
         "cpu_baseline": cpu,
     }
+    if staged is not None:
+        out["mixed_staged"] = {
+            "value": round(staged["gpairs_per_s"], 3), "ms_per_step": round(staged["ms_per_step"], 4),
+            "tiles_ipl_waves_jsplit_jtile": staged["tiles"],
+            "symmetric_speedup": round(mixed["gpairs_per_s"] / staged["gpairs_per_s"], 3),
+            "energy_diff_vs_symmetric_over_absE0": abs(mixed["E1"][2] - staged["E1"][2]) / abs(staged["E0"][2]),
+            "max_abs_dq_vs_symmetric": (mixed["final_q"] - staged["final_q"]).abs().max().item(),
+        }
     if fp64 is not None:
         dq = (mixed["final_q"] - fp64["final_q"]).abs().max().item()
         dp = (mixed["final_p"] - fp64["final_p"]).abs().max().item()
@@ -811,7 +832,9 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true", help="grav2d: skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true",
-                    help="grav2d: skip the Kahan and per-pair FP64 accumulation runs")
+                    help="grav2d: skip the Kahan and per-pair FP64 accumulation runs and the staged-form timing")
+    ap.add_argument("--launch", choices=["auto", "staged", "symmetric"], default="auto",
+                    help="grav2d: launch form of the mixed run (auto: symmetric at this N)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
