@@ -225,30 +225,48 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 
 // The 2D pair term of the gradient of eq. 3 is odd in r_i - r_j, so one
 // evaluation serves both particles (Newton's third law).  The particles are cut
-// into tiles of kSymTile = 4 wavefronts x 64 lanes x 4 i.  A block of k_sym2d<true>
-// owns a tile pair (a, b), a < b: its lanes hold the i of tile a in registers,
-// and tile b streams through in blocks of 64 j.  At step s of a 64-j block, lane
-// l pairs its 4 i with j = (l + s) mod 64: the j operands and the j-side sums
-// move one lane per step through ds_bpermute (the LDS crossbar, no VALU issue;
-// DPP lane moves measured 2-3x the cost of an FMA on gfx950), so every lane adds
-// to a different j and no atomics are needed.  Per pair: 2 differences, r^2 + eps
-// (2 FMA), 1 reciprocal, 2 FMA for the i side and 2 for the j side.
-//   i side: FP32 partial over 128 j, folded into FP64; the tile's sum goes to slot
-//           b of the i particles.
-//   j side: FP32 sum over the 256 i of a wavefront, the 4 wavefronts added in
-//           FP64 in a fixed order; the tile's sum goes to slot a of the j particles.
-// k_sym2d<false> takes a diagonal tile (a, a): every ordered pair of the tile, i
-// side only, into slot a.  Each particle thus receives one slot per tile and the
-// update kernel adds them in slot order: a fixed order, no atomics.
-// Pad particles (n .. npad - 1) sit at (1e30, 1e30): r^2 overflows to +inf for
-// any pair with a pad particle, the reciprocal is 0 and both terms are exactly
-// zero (a pad-pad pair has dx = dy = 0), so no mask is needed.
+// into tiles of kSymTile = 4 wavefronts x 64 lanes x 4 i.  A block of
+// k_sym2d<T, true> owns a tile pair (a, b), a < b: its lanes hold the i of tile a
+// in registers, and tile b streams through in blocks of 64 j.  At step s of a
+// 64-j block, lane l pairs its 4 i with j = (l + s) mod 64: the j operands and
+// the j-side sums move one lane per step through ds_bpermute (the LDS crossbar,
+// no VALU issue; DPP lane moves measured 2-3x the cost of an FMA on gfx950), so
+// every lane adds to a different j and no atomics are needed.  Per pair: 2
+// differences, r^2 + eps (2 FMA), 1 reciprocal, 2 FMA for the i side and 2 for
+// the j side.
+//   FP32 (MD_MIXED):
+//     i side: FP32 partial over 128 j, folded into FP64; the tile's sum goes to
+//             slot b of the i particles.
+//     j side: FP32 sum over the 256 i of a wavefront; the 4 wavefronts are added
+//             in FP64 in a fixed order at the end of the tile, into slot a of the
+//             j particles.
+//   FP64: the same in FP64 throughout; the wavefronts' j-side sums are added
+//     (same order) after every 64-j block, through a small LDS buffer.
+// k_sym2d<T, false> takes a diagonal tile (a, a): every ordered pair of the
+// tile, i side only, into slot a.  Each particle thus receives one slot per tile
+// and the update kernel adds them in slot order: a fixed order, no atomics.
+// Pad particles (n .. npad - 1):
+//   FP32: at (1e30, 1e30): r^2 overflows to +inf for any pair with a pad
+//     particle, the reciprocal is 0 and both terms are exactly zero (a pad-pad
+//     pair has dx = dy = 0), so no mask is needed;
+//   FP64: at (1e150, 1e150): r^2 is about 2e300 (finite: the refined FP64
+//     reciprocal of +inf would be NaN), so a term with a pad particle is about
+//     5e-151, below the last bit of any force sum larger than 1e-135.
 constexpr int kSymIpl = 4, kSymWaves = kSymTile / (kWave * kSymIpl);
-constexpr float kSymPad = 1e30f;
+template <typename T> constexpr T sym_pad();
+template <> constexpr float sym_pad<float>() { return 1e30f; }
+template <> constexpr double sym_pad<double>() { return 1e150; }
 
 __device__ __forceinline__ float lane_next(int addr, float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_next(int addr, double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Tile pair (a, b), a < b, of linear index t in row-major order over a.
@@ -264,37 +282,39 @@ __device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
     b = r + 1 + (t - row0(r));
 }
 
-template <bool SYM>
-__global__ __launch_bounds__(kSymWaves * kWave) void k_sym2d(const float *__restrict__ xs,
-                                                             const float *__restrict__ ys, int npad, int ntile,
-                                                             float eps, double *__restrict__ part)
+template <typename T, bool SYM>
+__global__ __launch_bounds__(kSymWaves * kWave) void k_sym2d(const T *__restrict__ xs, const T *__restrict__ ys,
+                                                             int npad, int ntile, T eps, double *__restrict__ part)
 {
+    constexpr bool F32 = sizeof(T) == 4;
     constexpr int IPL = kSymIpl, NBLK = kSymTile / kWave;
-    __shared__ float jw[SYM ? kSymWaves : 1][2][SYM ? kSymTile : 1];
+    // FP32: the wavefronts' j-side sums of the whole tile; FP64: of one 64-j block
+    __shared__ float jw32[SYM && F32 ? kSymWaves : 1][2][SYM && F32 ? kSymTile : 1];
+    __shared__ double jw64[SYM && !F32 ? kSymWaves : 1][2][SYM && !F32 ? kWave : 1];
     int a, b;
     if (SYM) sym_tile_pair(blockIdx.x, ntile, a, b);
     else a = b = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int i0 = a * kSymTile + wave * kWave * IPL + lane;
-    float xi[IPL], yi[IPL], ax[IPL], ay[IPL];
-    double tx[IPL], ty[IPL];
+    T xi[IPL], yi[IPL], ax[IPL], ay[IPL];
+    double tx[IPL], ty[IPL];  // FP32: the folded i-side sums
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         xi[k] = xs[i0 + k * kWave];
         yi[k] = ys[i0 + k * kWave];
-        ax[k] = ay[k] = 0.f;
+        ax[k] = ay[k] = T(0);
         tx[k] = ty[k] = 0.0;
     }
     const int next = ((lane + 1) & (kWave - 1)) * 4;  // ds_bpermute byte address of lane l + 1
     const int jl = b * kSymTile + lane;
-    float xn = xs[jl], yn = ys[jl];
+    T xn = xs[jl], yn = ys[jl];
     for (int blk = 0; blk < NBLK; ++blk) {
-        float xj = xn, yj = yn;
+        T xj = xn, yj = yn;
         if (blk + 1 < NBLK) {
             xn = xs[jl + (blk + 1) * kWave];
             yn = ys[jl + (blk + 1) * kWave];
         }
-        float sx = 0.f, sy = 0.f;  // j-side sums of the j this lane holds
+        T sx = T(0), sy = T(0);  // j-side sums of the j this lane holds
 #pragma unroll 16
         for (int s = 0; s < kWave; ++s) {
             if (s) {
@@ -307,44 +327,57 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym2d(const float *__rest
             }
 #pragma unroll
             for (int k = 0; k < IPL; ++k) {
-                const float dx = xj - xi[k], dy = yj - yi[k];
-                const float w = rcp32(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, eps)));
-                ax[k] = __builtin_fmaf(-dx, w, ax[k]);
-                ay[k] = __builtin_fmaf(-dy, w, ay[k]);
+                const T dx = xj - xi[k], dy = yj - yi[k];
+                const T w = rcp_(fma_(dx, dx, fma_(dy, dy, eps)));
+                ax[k] = fma_(-dx, w, ax[k]);
+                ay[k] = fma_(-dy, w, ay[k]);
                 if (SYM) {
-                    sx = __builtin_fmaf(dx, w, sx);
-                    sy = __builtin_fmaf(dy, w, sy);
+                    sx = fma_(dx, w, sx);
+                    sy = fma_(dy, w, sy);
                 }
             }
         }
-        if (SYM) {  // after step 63 lane l holds j = l - 1 (mod 64) of the block
-            const int m = blk * kWave + ((lane + kWave - 1) & (kWave - 1));
-            jw[wave][0][m] = sx;
-            jw[wave][1][m] = sy;
+        // after step 63 lane l holds j = l - 1 (mod 64) of the block
+        const int jm = (lane + kWave - 1) & (kWave - 1);
+        if constexpr (SYM && F32) {
+            jw32[wave][0][blk * kWave + jm] = sx;
+            jw32[wave][1][blk * kWave + jm] = sy;
+        } else if constexpr (SYM) {
+            jw64[wave][0][jm] = sx;
+            jw64[wave][1][jm] = sy;
+            __syncthreads();
+            if (threadIdx.x < 2 * kWave) {
+                const int c = threadIdx.x / kWave, m = threadIdx.x & (kWave - 1);
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < kSymWaves; ++w) t += jw64[w][c][m];
+                part[(size_t)(2 * a + c) * npad + b * kSymTile + blk * kWave + m] = t;
+            }
+            __syncthreads();
         }
-        if (blk & 1) {  // fold every 128 j
+        if (F32 && (blk & 1)) {  // fold every 128 j
 #pragma unroll
             for (int k = 0; k < IPL; ++k) {
                 tx[k] += (double)ax[k];
                 ty[k] += (double)ay[k];
-                ax[k] = ay[k] = 0.f;
+                ax[k] = ay[k] = T(0);
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int i = i0 + k * kWave;
-        part[(size_t)(2 * b) * npad + i] = tx[k];
-        part[(size_t)(2 * b + 1) * npad + i] = ty[k];
+        part[(size_t)(2 * b) * npad + i] = F32 ? tx[k] : (double)ax[k];
+        part[(size_t)(2 * b + 1) * npad + i] = F32 ? ty[k] : (double)ay[k];
     }
-    if (SYM) {
+    if constexpr (SYM && F32) {
         __syncthreads();
         for (int m = threadIdx.x; m < kSymTile; m += kSymWaves * kWave) {
             double sx = 0.0, sy = 0.0;
 #pragma unroll
             for (int w = 0; w < kSymWaves; ++w) {
-                sx += (double)jw[w][0][m];
-                sy += (double)jw[w][1][m];
+                sx += (double)jw32[w][0][m];
+                sy += (double)jw32[w][1][m];
             }
             part[(size_t)(2 * a) * npad + b * kSymTile + m] = sx;
             part[(size_t)(2 * a + 1) * npad + b * kSymTile + m] = sy;
@@ -352,13 +385,35 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym2d(const float *__rest
     }
 }
 
-__global__ void k_fill_pad(float *__restrict__ ops, int n, int npad, float v)
+template <typename T>
+__global__ void k_fill_pad(T *__restrict__ ops, int n, int npad)
 {
     const int i = n + blockIdx.x * blockDim.x + threadIdx.x;
     if (i < npad) {
-        ops[i] = v;
-        ops[npad + i] = v;
+        ops[i] = sym_pad<T>();
+        ops[npad + i] = sym_pad<T>();
     }
+}
+
+template <typename T>
+hipError_t sym_launch(md_ctx *c)
+{
+    const int n = (int)c->n, npad = (int)c->npad, ntile = npad / kSymTile;
+    T *ops = static_cast<T *>(c->ops);
+    if (!c->sym_pad) {  // once per context: the update kernels never write past n
+        if (npad > n)
+            hipLaunchKernelGGL(k_fill_pad<T>, dim3((unsigned)((npad - n + 255) / 256)), dim3(256), 0, c->stream, ops,
+                               n, npad);
+        c->sym_pad = true;
+    }
+    const dim3 block(kSymWaves * kWave);
+    const int noff = ntile * (ntile - 1) / 2;
+    if (noff > 0)
+        hipLaunchKernelGGL((k_sym2d<T, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad, npad,
+                           ntile, (T)c->eps, c->part);
+    hipLaunchKernelGGL((k_sym2d<T, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad, npad, ntile,
+                       (T)c->eps, c->part);
+    return hipGetLastError();
 }
 
 // --------------------------------------------------------------- update kernel --
@@ -594,7 +649,11 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
 
 int prep_kind(const md_ctx *c, bool fused)
 {
-    if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? (fused ? PREP_COPY64 : PREP_NONE) : PREP_CAST32;
+    if (c->model == MD_GRAV2D) {
+        if (c->prec != MD_FP64) return PREP_CAST32;
+        // FP64: the fused stage and the symmetric form read a padded copy; the staged kernel reads q
+        return fused || launch_form(c) == MD_LAUNCH_SYMMETRIC ? PREP_COPY64 : PREP_NONE;
+    }
     return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_HALF32;
 }
 
@@ -750,24 +809,8 @@ hipError_t launch_fused(md_ctx *c, int flags, double kick1, double kick2, double
 // Pair partials of the current operands.  For FP64 2D the operands are q itself.
 hipError_t launch_pair(md_ctx *c, const double *q)
 {
-    if (launch_form(c) == MD_LAUNCH_SYMMETRIC) {
-        const int n = (int)c->n, npad = (int)c->npad, ntile = npad / kSymTile;
-        if (!c->sym_pad) {  // once per context: the update kernels never write past n
-            if (npad > n)
-                hipLaunchKernelGGL(k_fill_pad, dim3((unsigned)((npad - n + 255) / 256)), dim3(256), 0, c->stream,
-                                   static_cast<float *>(c->ops), n, npad, kSymPad);
-            c->sym_pad = true;
-        }
-        const float *xs = static_cast<const float *>(c->ops);
-        const dim3 block(kSymWaves * kWave);
-        const int noff = ntile * (ntile - 1) / 2;
-        if (noff > 0)
-            hipLaunchKernelGGL(k_sym2d<true>, dim3((unsigned)noff), block, 0, c->stream, xs, xs + npad, npad, ntile,
-                               (float)c->eps, c->part);
-        hipLaunchKernelGGL(k_sym2d<false>, dim3((unsigned)ntile), block, 0, c->stream, xs, xs + npad, npad, ntile,
-                           (float)c->eps, c->part);
-        return hipGetLastError();
-    }
+    if (launch_form(c) == MD_LAUNCH_SYMMETRIC)
+        return c->prec == MD_FP64 ? sym_launch<double>(c) : sym_launch<float>(c);
     const Tiles &t = c->tiles;
     const int n = (int)c->n;
     const int per_block = kWave * t.ipl * t.waves;

@@ -3,8 +3,8 @@ and added to both particles, the per-tile FP64 slots added in a fixed order.
 
   * forces against the oracle at sizes that cover one and several tile pairs,
     ragged last tiles (pad particles) and both sides of the form's size range,
-    with the mixed tolerance of the staged form (the pair terms are the same FP32
-    terms, grouped differently);
+    in both precisions, with the staged form's tolerances (the pair terms are the
+    same terms, grouped differently);
   * agreement with the staged form to FP32 rounding, and bit-identical repeated
     evaluations (no atomics);
   * the total force vanishes to rounding: the i-side and j-side terms of a pair
@@ -31,6 +31,7 @@ from test_gpu_parity import FORCE_TOL  # noqa: E402
 GRAV2D, RING = md.GRAV2D, md.RING
 EPS = 1e-3
 TOL = FORCE_TOL[(GRAV2D, md.MIXED)]
+PRECS = [md.MIXED, md.FP64]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -39,9 +40,9 @@ def _oracle_threads():
     yield
 
 
-def _force(q, launch):
+def _force(q, launch, prec=md.MIXED):
     n = q.shape[-1]
-    ctx = md.md_init(GRAV2D, md.MIXED, n, EPS)
+    ctx = md.md_init(GRAV2D, prec, n, EPS)
     md.md_set_launch(ctx, launch)
     assert md.md_get_launch(ctx) == launch
     qd = dev(q)
@@ -52,17 +53,19 @@ def _force(q, launch):
     return out
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n", [2048, 2049, 3000, 4096, 5120, 9999])
-def test_symmetric_force_matches_oracle(n):
+def test_symmetric_force_matches_oracle(n, prec):
     q, _ = inputs.grav2d_disk(n, seed=300 + n)
     fo = oracle.force(GRAV2D, q, EPS)
-    fg = _force(q, md.LAUNCH_SYMMETRIC)
+    fg = _force(q, md.LAUNCH_SYMMETRIC, prec)
     err = rel_inf(fg, fo)
-    print(f"symmetric n={n} rel_err={err:.3e}")
-    assert err < TOL, err
+    print(f"symmetric prec={prec} n={n} rel_err={err:.3e}")
+    assert err < FORCE_TOL[(GRAV2D, prec)], err
 
 
-def test_symmetric_force_clustered_state():
+@pytest.mark.parametrize("prec", PRECS)
+def test_symmetric_force_clustered_state(prec):
     """Two tight clusters far apart (large |F| from close pairs, and pairs that
     cross tiles between the clusters)."""
     n = 6000
@@ -70,30 +73,34 @@ def test_symmetric_force_clustered_state():
     q = np.concatenate([rng.normal(-0.5, 0.02, size=(2, n // 2)), rng.normal(0.5, 0.02, size=(2, n - n // 2))], axis=1)
     q = q[:, rng.permutation(n)]
     fo = oracle.force(GRAV2D, q, EPS)
-    fg = _force(q, md.LAUNCH_SYMMETRIC)
+    fg = _force(q, md.LAUNCH_SYMMETRIC, prec)
     err = rel_inf(fg, fo)
-    print(f"symmetric clustered n={n} rel_err={err:.3e}")
-    assert err < TOL, err
+    print(f"symmetric clustered prec={prec} n={n} rel_err={err:.3e}")
+    assert err < FORCE_TOL[(GRAV2D, prec)], err
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n", [40_000, 131_073])
-def test_symmetric_against_staged(n):
-    """Both forms sum the same FP32 pair terms in different groupings."""
+def test_symmetric_against_staged(n, prec):
+    """Both forms sum the same pair terms in different groupings."""
     q, _ = inputs.grav2d_disk(n, seed=7)
-    fs = _force(q, md.LAUNCH_SYMMETRIC)
-    ft = _force(q, md.LAUNCH_STAGED)
+    fs = _force(q, md.LAUNCH_SYMMETRIC, prec)
+    ft = _force(q, md.LAUNCH_STAGED, prec)
+    # FP64: n u kappa at this n (as the full-size FP64 rows test)
+    tol = FORCE_TOL[(GRAV2D, prec)] * (10 if prec == md.FP64 else 1)
     err = rel_inf(fs, ft)
-    print(f"symmetric vs staged n={n} rel_diff={err:.3e}")
-    assert err < TOL, err
+    print(f"symmetric vs staged prec={prec} n={n} rel_diff={err:.3e}")
+    assert err < tol, err
     rows = np.concatenate([np.random.default_rng(n).choice(n, size=16, replace=False), [0, n - 1]])
     fo = oracle.force_rows(GRAV2D, q, rows, EPS)
-    assert rel_inf(fs[:, rows], fo) < TOL
+    assert rel_inf(fs[:, rows], fo) < tol
 
 
-def test_symmetric_repeatable_and_momentum_free():
+@pytest.mark.parametrize("prec", PRECS)
+def test_symmetric_repeatable_and_momentum_free(prec):
     n = 70_001
     q, _ = inputs.grav2d_disk(n, seed=11)
-    ctx = md.md_init(GRAV2D, md.MIXED, n, EPS)
+    ctx = md.md_init(GRAV2D, prec, n, EPS)
     assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
     qd = dev(q)
     f1, f2 = torch.empty_like(qd), torch.empty_like(qd)
@@ -103,17 +110,18 @@ def test_symmetric_repeatable_and_momentum_free():
     fh = host(f1)
     total = np.abs(fh.sum(axis=1)).max()
     scale = np.abs(fh).sum(axis=1).max()
-    print(f"symmetric |sum f| = {total:.3e} of sum |f| = {scale:.3e}")
-    assert total < 1e-6 * scale
+    print(f"symmetric prec={prec} |sum f| = {total:.3e} of sum |f| = {scale:.3e}")
+    assert total < (1e-6 if prec == md.MIXED else 1e-13) * scale
     ctx.close()
 
 
-def test_symmetric_trajectory_matches_oracle():
+@pytest.mark.parametrize("prec", PRECS)
+def test_symmetric_trajectory_matches_oracle(prec):
     n, nst, dt = 4096, 10, 0.01
     q0, p0 = inputs.grav2d_disk(n, seed=21)
     f0 = oracle.force(GRAV2D, q0, EPS)
     qo, po, _ = oracle.step(GRAV2D, q0, p0, f0, dt, nst, EPS)
-    ctx = md.md_init(GRAV2D, md.MIXED, n, EPS)
+    ctx = md.md_init(GRAV2D, prec, n, EPS)
     md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
     qd, pd = dev(q0), dev(p0)
     f = torch.empty_like(qd)
@@ -125,14 +133,19 @@ def test_symmetric_trajectory_matches_oracle():
     eg = host(md.md_energy(ctx, qd, pd))
     eo = oracle.energy(GRAV2D, qo, po, EPS)
     de = abs(eg[2] - eo[2]) / (abs(e0[0]) + abs(e0[1]))
-    print(f"symmetric trajectory: max|dq|={eq:.3e} max|dp|={ep:.3e} energy diff={de:.3e}")
-    assert eq < 1e-5 and ep < 1e-4 and de < 1e-5
+    print(f"symmetric trajectory prec={prec}: max|dq|={eq:.3e} max|dp|={ep:.3e} energy diff={de:.3e}")
+    if prec == md.MIXED:
+        assert eq < 1e-5 and ep < 1e-4 and de < 1e-5
+    else:  # the FP64 trajectory tolerance of the staged form
+        assert eq < 1e-11 and ep < 1e-9 and de < 1e-12
     ctx.close()
 
 
 def test_launch_form_and_refusals():
     big = md.md_init(GRAV2D, md.MIXED, md.SYMMETRIC_AUTO_N, EPS)
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
+    big64 = md.md_init(GRAV2D, md.FP64, md.SYMMETRIC_AUTO_N, EPS)
+    assert md.md_get_launch(big64) == md.LAUNCH_SYMMETRIC
     below = md.md_init(GRAV2D, md.MIXED, md.SYMMETRIC_AUTO_N - 1, EPS)
     assert md.md_get_launch(below) != md.LAUNCH_SYMMETRIC
     md.md_set_launch(below, md.LAUNCH_SYMMETRIC)
@@ -141,9 +154,9 @@ def test_launch_form_and_refusals():
     assert md.md_get_launch(big) == md.LAUNCH_STAGED
     md.md_set_launch(big, md.LAUNCH_AUTO)
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
-    for model, prec, n in [(GRAV2D, md.FP64, 50_000), (GRAV2D, md.MIXED_KAHAN, 50_000),
-                           (GRAV2D, md.MIXED_PAIRF64, 50_000), (RING, md.MIXED, 50_000),
-                           (GRAV2D, md.MIXED, 2047), (GRAV2D, md.MIXED, 524_289)]:
+    for model, prec, n in [(GRAV2D, md.MIXED_KAHAN, 50_000), (GRAV2D, md.MIXED_PAIRF64, 50_000),
+                           (RING, md.MIXED, 50_000), (RING, md.FP64, 50_000),
+                           (GRAV2D, md.MIXED, 2047), (GRAV2D, md.FP64, 2047), (GRAV2D, md.MIXED, 524_289)]:
         ctx = md.md_init(model, prec, n, EPS)
         assert md.md_get_launch(ctx) != md.LAUNCH_SYMMETRIC
         with pytest.raises(md.MDError):
@@ -152,7 +165,7 @@ def test_launch_form_and_refusals():
     batch = md.md_batch_init(GRAV2D, md.MIXED, [0, 3000, 6000], EPS)
     with pytest.raises(md.MDError):
         md.md_set_launch(batch, md.LAUNCH_SYMMETRIC)
-    for c in (big, below, batch):
+    for c in (big, big64, below, batch):
         c.close()
 
 
