@@ -98,9 +98,9 @@ enum md_status {
  * Workspace bytes a context for (model, prec, n) needs; 0 for an invalid
  * combination.  The figure covers every tile configuration md_set_tiles
  * accepts for this n, and every launch form the context can take: for
- * MD_GRAV2D with MD_MIXED or MD_FP64 and 2048 <= n <= 524288 it includes the
- * symmetric form's partial slots, 16 * n'^2 / 1024 bytes with n' = n rounded up
- * to a multiple of 1024 (1.07 GB at n = 262144).
+ * MD_GRAV2D and MD_RING with MD_MIXED or MD_FP64 and 2048 <= n <= 524288 it
+ * includes the symmetric form's partial slots, 8 d n'^2 / 1024 bytes with n' = n
+ * rounded up to a multiple of 1024 (1.07 GB for 2D at n = 262144).
  */
 size_t md_workspace_bytes(int model, int prec, int64_t n);
 
@@ -184,23 +184,26 @@ int md_max_j_split(int64_t n);
  *                     partials per wavefront within 48 KiB / wavefronts
  *                     (MD_EUNSUPPORTED otherwise; md_set_tiles then refuses
  *                     tiles outside that range);
- *   MD_LAUNCH_SYMMETRIC  2D gravity, MD_MIXED or MD_FP64, 2048 <= n <= 524288:
- *                     each pair is evaluated once and added to both particles
- *                     with opposite signs (the term of the gradient of eq. 3
- *                     is odd in r_i - r_j), which halves the pair evaluations
- *                     of the all-pairs sum.  The particles are cut into tiles
- *                     of 1024; one block takes a tile pair (a, b), a < b, and
- *                     writes its i-side and j-side sums to separate FP64 slots,
- *                     the blocks of the diagonal tiles take every pair of their
- *                     tile; the elementwise kernel adds the slots in a fixed
- *                     order.  No atomics: bit-reproducible run to run, but the
- *                     sums are grouped differently from the staged form
- *                     (results agree to the precision's rounding, not bit for
- *                     bit).  The FP64 form pads with particles at 1e150 (pair
- *                     terms with them are about 5e-151), the FP32 form at 1e30
- *                     (exactly zero); positions must stay far below both.
- *                     Tiles (md_set_tiles) do not apply to it.  MD_EUNSUPPORTED
- *                     for other models, precisions, batches or n;
+ *   MD_LAUNCH_SYMMETRIC  2D gravity or Ring, MD_MIXED or MD_FP64,
+ *                     2048 <= n <= 524288: each pair is evaluated once and
+ *                     added to both particles with opposite signs (the terms of
+ *                     the gradient of eq. 3 and of eq. 9 are odd in the pair's
+ *                     difference), which halves the pair evaluations of the
+ *                     all-pairs sum.  The particles are cut into tiles of 1024;
+ *                     one block takes a tile pair (a, b), a < b, and writes its
+ *                     i-side and j-side sums to separate FP64 slots, the blocks
+ *                     of the diagonal tiles take every pair of their tile; the
+ *                     elementwise kernel adds the slots in a fixed order.  No
+ *                     atomics: bit-reproducible run to run, but the sums are
+ *                     grouped differently from the staged form (results agree
+ *                     to the precision's rounding, not bit for bit).  The
+ *                     particles past n in the last tile contribute nothing: the
+ *                     Ring form gives them zero operands (exact zeros), the 2D
+ *                     FP32 form positions at 1e30 (exact zeros), the 2D FP64
+ *                     form positions at 1e150 (terms of about 5e-151); 2D
+ *                     positions must stay far below both.  Tiles
+ *                     (md_set_tiles) do not apply to it.  MD_EUNSUPPORTED for
+ *                     other models, precisions, batches or n;
  *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 8192 (the
  *                     built-in tiles there are the fused form's), symmetric
  *                     when it applies and n >= MD_SYMMETRIC_AUTO_N, else staged.

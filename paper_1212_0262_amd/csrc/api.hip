@@ -48,7 +48,8 @@ bool model_ok(int model) { return model == MD_HMF || model == MD_RING || model =
 // Contexts that can take the symmetric 2D form (and carry its partial slots).
 bool sym_capable(int model, int prec, int64_t n)
 {
-    return model == MD_GRAV2D && (prec == MD_MIXED || prec == MD_FP64) && n >= kSymMinN && n <= kSymMaxN;
+    return (model == MD_GRAV2D || model == MD_RING) && (prec == MD_MIXED || prec == MD_FP64) && n >= kSymMinN &&
+           n <= kSymMaxN;
 }
 
 struct Layout {
@@ -67,7 +68,8 @@ Layout layout(int model, int prec, int64_t n)
     L.ops = off;
     if (model == MD_RING) off = align_up(off + 2 * npad * (prec == MD_FP64 ? sizeof(double) : sizeof(float)));
     else if (model == MD_GRAV2D && prec != MD_FP64) off = align_up(off + 2 * npad * sizeof(float));
-    else if (sym_capable(model, prec, n)) off = align_up(off + 2 * npad * sizeof(double));  // 2D FP64, padded copy
+    else if (model == MD_GRAV2D && sym_capable(model, prec, n))
+        off = align_up(off + 2 * npad * sizeof(double));  // 2D FP64: the symmetric form's padded copy
     L.wops = off;
     if (model != MD_HMF && prec != MD_FP64) off = align_up(off + (size_t)dims(model) * npad * sizeof(float));
     L.part = off;
@@ -739,7 +741,7 @@ int md_set_launch(md_ctx *c, int mode)
         return fail(c, MD_EINVAL, "md_set_launch: unknown mode %d", mode);
     if (mode == MD_LAUNCH_SYMMETRIC && !sym_ok(c))
         return fail(c, MD_EUNSUPPORTED,
-                    "md_set_launch: the symmetric launch needs a single 2D system, MD_MIXED or MD_FP64, "
+                    "md_set_launch: the symmetric launch needs a single 2D or Ring system, MD_MIXED or MD_FP64, "
                     "%lld <= n <= %lld",
                     (long long)kSymMinN, (long long)kSymMaxN);
     if (mode == MD_LAUNCH_FUSED && !fused_ok(c, c->tiles))

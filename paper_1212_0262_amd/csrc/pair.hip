@@ -221,19 +221,23 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
     }
 }
 
-// ------------------------------------------------------ symmetric 2D kernels --
+// ------------------------------------------------------- symmetric kernels --
 
-// The 2D pair term of the gradient of eq. 3 is odd in r_i - r_j, so one
-// evaluation serves both particles (Newton's third law).  The particles are cut
-// into tiles of kSymTile = 4 wavefronts x 64 lanes x 4 i.  A block of
-// k_sym2d<T, true> owns a tile pair (a, b), a < b: its lanes hold the i of tile a
-// in registers, and tile b streams through in blocks of 64 j.  At step s of a
-// 64-j block, lane l pairs its 4 i with j = (l + s) mod 64: the j operands and
-// the j-side sums move one lane per step through ds_bpermute (the LDS crossbar,
-// no VALU issue; DPP lane moves measured 2-3x the cost of an FMA on gfx950), so
-// every lane adds to a different j and no atomics are needed.  Per pair: 2
-// differences, r^2 + eps (2 FMA), 1 reciprocal, 2 FMA for the i side and 2 for
-// the j side.
+// The 2D pair term of the gradient of eq. 3 is odd in r_i - r_j, and the Ring term
+// of eq. 9 is odd in ti - tj, so one evaluation serves both particles (Newton's
+// third law).  The particles are cut into tiles of kSymTile = 4 wavefronts x 64
+// lanes x 4 i.  A block of k_sym<MODEL, T, true> owns a tile pair (a, b), a < b:
+// its lanes hold the i of tile a in registers, and tile b streams through in
+// blocks of 64 j.  At step s of a 64-j block, lane l pairs its 4 i with
+// j = (l + s) mod 64: the j operands and the j-side sums move one lane per step
+// through ds_bpermute (the LDS crossbar, no VALU issue; DPP lane moves measured
+// 2-3x the cost of an FMA on gfx950), so every lane adds to a different j and no
+// atomics are needed.
+//   2D, per pair: 2 differences, r^2 + eps (2 FMA), 1 reciprocal, 2 FMA for the i
+//     side (the staged form's term) and 2 for the j side (its negative).
+//   Ring, per pair: the factors p q of the staged form's term (ring_factors; p is
+//     exactly antisymmetric, q symmetric), fma(p, q) on the i side and
+//     fma(-p, q) on the j side.
 //   FP32 (MD_MIXED):
 //     i side: FP32 partial over 128 j, folded into FP64; the tile's sum goes to
 //             slot b of the i particles.
@@ -242,20 +246,24 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 //             j particles.
 //   FP64: the same in FP64 throughout; the wavefronts' j-side sums are added
 //     (same order) after every 64-j block, through a small LDS buffer.
-// k_sym2d<T, false> takes a diagonal tile (a, a): every ordered pair of the
+// k_sym<MODEL, T, false> takes a diagonal tile (a, a): every ordered pair of the
 // tile, i side only, into slot a.  Each particle thus receives one slot per tile
 // and the update kernel adds them in slot order: a fixed order, no atomics.
-// Pad particles (n .. npad - 1):
-//   FP32: at (1e30, 1e30): r^2 overflows to +inf for any pair with a pad
+// Pad particles (n .. npad - 1) contribute nothing:
+//   2D FP32: at (1e30, 1e30): r^2 overflows to +inf for any pair with a pad
 //     particle, the reciprocal is 0 and both terms are exactly zero (a pad-pad
-//     pair has dx = dy = 0), so no mask is needed;
-//   FP64: at (1e150, 1e150): r^2 is about 2e300 (finite: the refined FP64
+//     pair has dx = dy = 0);
+//   2D FP64: at (1e150, 1e150): r^2 is about 2e300 (finite: the refined FP64
 //     reciprocal of +inf would be NaN), so a term with a pad particle is about
-//     5e-151, below the last bit of any force sum larger than 1e-135.
+//     5e-151, below the last bit of any force sum larger than 1e-135;
+//   Ring: operands (0, 0): the numerator p is exactly 0 and q finite.
 constexpr int kSymIpl = 4, kSymWaves = kSymTile / (kWave * kSymIpl);
-template <typename T> constexpr T sym_pad();
-template <> constexpr float sym_pad<float>() { return 1e30f; }
-template <> constexpr double sym_pad<double>() { return 1e150; }
+template <int MODEL, typename T>
+constexpr T sym_pad()
+{
+    if (MODEL == MD_RING) return T(0);
+    return sizeof(T) == 4 ? T(1e30f) : T(1e150);
+}
 
 __device__ __forceinline__ float lane_next(int addr, float v)
 {
@@ -282,137 +290,152 @@ __device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
     b = r + 1 + (t - row0(r));
 }
 
-template <typename T, bool SYM>
-__global__ __launch_bounds__(kSymWaves * kWave) void k_sym2d(const T *__restrict__ xs, const T *__restrict__ ys,
-                                                             int npad, int ntile, T eps, double *__restrict__ part)
+// r0, r1: the operand rows ([2][npad], padded); e: eps (2D), 1 + eps (Ring FP64)
+// or 2 eps (Ring FP32); part: slots [ntile][D][npad].
+template <int MODEL, typename T, bool SYM>
+__global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1,
+                                                           int npad, int ntile, T e, double *__restrict__ part)
 {
     constexpr bool F32 = sizeof(T) == 4;
+    constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
     constexpr int IPL = kSymIpl, NBLK = kSymTile / kWave;
     // FP32: the wavefronts' j-side sums of the whole tile; FP64: of one 64-j block
-    __shared__ float jw32[SYM && F32 ? kSymWaves : 1][2][SYM && F32 ? kSymTile : 1];
-    __shared__ double jw64[SYM && !F32 ? kSymWaves : 1][2][SYM && !F32 ? kWave : 1];
+    __shared__ float jw32[SYM && F32 ? kSymWaves : 1][D][SYM && F32 ? kSymTile : 1];
+    __shared__ double jw64[SYM && !F32 ? kSymWaves : 1][D][SYM && !F32 ? kWave : 1];
     int a, b;
     if (SYM) sym_tile_pair(blockIdx.x, ntile, a, b);
     else a = b = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int i0 = a * kSymTile + wave * kWave * IPL + lane;
-    T xi[IPL], yi[IPL], ax[IPL], ay[IPL];
-    double tx[IPL], ty[IPL];  // FP32: the folded i-side sums
+    T u0[IPL], u1[IPL], acc[D][IPL];
+    double fold[D][IPL];  // FP32: the folded i-side sums
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        xi[k] = xs[i0 + k * kWave];
-        yi[k] = ys[i0 + k * kWave];
-        ax[k] = ay[k] = T(0);
-        tx[k] = ty[k] = 0.0;
+        u0[k] = r0[i0 + k * kWave];
+        u1[k] = r1[i0 + k * kWave];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            acc[d][k] = T(0);
+            fold[d][k] = 0.0;
+        }
     }
     const int next = ((lane + 1) & (kWave - 1)) * 4;  // ds_bpermute byte address of lane l + 1
     const int jl = b * kSymTile + lane;
-    T xn = xs[jl], yn = ys[jl];
+    T v0n = r0[jl], v1n = r1[jl];
     for (int blk = 0; blk < NBLK; ++blk) {
-        T xj = xn, yj = yn;
+        T v0 = v0n, v1 = v1n;
         if (blk + 1 < NBLK) {
-            xn = xs[jl + (blk + 1) * kWave];
-            yn = ys[jl + (blk + 1) * kWave];
+            v0n = r0[jl + (blk + 1) * kWave];
+            v1n = r1[jl + (blk + 1) * kWave];
         }
-        T sx = T(0), sy = T(0);  // j-side sums of the j this lane holds
+        T sj[D];  // j-side sums of the j this lane holds
+#pragma unroll
+        for (int d = 0; d < D; ++d) sj[d] = T(0);
 #pragma unroll 16
         for (int s = 0; s < kWave; ++s) {
             if (s) {
-                xj = lane_next(next, xj);
-                yj = lane_next(next, yj);
+                v0 = lane_next(next, v0);
+                v1 = lane_next(next, v1);
                 if (SYM) {
-                    sx = lane_next(next, sx);
-                    sy = lane_next(next, sy);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) sj[d] = lane_next(next, sj[d]);
                 }
             }
 #pragma unroll
             for (int k = 0; k < IPL; ++k) {
-                const T dx = xj - xi[k], dy = yj - yi[k];
-                const T w = rcp_(fma_(dx, dx, fma_(dy, dy, eps)));
-                ax[k] = fma_(-dx, w, ax[k]);
-                ay[k] = fma_(-dy, w, ay[k]);
-                if (SYM) {
-                    sx = fma_(dx, w, sx);
-                    sy = fma_(dy, w, sy);
+                if constexpr (MODEL == MD_GRAV2D) {
+                    const T dx = v0 - u0[k], dy = v1 - u1[k];
+                    const T w = rcp_(fma_(dx, dx, fma_(dy, dy, e)));
+                    acc[0][k] = fma_(-dx, w, acc[0][k]);
+                    acc[1][k] = fma_(-dy, w, acc[1][k]);
+                    if (SYM) {
+                        sj[0] = fma_(dx, w, sj[0]);
+                        sj[1] = fma_(dy, w, sj[1]);
+                    }
+                } else {
+                    T p, q;
+                    ring_factors(u0[k], u1[k], v0, v1, e, p, q);
+                    acc[0][k] = fma_(p, q, acc[0][k]);
+                    if (SYM) sj[0] = fma_(-p, q, sj[0]);
                 }
             }
         }
         // after step 63 lane l holds j = l - 1 (mod 64) of the block
         const int jm = (lane + kWave - 1) & (kWave - 1);
         if constexpr (SYM && F32) {
-            jw32[wave][0][blk * kWave + jm] = sx;
-            jw32[wave][1][blk * kWave + jm] = sy;
+#pragma unroll
+            for (int d = 0; d < D; ++d) jw32[wave][d][blk * kWave + jm] = sj[d];
         } else if constexpr (SYM) {
-            jw64[wave][0][jm] = sx;
-            jw64[wave][1][jm] = sy;
+#pragma unroll
+            for (int d = 0; d < D; ++d) jw64[wave][d][jm] = sj[d];
             __syncthreads();
-            if (threadIdx.x < 2 * kWave) {
-                const int c = threadIdx.x / kWave, m = threadIdx.x & (kWave - 1);
+            if (threadIdx.x < D * kWave) {
+                const int d = threadIdx.x / kWave, m = threadIdx.x & (kWave - 1);
                 double t = 0.0;
 #pragma unroll
-                for (int w = 0; w < kSymWaves; ++w) t += jw64[w][c][m];
-                part[(size_t)(2 * a + c) * npad + b * kSymTile + blk * kWave + m] = t;
+                for (int w = 0; w < kSymWaves; ++w) t += jw64[w][d][m];
+                part[(size_t)(D * a + d) * npad + b * kSymTile + blk * kWave + m] = t;
             }
             __syncthreads();
         }
         if (F32 && (blk & 1)) {  // fold every 128 j
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) {
-                tx[k] += (double)ax[k];
-                ty[k] += (double)ay[k];
-                ax[k] = ay[k] = T(0);
-            }
+            for (int k = 0; k < IPL; ++k)
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    fold[d][k] += (double)acc[d][k];
+                    acc[d][k] = T(0);
+                }
         }
     }
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        const int i = i0 + k * kWave;
-        part[(size_t)(2 * b) * npad + i] = F32 ? tx[k] : (double)ax[k];
-        part[(size_t)(2 * b + 1) * npad + i] = F32 ? ty[k] : (double)ay[k];
-    }
+    for (int k = 0; k < IPL; ++k)
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            part[(size_t)(D * b + d) * npad + i0 + k * kWave] = F32 ? fold[d][k] : (double)acc[d][k];
     if constexpr (SYM && F32) {
         __syncthreads();
         for (int m = threadIdx.x; m < kSymTile; m += kSymWaves * kWave) {
-            double sx = 0.0, sy = 0.0;
 #pragma unroll
-            for (int w = 0; w < kSymWaves; ++w) {
-                sx += (double)jw32[w][0][m];
-                sy += (double)jw32[w][1][m];
+            for (int d = 0; d < D; ++d) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < kSymWaves; ++w) t += (double)jw32[w][d][m];
+                part[(size_t)(D * a + d) * npad + b * kSymTile + m] = t;
             }
-            part[(size_t)(2 * a) * npad + b * kSymTile + m] = sx;
-            part[(size_t)(2 * a + 1) * npad + b * kSymTile + m] = sy;
         }
     }
 }
 
-template <typename T>
+template <int MODEL, typename T>
 __global__ void k_fill_pad(T *__restrict__ ops, int n, int npad)
 {
     const int i = n + blockIdx.x * blockDim.x + threadIdx.x;
     if (i < npad) {
-        ops[i] = sym_pad<T>();
-        ops[npad + i] = sym_pad<T>();
+        ops[i] = sym_pad<MODEL, T>();
+        ops[npad + i] = sym_pad<MODEL, T>();
     }
 }
 
-template <typename T>
+template <int MODEL, typename T>
 hipError_t sym_launch(md_ctx *c)
 {
     const int n = (int)c->n, npad = (int)c->npad, ntile = npad / kSymTile;
     T *ops = static_cast<T *>(c->ops);
     if (!c->sym_pad) {  // once per context: the update kernels never write past n
         if (npad > n)
-            hipLaunchKernelGGL(k_fill_pad<T>, dim3((unsigned)((npad - n + 255) / 256)), dim3(256), 0, c->stream, ops,
-                               n, npad);
+            hipLaunchKernelGGL((k_fill_pad<MODEL, T>), dim3((unsigned)((npad - n + 255) / 256)), dim3(256), 0,
+                               c->stream, ops, n, npad);
         c->sym_pad = true;
     }
+    const T e = MODEL == MD_GRAV2D ? (T)c->eps : sizeof(T) == 4 ? (T)(2.0 * c->eps) : (T)(1.0 + c->eps);
     const dim3 block(kSymWaves * kWave);
     const int noff = ntile * (ntile - 1) / 2;
     if (noff > 0)
-        hipLaunchKernelGGL((k_sym2d<T, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad, npad,
-                           ntile, (T)c->eps, c->part);
-    hipLaunchKernelGGL((k_sym2d<T, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad, npad, ntile,
-                       (T)c->eps, c->part);
+        hipLaunchKernelGGL((k_sym<MODEL, T, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad, npad,
+                           ntile, e, c->part);
+    hipLaunchKernelGGL((k_sym<MODEL, T, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad, npad,
+                       ntile, e, c->part);
     return hipGetLastError();
 }
 
@@ -809,8 +832,11 @@ hipError_t launch_fused(md_ctx *c, int flags, double kick1, double kick2, double
 // Pair partials of the current operands.  For FP64 2D the operands are q itself.
 hipError_t launch_pair(md_ctx *c, const double *q)
 {
-    if (launch_form(c) == MD_LAUNCH_SYMMETRIC)
-        return c->prec == MD_FP64 ? sym_launch<double>(c) : sym_launch<float>(c);
+    if (launch_form(c) == MD_LAUNCH_SYMMETRIC) {
+        if (c->model == MD_GRAV2D)
+            return c->prec == MD_FP64 ? sym_launch<MD_GRAV2D, double>(c) : sym_launch<MD_GRAV2D, float>(c);
+        return c->prec == MD_FP64 ? sym_launch<MD_RING, double>(c) : sym_launch<MD_RING, float>(c);
+    }
     const Tiles &t = c->tiles;
     const int n = (int)c->n;
     const int per_block = kWave * t.ipl * t.waves;

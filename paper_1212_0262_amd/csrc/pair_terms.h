@@ -70,10 +70,11 @@ __device__ __forceinline__ void pair_2d(T xi, T yi, T xj, T yj, T eps, A &ax, A 
     ay.add(dy, w);
 }
 
-// Ring (eq. 9): adds sin(ti - tj) / (1 - cos(ti - tj) + eps)^{3/2} to a, from the
-// cosines and sines of both angles.  one_eps = 1 + eps.
-template <typename T, typename A>
-__device__ __forceinline__ void pair_ring(T ci, T si, T cj, T sj, T one_eps, A &a)
+// Ring (eq. 9): the term sin(ti - tj) / (1 - cos(ti - tj) + eps)^{3/2} as the
+// factors p q, from the cosines and sines of both angles.  one_eps = 1 + eps.
+// p (the numerator) is exactly antisymmetric in i, j and q symmetric.
+template <typename T>
+__device__ __forceinline__ void ring_factors_eq9(T ci, T si, T cj, T sj, T one_eps, T &p, T &q)
 {
     T num;
     {
@@ -82,7 +83,8 @@ __device__ __forceinline__ void pair_ring(T ci, T si, T cj, T sj, T one_eps, A &
     }
     const T u = fma_(-ci, cj, fma_(-si, sj, one_eps));
     const T r = rsq_(u);
-    a.add(num, r * r * r);
+    p = num;
+    q = r * r * r;
 }
 
 // Ring, half-angle operands (the FP32 forms): A = sqrt2 sin(t/2), B = sqrt2 cos(t/2)
@@ -92,9 +94,10 @@ __device__ __forceinline__ void pair_ring(T ci, T si, T cj, T sj, T one_eps, A &
 // and r' = u'^{-1/2}, the term sin d / (1 - cos d + eps)^{3/2} is sqrt2 a b r'^3;
 // the sqrt2 goes into the prefactor, and eps2 = 2 eps.  Unlike eq. 9's angle-sum
 // form, 1 - cos d is formed without cancelling against 1: its rounding error
-// scales with |d|, which matters in FP32 for close pairs.
-template <typename T, typename A>
-__device__ __forceinline__ void pair_ring_half(T ai, T bi, T aj, T bj, T eps2, A &acc)
+// scales with |d|, which matters in FP32 for close pairs.  Factors: p = a b
+// (antisymmetric), q = r'^3 (symmetric).
+template <typename T>
+__device__ __forceinline__ void ring_factors_half(T ai, T bi, T aj, T bj, T eps2, T &p, T &q)
 {
     T a;
     {
@@ -103,16 +106,27 @@ __device__ __forceinline__ void pair_ring_half(T ai, T bi, T aj, T bj, T eps2, A
     }
     const T b = fma_(bi, bj, ai * aj);
     const T r = rsq_(fma_(a, a, eps2));
-    acc.add(a * b, r * r * r);
+    p = a * b;
+    q = r * r * r;
 }
 
-// The Ring pair term of the context's precision: eq. 9 on (cos t, sin t) in FP64;
-// the half-angle form on sqrt2 (cos(t/2), sin(t/2)) in FP32 (then e holds 2 eps).
+// The Ring pair term's factors in the context's precision: eq. 9 on (cos t, sin t)
+// in FP64; the half-angle form on sqrt2 (cos(t/2), sin(t/2)) in FP32 (then e holds
+// 2 eps, else 1 + eps).
+template <typename T>
+__device__ __forceinline__ void ring_factors(T c0, T s0, T c1, T s1, T e, T &p, T &q)
+{
+    if constexpr (sizeof(T) == 8) ring_factors_eq9(c0, s0, c1, s1, e, p, q);
+    else ring_factors_half(s0, c0, s1, c1, e, p, q);
+}
+
+// Adds the Ring pair term (i = 0, j = 1) to the accumulator a.
 template <typename T, typename A>
 __device__ __forceinline__ void ring_term(T c0, T s0, T c1, T s1, T e, A &a)
 {
-    if constexpr (sizeof(T) == 8) pair_ring(c0, s0, c1, s1, e, a);
-    else pair_ring_half(s0, c0, s1, c1, e, a);
+    T p, q;
+    ring_factors(c0, s0, c1, s1, e, p, q);
+    a.add(p, q);
 }
 
 // Streams the j operands (rows r0, r1) of j in [j0, j1) through a block-shared

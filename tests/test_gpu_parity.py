@@ -311,8 +311,9 @@ def test_hmf_config_full_size(prec, hmf_full_reference):
 
 @pytest.mark.parametrize("n", [131_071, 131_072])
 def test_ring_mixed_both_staged_kernels(n):
-    """The Ring FP32 forms use the LDS-window pair kernel below N = 131072 and the
-    scalar-load one from there on: sampled rows of both against the oracle."""
+    """The Ring FP32 forms at N = 131071 and 131072 (a ragged and a full last tile):
+    the automatic form (symmetric for MD_MIXED, the LDS-window staged kernel for
+    MD_MIXED_KAHAN), sampled rows against the oracle."""
     q, _ = inputs.ring_waterbag(n, seed=14)
     rows = np.concatenate([np.random.default_rng(14).choice(n, size=48, replace=False), [0, n - 1]])
     fo = oracle.force_rows(RING, q, rows, 0.01)

@@ -1,5 +1,6 @@
-"""The symmetric 2D launch form (MD_LAUNCH_SYMMETRIC): each pair evaluated once
-and added to both particles, the per-tile FP64 slots added in a fixed order.
+"""The symmetric launch form (MD_LAUNCH_SYMMETRIC) of the 2D and Ring models: each
+pair evaluated once and added to both particles, the per-tile FP64 slots added
+in a fixed order.
 
   * forces against the oracle at sizes that cover one and several tile pairs,
     ragged last tiles (pad particles) and both sides of the form's size range,
@@ -32,6 +33,11 @@ GRAV2D, RING = md.GRAV2D, md.RING
 EPS = 1e-3
 TOL = FORCE_TOL[(GRAV2D, md.MIXED)]
 PRECS = [md.MIXED, md.FP64]
+MODELS = [(GRAV2D, 1e-3), (RING, 0.01)]
+
+
+def _state(model, n, seed):
+    return inputs.grav2d_disk(n, seed=seed) if model == GRAV2D else inputs.ring_waterbag(n, seed=seed)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -40,9 +46,9 @@ def _oracle_threads():
     yield
 
 
-def _force(q, launch, prec=md.MIXED):
+def _force(q, launch, prec=md.MIXED, model=GRAV2D, eps=EPS):
     n = q.shape[-1]
-    ctx = md.md_init(GRAV2D, prec, n, EPS)
+    ctx = md.md_init(model, prec, n, eps)
     md.md_set_launch(ctx, launch)
     assert md.md_get_launch(ctx) == launch
     qd = dev(q)
@@ -53,15 +59,16 @@ def _force(q, launch, prec=md.MIXED):
     return out
 
 
+@pytest.mark.parametrize("model,eps", MODELS)
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n", [2048, 2049, 3000, 4096, 5120, 9999])
-def test_symmetric_force_matches_oracle(n, prec):
-    q, _ = inputs.grav2d_disk(n, seed=300 + n)
-    fo = oracle.force(GRAV2D, q, EPS)
-    fg = _force(q, md.LAUNCH_SYMMETRIC, prec)
+def test_symmetric_force_matches_oracle(n, prec, model, eps):
+    q, _ = _state(model, n, seed=300 + n)
+    fo = oracle.force(model, q, eps)
+    fg = _force(q, md.LAUNCH_SYMMETRIC, prec, model, eps)
     err = rel_inf(fg, fo)
-    print(f"symmetric prec={prec} n={n} rel_err={err:.3e}")
-    assert err < FORCE_TOL[(GRAV2D, prec)], err
+    print(f"symmetric model={model} prec={prec} n={n} rel_err={err:.3e}")
+    assert err < FORCE_TOL[(model, prec)], err
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -79,49 +86,52 @@ def test_symmetric_force_clustered_state(prec):
     assert err < FORCE_TOL[(GRAV2D, prec)], err
 
 
+@pytest.mark.parametrize("model,eps", MODELS)
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n", [40_000, 131_073])
-def test_symmetric_against_staged(n, prec):
+def test_symmetric_against_staged(n, prec, model, eps):
     """Both forms sum the same pair terms in different groupings."""
-    q, _ = inputs.grav2d_disk(n, seed=7)
-    fs = _force(q, md.LAUNCH_SYMMETRIC, prec)
-    ft = _force(q, md.LAUNCH_STAGED, prec)
+    q, _ = _state(model, n, seed=7)
+    fs = _force(q, md.LAUNCH_SYMMETRIC, prec, model, eps)
+    ft = _force(q, md.LAUNCH_STAGED, prec, model, eps)
     # FP64: n u kappa at this n (as the full-size FP64 rows test)
-    tol = FORCE_TOL[(GRAV2D, prec)] * (10 if prec == md.FP64 else 1)
+    tol = FORCE_TOL[(model, prec)] * (10 if prec == md.FP64 else 1)
     err = rel_inf(fs, ft)
-    print(f"symmetric vs staged prec={prec} n={n} rel_diff={err:.3e}")
+    print(f"symmetric vs staged model={model} prec={prec} n={n} rel_diff={err:.3e}")
     assert err < tol, err
     rows = np.concatenate([np.random.default_rng(n).choice(n, size=16, replace=False), [0, n - 1]])
-    fo = oracle.force_rows(GRAV2D, q, rows, EPS)
-    assert rel_inf(fs[:, rows], fo) < tol
+    fo = oracle.force_rows(model, q, rows, eps)
+    assert rel_inf(fs[..., rows], fo) < tol
 
 
+@pytest.mark.parametrize("model,eps", MODELS)
 @pytest.mark.parametrize("prec", PRECS)
-def test_symmetric_repeatable_and_momentum_free(prec):
+def test_symmetric_repeatable_and_momentum_free(prec, model, eps):
     n = 70_001
-    q, _ = inputs.grav2d_disk(n, seed=11)
-    ctx = md.md_init(GRAV2D, prec, n, EPS)
+    q, _ = _state(model, n, seed=11)
+    ctx = md.md_init(model, prec, n, eps)
     assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
     qd = dev(q)
     f1, f2 = torch.empty_like(qd), torch.empty_like(qd)
     md.md_force(ctx, qd, f1)
     md.md_force(ctx, qd, f2)
     assert torch.equal(f1, f2)
-    fh = host(f1)
+    fh = host(f1).reshape(-1, n)
     total = np.abs(fh.sum(axis=1)).max()
     scale = np.abs(fh).sum(axis=1).max()
-    print(f"symmetric prec={prec} |sum f| = {total:.3e} of sum |f| = {scale:.3e}")
+    print(f"symmetric model={model} prec={prec} |sum f| = {total:.3e} of sum |f| = {scale:.3e}")
     assert total < (1e-6 if prec == md.MIXED else 1e-13) * scale
     ctx.close()
 
 
+@pytest.mark.parametrize("model,eps,dt", [(GRAV2D, 1e-3, 0.01), (RING, 0.01, 0.05)])
 @pytest.mark.parametrize("prec", PRECS)
-def test_symmetric_trajectory_matches_oracle(prec):
-    n, nst, dt = 4096, 10, 0.01
-    q0, p0 = inputs.grav2d_disk(n, seed=21)
-    f0 = oracle.force(GRAV2D, q0, EPS)
-    qo, po, _ = oracle.step(GRAV2D, q0, p0, f0, dt, nst, EPS)
-    ctx = md.md_init(GRAV2D, prec, n, EPS)
+def test_symmetric_trajectory_matches_oracle(prec, model, eps, dt):
+    n, nst = 4096, 10
+    q0, p0 = _state(model, n, seed=21)
+    f0 = oracle.force(model, q0, eps)
+    qo, po, _ = oracle.step(model, q0, p0, f0, dt, nst, eps)
+    ctx = md.md_init(model, prec, n, eps)
     md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
     qd, pd = dev(q0), dev(p0)
     f = torch.empty_like(qd)
@@ -129,11 +139,11 @@ def test_symmetric_trajectory_matches_oracle(prec):
     md.md_step(ctx, qd, pd, f, dt, nst)
     eq = np.abs(host(qd) - qo).max()
     ep = np.abs(host(pd) - po).max()
-    e0 = oracle.energy(GRAV2D, q0, p0, EPS)
+    e0 = oracle.energy(model, q0, p0, eps)
     eg = host(md.md_energy(ctx, qd, pd))
-    eo = oracle.energy(GRAV2D, qo, po, EPS)
+    eo = oracle.energy(model, qo, po, eps)
     de = abs(eg[2] - eo[2]) / (abs(e0[0]) + abs(e0[1]))
-    print(f"symmetric trajectory prec={prec}: max|dq|={eq:.3e} max|dp|={ep:.3e} energy diff={de:.3e}")
+    print(f"symmetric trajectory model={model} prec={prec}: max|dq|={eq:.3e} max|dp|={ep:.3e} energy diff={de:.3e}")
     if prec == md.MIXED:
         assert eq < 1e-5 and ep < 1e-4 and de < 1e-5
     else:  # the FP64 trajectory tolerance of the staged form
@@ -146,6 +156,10 @@ def test_launch_form_and_refusals():
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
     big64 = md.md_init(GRAV2D, md.FP64, md.SYMMETRIC_AUTO_N, EPS)
     assert md.md_get_launch(big64) == md.LAUNCH_SYMMETRIC
+    ring = md.md_init(RING, md.MIXED, md.SYMMETRIC_AUTO_N, 0.01)
+    assert md.md_get_launch(ring) == md.LAUNCH_SYMMETRIC
+    ring64 = md.md_init(RING, md.FP64, md.SYMMETRIC_AUTO_N, 0.01)
+    assert md.md_get_launch(ring64) == md.LAUNCH_SYMMETRIC
     below = md.md_init(GRAV2D, md.MIXED, md.SYMMETRIC_AUTO_N - 1, EPS)
     assert md.md_get_launch(below) != md.LAUNCH_SYMMETRIC
     md.md_set_launch(below, md.LAUNCH_SYMMETRIC)
@@ -155,8 +169,9 @@ def test_launch_form_and_refusals():
     md.md_set_launch(big, md.LAUNCH_AUTO)
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
     for model, prec, n in [(GRAV2D, md.MIXED_KAHAN, 50_000), (GRAV2D, md.MIXED_PAIRF64, 50_000),
-                           (RING, md.MIXED, 50_000), (RING, md.FP64, 50_000),
-                           (GRAV2D, md.MIXED, 2047), (GRAV2D, md.FP64, 2047), (GRAV2D, md.MIXED, 524_289)]:
+                           (RING, md.MIXED_KAHAN, 50_000), (RING, md.MIXED_PAIRF64, 50_000),
+                           (GRAV2D, md.MIXED, 2047), (GRAV2D, md.FP64, 2047), (RING, md.FP64, 2047),
+                           (GRAV2D, md.MIXED, 524_289), (RING, md.MIXED, 524_289)]:
         ctx = md.md_init(model, prec, n, EPS)
         assert md.md_get_launch(ctx) != md.LAUNCH_SYMMETRIC
         with pytest.raises(md.MDError):
@@ -165,7 +180,7 @@ def test_launch_form_and_refusals():
     batch = md.md_batch_init(GRAV2D, md.MIXED, [0, 3000, 6000], EPS)
     with pytest.raises(md.MDError):
         md.md_set_launch(batch, md.LAUNCH_SYMMETRIC)
-    for c in (big, big64, below, batch):
+    for c in (big, big64, ring, ring64, below, batch):
         c.close()
 
 
