@@ -675,6 +675,7 @@ def paper_tables_workload(md, torch, args):
                 if model != md.HMF:
                     row[pname + "_gpairs_per_s"] = 3.0 * n * n / t / 1e9
                 row[pname + "_tiles"] = list(md.md_get_tiles(ctx))
+                row[pname + "_launch"] = LAUNCH_NAMES.get(md.md_get_launch(ctx), "staged")
                 ctx.close()
             log(f"bench: {model_name} N={n}: fp64 {row['fp64_s_per_step']:.3e} s, mixed {row['mixed_s_per_step']:.3e} s "
                 f"per step (paper 1 GPU {paper_s:g} s)")
