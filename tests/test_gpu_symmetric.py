@@ -151,6 +151,25 @@ def test_symmetric_trajectory_matches_oracle(prec, model, eps, dt):
     ctx.close()
 
 
+@pytest.mark.parametrize("model,eps", MODELS)
+def test_symmetric_at_the_maximum_size(model, eps):
+    """n = 524288, the largest n the form accepts (512 tiles; the Ring slots take
+    2.1 GB): sampled rows of the automatic (symmetric) mixed form against the oracle."""
+    n = 524_288
+    q, _ = _state(model, n, seed=41)
+    ctx = md.md_init(model, md.MIXED, n, eps)
+    assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
+    qd = dev(q)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    rows = np.concatenate([np.random.default_rng(41).choice(n, size=16, replace=False), [0, 1023, 1024, n - 1]])
+    fo = oracle.force_rows(model, q, rows, eps)
+    err = rel_inf(host(f)[..., rows], fo)
+    print(f"symmetric model={model} n={n} sampled rel_err={err:.3e}")
+    assert err < FORCE_TOL[(model, md.MIXED)], err
+    ctx.close()
+
+
 def test_launch_form_and_refusals():
     big = md.md_init(GRAV2D, md.MIXED, md.SYMMETRIC_AUTO_N, EPS)
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
