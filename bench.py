@@ -310,8 +310,9 @@ ENS_DT = 0.05
 def ensemble_workload(md, torch, args):
     """Ring ensemble: 256 realizations, N_b = round(exp(U(ln 1000, ln 16384))) (seed 4),
     waterbag ICs per realization (seeded [4, b]), eps = 0.01, dt = 0.05, FP32 pairs
-    with Kahan-compensated accumulation; tiles autotuned; the whole run replayed as
-    one captured HIP graph."""
+    with Kahan-compensated accumulation, md_step's automatic launch form (symmetric
+    here; the staged form with autotuned tiles timed beside it); the whole run
+    replayed as one captured HIP graph."""
     import numpy as np
 
     from paper_1212_0262_amd import autotune, inputs
@@ -330,10 +331,17 @@ def ensemble_workload(md, torch, args):
     f = torch.empty_like(q)
     torch.cuda.synchronize()
     default_tiles = md.md_get_tiles(ctx)
+    # the staged form's tiles, tuned (the symmetric form has no tile choice)
+    md.md_set_launch(ctx, md.LAUNCH_STAGED)
     with torch.cuda.stream(stream):
         t_default = autotune.time_step(ctx, q)
         best, table = autotune.tune(ctx, q, cache=None)
-    log(f"bench: ensemble tiles default {default_tiles} {t_default:.3f} ms/step, tuned {best} {table[0][1]:.3f} ms/step")
+    md.md_set_launch(ctx, md.LAUNCH_AUTO)
+    launch = LAUNCH_NAMES[md.md_get_launch(ctx)]
+    with torch.cuda.stream(stream):
+        t_auto = autotune.time_step(ctx, q)
+    log(f"bench: ensemble staged tiles default {default_tiles} {t_default:.3f} ms/step, tuned {best} "
+        f"{table[0][1]:.3f} ms/step; automatic form {launch} {t_auto:.3f} ms/step")
     with torch.cuda.stream(stream):
         e0 = md.md_energy(ctx, q, p).cpu().numpy()
         md.md_force(ctx, q, f)
@@ -376,7 +384,7 @@ def ensemble_workload(md, torch, args):
             ev1.record(stream)
             torch.cuda.synchronize()
             ref[name] = {"ms": ev0.elapsed_time(ev1), "E1": md.md_energy(c2, q2, p2).cpu().numpy(),
-                         "tiles": list(md.md_get_tiles(c2))}
+                         "tiles": list(md.md_get_tiles(c2)), "launch": LAUNCH_NAMES[md.md_get_launch(c2)]}
         c2.close()
         del q2, p2, f2
     e64 = ref["fp64"]["E1"]
@@ -406,11 +414,13 @@ def ensemble_workload(md, torch, args):
         "ms_per_step": round(graph_ms / args.steps, 4), "dtype": "f32",
         "config": {"workload": "ring ensemble nb=256 N_b log-uniform [1000,16384] seed=4 eps=0.01 dt=0.05",
                    "model": "ring", "nb": ENS_NB, "n_total": int(off[-1]), "pairs_per_eval": pairs_per_eval,
-                   "precision": "mixed_kahan", "tiles": list(best), "tiles_default": list(default_tiles)},
+                   "precision": "mixed_kahan", "launch": launch, "staged_tiles_tuned": list(best),
+                   "staged_tiles_default": list(default_tiles)},
         "roofline": None, "cpu_baseline": cpu,
         "ensemble": {"graph_ms": graph_ms, "eager_ms": eager_ms, "graph_equals_eager": same,
-                     "step_ms_default_tiles": t_default, "step_ms_tuned": table[0][1],
-                     "tune_table_top5": [[list(t), ms] for t, ms in table[:5]],
+                     "step_ms": t_auto, "staged_step_ms_default_tiles": t_default,
+                     "staged_step_ms_tuned": table[0][1], "speedup_vs_tuned_staged": table[0][1] / t_auto,
+                     "staged_tune_table_top5": [[list(t), ms] for t, ms in table[:5]],
                      "dE_E_max": float(dE.max()), "dE_E_median": float(np.median(dE)),
                      "fp64_dE_E_max": float(dE64.max()), "fp64_dE_E_median": float(np.median(dE64)),
                      "kahan_vs_fp64_energy_diff_over_absE0_max": float(prec_err.max()),
@@ -418,6 +428,7 @@ def ensemble_workload(md, torch, args):
                      "mixed_vs_fp64_energy_diff_over_absE0_max": float(prec_err_mixed.max()),
                      "fp64_gpairs_per_s": pairs / (ref["fp64"]["ms"] * 1e-3) / 1e9,
                      "mixed_gpairs_per_s": pairs / (ref["mixed"]["ms"] * 1e-3) / 1e9,
+                     "fp64_launch": ref["fp64"]["launch"], "mixed_launch": ref["mixed"]["launch"],
                      "fp64_tiles": ref["fp64"]["tiles"], "mixed_tiles": ref["mixed"]["tiles"]},
     }
 

@@ -167,11 +167,19 @@ bool fused_ok(const md_ctx *c, const Tiles &t)
     return S <= kFusedMaxWaves && t.ipl * dims(c->model) * kWave * 8 <= kFusedLdsBytes / S;
 }
 
-bool sym_ok(const md_ctx *c) { return !c->batch && sym_capable(c->model, c->prec, c->n); }
+bool sym_ok(const md_ctx *c) { return c->batch ? c->batch->sym : sym_capable(c->model, c->prec, c->n); }
+
+// MD_LAUNCH_AUTO for an ensemble: the symmetric form when the realizations' tile
+// pairs outnumber their diagonal tiles (small realizations gain nothing from it).
+bool batch_sym_auto(const Batch &B) { return B.sym && B.n_soff >= B.n_sdiag; }
 
 // md_step's launch form for this context.
 int form_of(const md_ctx *c)
 {
+    if (c->batch) {
+        const bool s = c->launch == MD_LAUNCH_SYMMETRIC || (c->launch == MD_LAUNCH_AUTO && batch_sym_auto(*c->batch));
+        return s && c->batch->sym ? MD_LAUNCH_SYMMETRIC : MD_LAUNCH_STAGED;
+    }
     if (c->launch == MD_LAUNCH_SYMMETRIC || (c->launch == MD_LAUNCH_AUTO && c->n >= kSymAutoN))
         if (sym_ok(c)) return MD_LAUNCH_SYMMETRIC;
     if (c->launch == MD_LAUNCH_STAGED || c->launch == MD_LAUNCH_SYMMETRIC || !fused_ok(c, c->tiles))
@@ -403,6 +411,38 @@ int make_batch(int model, int prec, int nb, const int64_t *off, const double *ep
     B.roff[nb] = B.n_rows;
     B.n_eitems = (int)(B.eitems.size() / 8);
     B.eoff[nb] = B.n_eitems;
+    // symmetric form: every realization within the single-system limits, slots within 4 GiB
+    const bool sym_prec = model == MD_RING ? (prec == MD_MIXED || prec == MD_MIXED_KAHAN || prec == MD_FP64)
+                                           : (prec == MD_MIXED || prec == MD_MIXED_KAHAN);
+    B.tmax = (int)div_up(B.nmax, kSymTile);
+    const size_t sym_slot_bytes = (size_t)B.tmax * dims(model) * (size_t)pad_n(off[nb]) * sizeof(double);
+    B.sym = sym_prec && B.nmax <= kSymMaxN && sym_slot_bytes <= (size_t(1) << 32);
+    B.sitems.clear();
+    B.srows.clear();
+    B.n_soff = B.n_sdiag = 0;
+    if (B.sym) {
+        std::vector<int> diag;
+        for (int b = 0; b < nb; ++b) {
+            const int64_t o = off[b], n = off[b + 1] - off[b];
+            const int T = (int)div_up(n, kSymTile);
+            for (int ta = 0; ta < T; ++ta) {
+                const int ia = (int)(o + (int64_t)ta * kSymTile);
+                for (int tb = ta + 1; tb < T; ++tb) {
+                    const int it[8] = {b, ia, (int)(o + n), tb, (int)(o + (int64_t)tb * kSymTile), (int)(o + n), ta, 0};
+                    B.sitems.insert(B.sitems.end(), it, it + 8);
+                }
+                const int dg[8] = {b, ia, (int)(o + n), ta, ia, (int)(o + n), ta, 0};
+                diag.insert(diag.end(), dg, dg + 8);
+            }
+            for (int64_t i0 = o; i0 < o + n; i0 += 256) {
+                const int r[4] = {b, (int)i0, (int)(i0 + 256 < o + n ? i0 + 256 : o + n), T};
+                B.srows.insert(B.srows.end(), r, r + 4);
+            }
+        }
+        B.n_soff = (int)(B.sitems.size() / 8);
+        B.n_sdiag = (int)(diag.size() / 8);
+        B.sitems.insert(B.sitems.end(), diag.begin(), diag.end());
+    }
     // largest pair-item count over all tile choices: 64-particle i blocks, smax pieces
     const int64_t cmin = batch_chunk(B, B.smax);
     int64_t mx = 0;
@@ -449,7 +489,7 @@ void build_lists(Batch &B, const Tiles &t)
 }
 
 struct BatchLayout {
-    size_t scal, ops, part, items, rows, eitems, eps, pref, ered, kred, eoff, roff, off, total;
+    size_t scal, ops, part, items, rows, eitems, eps, pref, ered, kred, eoff, roff, off, sitems, srows, total;
 };
 
 BatchLayout batch_layout(int model, int prec, const Batch &B)
@@ -468,7 +508,7 @@ BatchLayout batch_layout(int model, int prec, const Batch &B)
     if (model == MD_RING) ops = 2 * npad * (prec == MD_FP64 ? sizeof(double) : sizeof(float));
     else if (prec != MD_FP64) ops = 2 * npad * sizeof(float);
     L.ops = take(ops);
-    L.part = take((size_t)B.smax * d * npad * sizeof(double));
+    L.part = take((size_t)std::max(B.smax, B.sym ? B.tmax : 0) * d * npad * sizeof(double));
     L.items = take((size_t)B.max_items * 8 * sizeof(int));
     L.rows = take((size_t)B.n_rows * 4 * sizeof(int));
     L.eitems = take((size_t)B.n_eitems * 8 * sizeof(int));
@@ -479,6 +519,8 @@ BatchLayout batch_layout(int model, int prec, const Batch &B)
     L.eoff = take((B.nb + 1) * sizeof(int));
     L.roff = take((B.nb + 1) * sizeof(int));
     L.off = take((B.nb + 1) * sizeof(int64_t));
+    L.sitems = take(B.sitems.size() * sizeof(int));
+    L.srows = take(B.srows.size() * sizeof(int));
     L.total = o;
     return L;
 }
@@ -671,6 +713,8 @@ int md_batch_init(md_ctx **out, int model, int prec, int nb, const int64_t *offs
     B->d_eoff = reinterpret_cast<int *>(c->ws + L.eoff);
     B->d_roff = reinterpret_cast<int *>(c->ws + L.roff);
     B->d_off = reinterpret_cast<int64_t *>(c->ws + L.off);
+    B->d_sitems = c->ws + L.sitems;
+    B->d_srows = c->ws + L.srows;
     c->tiles = batch_default_tiles(*B);
     build_lists(*B, c->tiles);
     hipError_t e = hipGetDevice(&c->dev);
@@ -683,6 +727,10 @@ int md_batch_init(md_ctx **out, int model, int prec, int nb, const int64_t *offs
     if (e == hipSuccess) e = hipMemcpyAsync(B->d_eoff, B->eoff.data(), (nb + 1) * sizeof(int), h2d, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(B->d_roff, B->roff.data(), (nb + 1) * sizeof(int), h2d, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(B->d_off, B->off.data(), (nb + 1) * sizeof(int64_t), h2d, c->stream);
+    if (e == hipSuccess && !B->sitems.empty())
+        e = hipMemcpyAsync(B->d_sitems, B->sitems.data(), B->sitems.size() * sizeof(int), h2d, c->stream);
+    if (e == hipSuccess && !B->srows.empty())
+        e = hipMemcpyAsync(B->d_srows, B->srows.data(), B->srows.size() * sizeof(int), h2d, c->stream);
     if (e != hipSuccess) {
         delete c;
         return MD_EDEVICE;
@@ -741,9 +789,9 @@ int md_set_launch(md_ctx *c, int mode)
         return fail(c, MD_EINVAL, "md_set_launch: unknown mode %d", mode);
     if (mode == MD_LAUNCH_SYMMETRIC && !sym_ok(c))
         return fail(c, MD_EUNSUPPORTED,
-                    "md_set_launch: the symmetric launch needs a single 2D or Ring system, MD_MIXED or MD_FP64, "
-                    "%lld <= n <= %lld",
-                    (long long)kSymMinN, (long long)kSymMaxN);
+                    "md_set_launch: the symmetric launch needs a 2D or Ring system, MD_MIXED or MD_FP64 (ensembles: "
+                    "MD_MIXED, MD_MIXED_KAHAN, Ring MD_FP64), %lld <= n <= %lld (ensembles: every N_b <= %lld)",
+                    (long long)kSymMinN, (long long)kSymMaxN, (long long)kSymMaxN);
     if (mode == MD_LAUNCH_FUSED && !fused_ok(c, c->tiles))
         return fail(c, MD_EUNSUPPORTED,
                     "md_set_launch: the fused launch needs a single Ring or 2D system with n <= %lld and tiles it "

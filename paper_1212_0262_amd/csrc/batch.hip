@@ -8,13 +8,15 @@
 // Layout: the realizations are concatenated, [d][ntot] FP64 structure of arrays
 // with CSR offsets off[b] .. off[b+1].
 //
-// Scheduling: one launch per stage for the whole ensemble.  The host cuts every
+// Scheduling (staged form): one launch per stage for the whole ensemble.  The host cuts every
 // realization into (i-block, j-chunk) work items -- an i-block of
 // 64 * i_per_lane * waves particles against a j-chunk of one realization's own
 // particles -- and sorts them by cost, largest first, so that the 260x spread of
 // N_b^2 does not leave a tail.  Each item writes its own slot of the partial
 // buffer; the update kernel adds a particle's slots in chunk order, so results
-// do not depend on the schedule (bitwise reproducible).
+// do not depend on the schedule (bitwise reproducible).  The symmetric form
+// (k_batch_sym) instead takes tile pairs within each realization, each pair of
+// particles evaluated once.
 #include "device.h"
 #include "md_internal.h"
 #include "pair_terms.h"
@@ -26,7 +28,7 @@ using namespace pairs;
 
 // Pair work item: a = (b, i0, i1, slot), c = (j0, j1, 0, 0); global indices.
 struct alignas(32) PairItem {
-    int b, i0, i1, slot, j0, j1, pad0, pad1;
+    int b, i0, i1, slot, j0, j1, slot_j, pad;  // slot_j: the symmetric form's j-side slot
 };
 
 template <typename T, typename A, int IPL>
@@ -315,6 +317,87 @@ __global__ __launch_bounds__(256) void k_batch_pair_ring_win(const PairItem *__r
     }
 }
 
+// Symmetric form (sym_tile in pair_terms.h): a work item is a tile pair
+// (a, b), a < b, of one realization, or one of its diagonal tiles (SYM = false).
+// it.i0, it.j0: the tiles' first particles; it.i1, it.j1: the realization's end.
+// Particles past the end read their realization's last operand and replace it by
+// the pad value, whose terms vanish.  The i side goes to slot it.slot of the i
+// particles, the j side (the wavefronts' sums added in FP64, fixed order, after
+// every 64-j block) to slot it.slot_j of the j particles.
+template <int MODEL, typename T, typename A, bool SYM>
+__global__ __launch_bounds__(kSymWaves * kWave) void k_batch_sym(const PairItem *__restrict__ items,
+                                                                 const T *__restrict__ r0, const T *__restrict__ r1,
+                                                                 const double *__restrict__ beps, int npad,
+                                                                 double *__restrict__ part)
+{
+    constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
+    __shared__ double jw[SYM ? kSymWaves : 1][D][SYM ? kWave : 1];
+    const PairItem it = items[blockIdx.x];
+    const double eb = beps[it.b];
+    const T e = MODEL == MD_GRAV2D ? (T)eb : sizeof(T) == 4 ? (T)(2.0 * eb) : (T)(1.0 + eb);
+    const T pad = sym_pad<MODEL, T>();
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int ib = it.i0 + wave * kWave * kSymIpl + lane;
+    T u0[kSymIpl], u1[kSymIpl];
+    A acc[D][kSymIpl];
+#pragma unroll
+    for (int k = 0; k < kSymIpl; ++k) {
+        const int i = ib + k * kWave;
+        const int ic = min(i, it.i1 - 1);
+        u0[k] = i < it.i1 ? r0[ic] : pad;
+        u1[k] = i < it.i1 ? r1[ic] : pad;
+    }
+    sym_tile<MODEL, T, A, SYM>(
+        u0, u1, e, lane,
+        [&](int blk, T &v0, T &v1) {
+            const int j = it.j0 + blk * kWave + lane;
+            const int jc = min(j, it.j1 - 1);
+            v0 = j < it.j1 ? r0[jc] : pad;
+            v1 = j < it.j1 ? r1[jc] : pad;
+        },
+        [&](int blk, int m, A (&sj)[D]) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) jw[wave][d][m] = sj[d].get();
+            __syncthreads();
+            if (threadIdx.x < D * kWave) {
+                const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
+                const int j = it.j0 + blk * kWave + mm;
+                if (j < it.j1) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kSymWaves; ++w) t += jw[w][d][mm];
+                    part[(size_t)(D * it.slot_j + d) * npad + j] = t;
+                }
+            }
+            __syncthreads();
+        },
+        acc);
+#pragma unroll
+    for (int k = 0; k < kSymIpl; ++k) {
+        const int i = ib + k * kWave;
+        if (i < it.i1) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) part[(size_t)(D * it.slot + d) * npad + i] = acc[d][k].get();
+        }
+    }
+}
+
+template <int MODEL, typename T, typename A>
+hipError_t sym_launch(md_ctx *c)
+{
+    const Batch &B = *c->batch;
+    const T *r0 = static_cast<const T *>(c->ops);
+    const int npad = (int)c->npad;
+    const PairItem *items = reinterpret_cast<const PairItem *>(B.d_sitems);
+    const dim3 block(kSymWaves * kWave);
+    if (B.n_soff > 0)
+        hipLaunchKernelGGL((k_batch_sym<MODEL, T, A, true>), dim3((unsigned)B.n_soff), block, 0, c->stream, items, r0,
+                           r0 + npad, B.d_eps, npad, c->part);
+    hipLaunchKernelGGL((k_batch_sym<MODEL, T, A, false>), dim3((unsigned)B.n_sdiag), block, 0, c->stream,
+                       items + B.n_soff, r0, r0 + npad, B.d_eps, npad, c->part);
+    return hipGetLastError();
+}
+
 int prep_kind(const md_ctx *c)
 {
     if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? PREP_NONE : PREP_CAST32;
@@ -358,6 +441,13 @@ hipError_t pair_launch(md_ctx *c, const void *src)
 
 hipError_t batch_pair(md_ctx *c, const double *q)
 {
+    if (launch_form(c) == MD_LAUNCH_SYMMETRIC) {
+        if (c->model == MD_GRAV2D)
+            return c->prec == MD_MIXED_KAHAN ? sym_launch<MD_GRAV2D, float, AccKahan>(c)
+                                             : sym_launch<MD_GRAV2D, float, AccTile>(c);
+        if (c->prec == MD_FP64) return sym_launch<MD_RING, double, AccF64>(c);
+        return c->prec == MD_MIXED_KAHAN ? sym_launch<MD_RING, float, AccKahan>(c) : sym_launch<MD_RING, float, AccTile>(c);
+    }
     const void *src = (c->model == MD_GRAV2D && c->prec == MD_FP64) ? (const void *)q : (const void *)c->ops;
     switch (c->prec) {
     case MD_FP64: return pair_launch<double, AccF64>(c, src);
@@ -374,7 +464,8 @@ hipError_t batch_update(md_ctx *c, int flags, double kick1, double kick2, double
     const int pk = prep_kind(c);
     if (pk == PREP_NONE) flags &= ~UPD_PREP;
     const dim3 grid((unsigned)B.n_rows), block(256);
-    const int4 *rows = reinterpret_cast<const int4 *>(B.d_rows);
+    // the symmetric form's rows carry S_b = T_b tile slots
+    const int4 *rows = reinterpret_cast<const int4 *>(launch_form(c) == MD_LAUNCH_SYMMETRIC ? B.d_srows : B.d_rows);
     const int npad = (int)c->npad, ntot = (int)c->n;
 #define MD_BUPD(D_, P_)                                                                                         \
     hipLaunchKernelGGL((k_batch_update<D_, P_>), grid, block, 0, c->stream, rows, B.d_pref, c->part, npad, ntot, \

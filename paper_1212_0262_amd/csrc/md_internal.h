@@ -80,6 +80,14 @@ struct Batch {
     std::vector<int> eoff, roff;    // per-realization ranges of energy / row items
     int n_items = 0, n_rows = 0, n_eitems = 0, max_items = 0;
     void *d_items = nullptr, *d_rows = nullptr, *d_eitems = nullptr;
+    // symmetric form: tile pairs within each realization, 8 ints each
+    // (b, i0, i1, slot_i, j0, j1, slot_j, 0), the n_soff tile pairs a < b first,
+    // then the n_sdiag diagonal tiles; srows: the row items with S_b = T_b tiles
+    bool sym = false;  // the ensemble can take the symmetric form
+    int tmax = 0;      // most tiles of one realization
+    std::vector<int> sitems, srows;
+    int n_soff = 0, n_sdiag = 0;
+    void *d_sitems = nullptr, *d_srows = nullptr;
     double *d_eps = nullptr, *d_pref = nullptr, *d_ered = nullptr, *d_kred = nullptr;
     int *d_eoff = nullptr, *d_roff = nullptr;
     int64_t *d_off = nullptr;

@@ -25,6 +25,8 @@
 #include "md_internal.h"
 #include "pair_terms.h"
 
+#include <type_traits>
+
 namespace md {
 namespace {
 
@@ -223,32 +225,16 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 
 // ------------------------------------------------------- symmetric kernels --
 
-// The 2D pair term of the gradient of eq. 3 is odd in r_i - r_j, and the Ring term
-// of eq. 9 is odd in ti - tj, so one evaluation serves both particles (Newton's
-// third law).  The particles are cut into tiles of kSymTile = 4 wavefronts x 64
-// lanes x 4 i.  A block of k_sym<MODEL, T, true> owns a tile pair (a, b), a < b:
-// its lanes hold the i of tile a in registers, and tile b streams through in
-// blocks of 64 j.  At step s of a 64-j block, lane l pairs its 4 i with
-// j = (l + s) mod 64: the j operands and the j-side sums move one lane per step
-// through ds_bpermute (the LDS crossbar, no VALU issue; DPP lane moves measured
-// 2-3x the cost of an FMA on gfx950), so every lane adds to a different j and no
-// atomics are needed.
-//   2D, per pair: 2 differences, r^2 + eps (2 FMA), 1 reciprocal, 2 FMA for the i
-//     side (the staged form's term) and 2 for the j side (its negative).
-//   Ring, per pair: the factors p q of the staged form's term (ring_factors; p is
-//     exactly antisymmetric, q symmetric), fma(p, q) on the i side and
-//     fma(-p, q) on the j side.
-//   FP32 (MD_MIXED):
-//     i side: FP32 partial over 128 j, folded into FP64; the tile's sum goes to
-//             slot b of the i particles.
-//     j side: FP32 sum over the 256 i of a wavefront; the 4 wavefronts are added
-//             in FP64 in a fixed order at the end of the tile, into slot a of the
-//             j particles.
-//   FP64: the same in FP64 throughout; the wavefronts' j-side sums are added
-//     (same order) after every 64-j block, through a small LDS buffer.
-// k_sym<MODEL, T, false> takes a diagonal tile (a, a): every ordered pair of the
-// tile, i side only, into slot a.  Each particle thus receives one slot per tile
-// and the update kernel adds them in slot order: a fixed order, no atomics.
+// One launch of k_sym<MODEL, T, A, true> takes every tile pair (a, b), a < b, of
+// a single system (the scheme of sym_tile in pair_terms.h); k_sym<..., false>
+// takes the diagonal tiles (a, a): every ordered pair of the tile, i side only.
+//   i side: the tile's sum goes to slot b of the i particles (FP32: partials over
+//     128 j folded into FP64);
+//   j side: FP32 sum over the 256 i of a wavefront, the 4 wavefronts added in
+//     FP64 in a fixed order at the end of the tile (FP64 form: after every 64-j
+//     block, through a small LDS buffer), into slot a of the j particles.
+// Each particle thus receives one slot per tile and the update kernel adds them
+// in slot order: a fixed order, no atomics.
 // Pad particles (n .. npad - 1) contribute nothing:
 //   2D FP32: at (1e30, 1e30): r^2 overflows to +inf for any pair with a pad
 //     particle, the reciprocal is 0 and both terms are exactly zero (a pad-pad
@@ -257,26 +243,6 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 //     reciprocal of +inf would be NaN), so a term with a pad particle is about
 //     5e-151, below the last bit of any force sum larger than 1e-135;
 //   Ring: operands (0, 0): the numerator p is exactly 0 and q finite.
-constexpr int kSymIpl = 4, kSymWaves = kSymTile / (kWave * kSymIpl);
-template <int MODEL, typename T>
-constexpr T sym_pad()
-{
-    if (MODEL == MD_RING) return T(0);
-    return sizeof(T) == 4 ? T(1e30f) : T(1e150);
-}
-
-__device__ __forceinline__ float lane_next(int addr, float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ double lane_next(int addr, double v)
-{
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
 // Tile pair (a, b), a < b, of linear index t in row-major order over a.
 __device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
 {
@@ -290,15 +256,13 @@ __device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
     b = r + 1 + (t - row0(r));
 }
 
-// r0, r1: the operand rows ([2][npad], padded); e: eps (2D), 1 + eps (Ring FP64)
-// or 2 eps (Ring FP32); part: slots [ntile][D][npad].
-template <int MODEL, typename T, bool SYM>
+// r0, r1: the operand rows ([2][npad], padded); part: slots [ntile][D][npad].
+template <int MODEL, typename T, typename A, bool SYM>
 __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1,
                                                            int npad, int ntile, T e, double *__restrict__ part)
 {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
-    constexpr int IPL = kSymIpl, NBLK = kSymTile / kWave;
     // FP32: the wavefronts' j-side sums of the whole tile; FP64: of one 64-j block
     __shared__ float jw32[SYM && F32 ? kSymWaves : 1][D][SYM && F32 ? kSymTile : 1];
     __shared__ double jw64[SYM && !F32 ? kSymWaves : 1][D][SYM && !F32 ? kWave : 1];
@@ -306,93 +270,44 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
     if (SYM) sym_tile_pair(blockIdx.x, ntile, a, b);
     else a = b = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int i0 = a * kSymTile + wave * kWave * IPL + lane;
-    T u0[IPL], u1[IPL], acc[D][IPL];
-    double fold[D][IPL];  // FP32: the folded i-side sums
+    const int i0 = a * kSymTile + wave * kWave * kSymIpl + lane;
+    T u0[kSymIpl], u1[kSymIpl];
+    A acc[D][kSymIpl];
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
+    for (int k = 0; k < kSymIpl; ++k) {
         u0[k] = r0[i0 + k * kWave];
         u1[k] = r1[i0 + k * kWave];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            acc[d][k] = T(0);
-            fold[d][k] = 0.0;
-        }
     }
-    const int next = ((lane + 1) & (kWave - 1)) * 4;  // ds_bpermute byte address of lane l + 1
     const int jl = b * kSymTile + lane;
-    T v0n = r0[jl], v1n = r1[jl];
-    for (int blk = 0; blk < NBLK; ++blk) {
-        T v0 = v0n, v1 = v1n;
-        if (blk + 1 < NBLK) {
-            v0n = r0[jl + (blk + 1) * kWave];
-            v1n = r1[jl + (blk + 1) * kWave];
-        }
-        T sj[D];  // j-side sums of the j this lane holds
+    sym_tile<MODEL, T, A, SYM>(
+        u0, u1, e, lane,
+        [&](int blk, T &v0, T &v1) {
+            v0 = r0[jl + blk * kWave];
+            v1 = r1[jl + blk * kWave];
+        },
+        [&](int blk, int m, A (&sj)[D]) {
+            if constexpr (F32) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) sj[d] = T(0);
-#pragma unroll 16
-        for (int s = 0; s < kWave; ++s) {
-            if (s) {
-                v0 = lane_next(next, v0);
-                v1 = lane_next(next, v1);
-                if (SYM) {
+                for (int d = 0; d < D; ++d) jw32[wave][d][blk * kWave + m] = (float)sj[d].get();
+            } else {
 #pragma unroll
-                    for (int d = 0; d < D; ++d) sj[d] = lane_next(next, sj[d]);
+                for (int d = 0; d < D; ++d) jw64[wave][d][m] = sj[d].get();
+                __syncthreads();
+                if (threadIdx.x < D * kWave) {
+                    const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
+                    double t = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kSymWaves; ++w) t += jw64[w][d][mm];
+                    part[(size_t)(D * a + d) * npad + b * kSymTile + blk * kWave + mm] = t;
                 }
+                __syncthreads();
             }
+        },
+        acc);
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) {
-                if constexpr (MODEL == MD_GRAV2D) {
-                    const T dx = v0 - u0[k], dy = v1 - u1[k];
-                    const T w = rcp_(fma_(dx, dx, fma_(dy, dy, e)));
-                    acc[0][k] = fma_(-dx, w, acc[0][k]);
-                    acc[1][k] = fma_(-dy, w, acc[1][k]);
-                    if (SYM) {
-                        sj[0] = fma_(dx, w, sj[0]);
-                        sj[1] = fma_(dy, w, sj[1]);
-                    }
-                } else {
-                    T p, q;
-                    ring_factors(u0[k], u1[k], v0, v1, e, p, q);
-                    acc[0][k] = fma_(p, q, acc[0][k]);
-                    if (SYM) sj[0] = fma_(-p, q, sj[0]);
-                }
-            }
-        }
-        // after step 63 lane l holds j = l - 1 (mod 64) of the block
-        const int jm = (lane + kWave - 1) & (kWave - 1);
-        if constexpr (SYM && F32) {
+    for (int k = 0; k < kSymIpl; ++k)
 #pragma unroll
-            for (int d = 0; d < D; ++d) jw32[wave][d][blk * kWave + jm] = sj[d];
-        } else if constexpr (SYM) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) jw64[wave][d][jm] = sj[d];
-            __syncthreads();
-            if (threadIdx.x < D * kWave) {
-                const int d = threadIdx.x / kWave, m = threadIdx.x & (kWave - 1);
-                double t = 0.0;
-#pragma unroll
-                for (int w = 0; w < kSymWaves; ++w) t += jw64[w][d][m];
-                part[(size_t)(D * a + d) * npad + b * kSymTile + blk * kWave + m] = t;
-            }
-            __syncthreads();
-        }
-        if (F32 && (blk & 1)) {  // fold every 128 j
-#pragma unroll
-            for (int k = 0; k < IPL; ++k)
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    fold[d][k] += (double)acc[d][k];
-                    acc[d][k] = T(0);
-                }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < IPL; ++k)
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-            part[(size_t)(D * b + d) * npad + i0 + k * kWave] = F32 ? fold[d][k] : (double)acc[d][k];
+        for (int d = 0; d < D; ++d) part[(size_t)(D * b + d) * npad + i0 + k * kWave] = acc[d][k].get();
     if constexpr (SYM && F32) {
         __syncthreads();
         for (int m = threadIdx.x; m < kSymTile; m += kSymWaves * kWave) {
@@ -431,10 +346,11 @@ hipError_t sym_launch(md_ctx *c)
     const T e = MODEL == MD_GRAV2D ? (T)c->eps : sizeof(T) == 4 ? (T)(2.0 * c->eps) : (T)(1.0 + c->eps);
     const dim3 block(kSymWaves * kWave);
     const int noff = ntile * (ntile - 1) / 2;
+    using A = std::conditional_t<sizeof(T) == 4, AccTile, AccF64>;
     if (noff > 0)
-        hipLaunchKernelGGL((k_sym<MODEL, T, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad, npad,
-                           ntile, e, c->part);
-    hipLaunchKernelGGL((k_sym<MODEL, T, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad, npad,
+        hipLaunchKernelGGL((k_sym<MODEL, T, A, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad,
+                           npad, ntile, e, c->part);
+    hipLaunchKernelGGL((k_sym<MODEL, T, A, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad, npad,
                        ntile, e, c->part);
     return hipGetLastError();
 }

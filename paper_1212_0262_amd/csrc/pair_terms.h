@@ -9,7 +9,23 @@
 namespace md {
 namespace pairs {
 
+// The value v of lane addr / 4 of the wavefront (ds_bpermute: the LDS crossbar,
+// no LDS memory and no VALU issue).
+__device__ __forceinline__ float lane_next(int addr, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_next(int addr, double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------- accumulators --
+// rotate(addr): take the accumulator of lane addr / 4 (the symmetric kernels move
+// the j-side sums with their j).
 
 // FP32 partial over a j tile, folded into an FP64 total once per tile.
 struct AccTile {
@@ -18,6 +34,7 @@ struct AccTile {
     __device__ __forceinline__ void add(float a, float b) { s = __builtin_fmaf(a, b, s); }
     __device__ __forceinline__ void fold() { t += (double)s; s = 0.f; }
     __device__ __forceinline__ double get() const { return t; }
+    __device__ __forceinline__ void rotate(int addr) { s = lane_next(addr, s); }
 };
 
 // Kahan-compensated FP32 sum of every pair term; -c holds the lost low part.
@@ -32,6 +49,11 @@ struct AccKahan {
     }
     __device__ __forceinline__ void fold() {}
     __device__ __forceinline__ double get() const { return (double)s - (double)c; }
+    __device__ __forceinline__ void rotate(int addr)
+    {
+        s = lane_next(addr, s);
+        c = lane_next(addr, c);
+    }
 };
 
 // Each FP32 pair term added into an FP64 accumulator.
@@ -40,6 +62,7 @@ struct AccPair64 {
     __device__ __forceinline__ void add(float a, float b) { t += (double)(a * b); }
     __device__ __forceinline__ void fold() {}
     __device__ __forceinline__ double get() const { return t; }
+    __device__ __forceinline__ void rotate(int addr) { t = lane_next(addr, t); }
 };
 
 // Plain FP64.
@@ -48,6 +71,7 @@ struct AccF64 {
     __device__ __forceinline__ void add(double a, double b) { t = __builtin_fma(a, b, t); }
     __device__ __forceinline__ void fold() {}
     __device__ __forceinline__ double get() const { return t; }
+    __device__ __forceinline__ void rotate(int addr) { t = lane_next(addr, t); }
 };
 
 __device__ __forceinline__ float rcp_(float x) { return rcp32(x); }
@@ -160,6 +184,98 @@ __device__ __forceinline__ void window_stream(const T *__restrict__ r0, const T 
             for (int u = 0; u < j1 - g; ++u) term(win[0][off + u], win[1][off + u]);
         }
         if ((g + 16 - j0) % jtile == 0 || g + 16 >= j1) fold();
+    }
+}
+
+
+// ------------------------------------------------------- symmetric tile pass --
+
+// The 2D pair term of the gradient of eq. 3 is odd in r_i - r_j, and the Ring term
+// of eq. 9 is odd in ti - tj, so one evaluation serves both particles (Newton's
+// third law).  A tile is kSymTile = 4 wavefronts x 64 lanes x 4 i.  For a tile
+// pair (a, b) each wavefront holds its 256 i of tile a in registers and tile b
+// streams through in 16 blocks of 64 j.  At step s of a 64-j block, lane l pairs
+// its 4 i with j = (l + s) mod 64: the j operands and the j-side sums move one
+// lane per step through ds_bpermute (no VALU issue; DPP lane moves measured 2-3x
+// the cost of an FMA on gfx950), so every lane adds to a different j and no
+// atomics are needed.
+//   2D, per pair: 2 differences, r^2 + eps (2 FMA), 1 reciprocal; the i side adds
+//     the staged form's term (r_i - r_j) w, the j side its negative.
+//   Ring, per pair: the factors p q of the staged form's term (ring_factors; p is
+//     exactly antisymmetric, q symmetric); the i side adds p q, the j side -p q.
+// A is the accumulation policy of the precision form (AccTile: FP32, folded into
+// FP64 every 128 j on the i side; AccKahan; AccF64).  SYM = false: a diagonal tile,
+// every ordered pair, i side only.
+//   u0, u1:   the wavefront's i operands (4 per lane);
+//   e:        eps (2D), 1 + eps (Ring FP64) or 2 eps (Ring FP32);
+//   load(blk, v0, v1): this lane's j operands of 64-j block blk (lane l: j = l);
+//   jsum(blk, m, sj):  the j-side sums of the block; sj belongs to j = m of it;
+//   acc:      the i-side accumulators, [component][i].
+constexpr int kSymIpl = 4, kSymWaves = kSymTile / (kWave * kSymIpl);
+
+// Operand value of a pad particle (beyond the system's or realization's end): its
+// pair terms vanish.  2D FP32: r^2 overflows to +inf, the reciprocal is 0 and the
+// terms exactly 0.  2D FP64: r^2 about 2e300 (the refined FP64 reciprocal of +inf
+// would be NaN), terms about 5e-151.  Ring: the numerator p is exactly 0.
+template <int MODEL, typename T>
+__host__ __device__ constexpr T sym_pad()
+{
+    if (MODEL == MD_RING) return T(0);
+    return sizeof(T) == 4 ? T(1e30f) : T(1e150);
+}
+
+template <int MODEL, typename T, typename A, bool SYM, typename Load, typename JSum>
+__device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[kSymIpl], T e, int lane, Load &&load,
+                                         JSum &&jsum, A (&acc)[MODEL == MD_GRAV2D ? 2 : 1][kSymIpl])
+{
+    constexpr int D = MODEL == MD_GRAV2D ? 2 : 1, NBLK = kSymTile / kWave;
+    const int next = ((lane + 1) & (kWave - 1)) * 4;  // ds_bpermute byte address of lane l + 1
+    T v0n, v1n;
+    load(0, v0n, v1n);
+    for (int blk = 0; blk < NBLK; ++blk) {
+        T v0 = v0n, v1 = v1n;
+        if (blk + 1 < NBLK) load(blk + 1, v0n, v1n);
+        A sj[D];  // j-side sums of the j this lane holds
+#pragma unroll 16
+        for (int s = 0; s < kWave; ++s) {
+            if (s) {
+                v0 = lane_next(next, v0);
+                v1 = lane_next(next, v1);
+                if (SYM) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) sj[d].rotate(next);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kSymIpl; ++k) {
+                if constexpr (MODEL == MD_GRAV2D) {
+                    const T dx = v0 - u0[k], dy = v1 - u1[k];
+                    const T w = rcp_(fma_(dx, dx, fma_(dy, dy, e)));
+                    acc[0][k].add(-dx, w);
+                    acc[1][k].add(-dy, w);
+                    if (SYM) {
+                        sj[0].add(dx, w);
+                        sj[1].add(dy, w);
+                    }
+                } else {
+                    T p, q;
+                    ring_factors(u0[k], u1[k], v0, v1, e, p, q);
+                    acc[0][k].add(p, q);
+                    if (SYM) sj[0].add(-p, q);
+                }
+            }
+        }
+        if (SYM) {  // after step 63 lane l holds j = l - 1 (mod 64) of the block
+#pragma unroll
+            for (int d = 0; d < D; ++d) sj[d].fold();
+            jsum(blk, (lane + kWave - 1) & (kWave - 1), sj);
+        }
+        if (blk & 1) {  // every 128 j
+#pragma unroll
+            for (int k = 0; k < kSymIpl; ++k)
+#pragma unroll
+                for (int d = 0; d < D; ++d) acc[d][k].fold();
+        }
     }
 }
 

@@ -196,7 +196,7 @@ def test_launch_form_and_refusals():
         with pytest.raises(md.MDError):
             md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
         ctx.close()
-    batch = md.md_batch_init(GRAV2D, md.MIXED, [0, 3000, 6000], EPS)
+    batch = md.md_batch_init(GRAV2D, md.FP64, [0, 3000, 6000], EPS)  # no symmetric FP64 2D ensembles
     with pytest.raises(md.MDError):
         md.md_set_launch(batch, md.LAUNCH_SYMMETRIC)
     for c in (big, big64, ring, ring64, below, batch):
@@ -232,3 +232,120 @@ def test_symmetric_step_graph_replays():
         np.testing.assert_array_equal(host(pg), host(pe))
         np.testing.assert_array_equal(host(fg), host(fe))
     ctx.close()
+
+
+# ------------------------------------------------------------------ ensembles --
+
+BATCH_SIZES = [1, 700, 1024, 1025, 2048, 3000, 5000]
+
+
+def _ensemble(model, sizes, seed):
+    qs, ps = [], []
+    for b, n in enumerate(sizes):
+        q, p = inputs.grav2d_disk(n, seed=seed + b) if model == GRAV2D else inputs.ensemble_member(b, n, seed=seed)
+        qs.append(q)
+        ps.append(p)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return np.concatenate(qs, axis=1), np.concatenate(ps, axis=1), off
+
+
+def _batch_force(model, prec, q, off, eps_b, launch):
+    ctx = md.md_batch_init(model, prec, off, eps_b)
+    md.md_set_launch(ctx, launch)
+    assert md.md_get_launch(ctx) == launch
+    qd = dev(q)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    out = host(f)
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("model,prec,eps", [(RING, md.MIXED, 0.01), (RING, md.MIXED_KAHAN, 0.01), (RING, md.FP64, 0.01),
+                                            (GRAV2D, md.MIXED, 1e-3), (GRAV2D, md.MIXED_KAHAN, 1e-3)])
+def test_symmetric_ensemble_matches_oracle(model, prec, eps):
+    """Every realization (ragged last tiles, single-tile and one-particle ones,
+    uneven eps) against the oracle on that realization alone."""
+    q, _, off = _ensemble(model, BATCH_SIZES, seed=50)
+    eps_b = np.full(len(BATCH_SIZES), eps)
+    eps_b[-2] = 2 * eps
+    f = _batch_force(model, prec, q, off, eps_b, md.LAUNCH_SYMMETRIC)
+    tol = 5e-12 if prec == md.FP64 else FORCE_TOL[(model, md.MIXED)]
+    for b, n in enumerate(BATCH_SIZES):
+        qb, fb = q[:, off[b]:off[b + 1]], f[:, off[b]:off[b + 1]]
+        if n == 1:
+            assert np.all(fb == 0.0)
+            continue
+        err = rel_inf(fb, oracle.force(model, qb, eps_b[b]))
+        print(f"symmetric ensemble model={model} prec={prec} N_b={n} rel_err={err:.3e}")
+        assert err < tol, (b, n, err)
+
+
+def test_symmetric_ensemble_against_staged_and_repeatable():
+    sizes = [3000, 9000, 16384, 12000, 1500]
+    q, _, off = _ensemble(RING, sizes, seed=60)
+    eps_b = np.full(len(sizes), 0.01)
+    fs = _batch_force(RING, md.MIXED_KAHAN, q, off, eps_b, md.LAUNCH_SYMMETRIC)
+    ft = _batch_force(RING, md.MIXED_KAHAN, q, off, eps_b, md.LAUNCH_STAGED)
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        assert rel_inf(fs[:, sl], ft[:, sl]) < FORCE_TOL[(RING, md.MIXED)]
+    assert np.array_equal(fs, _batch_force(RING, md.MIXED_KAHAN, q, off, eps_b, md.LAUNCH_SYMMETRIC))
+
+
+def test_symmetric_ensemble_step_and_graph():
+    """A few steps of a Ring ensemble in the symmetric form against the oracle per
+    realization, and the same steps graph-captured, equal on every replay."""
+    sizes = [2048, 5000, 1024, 3500]
+    q0, p0, off = _ensemble(RING, sizes, seed=70)
+    eps_b = np.full(len(sizes), 0.01)
+    ctx = md.md_batch_init(RING, md.MIXED_KAHAN, off, eps_b)
+    md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
+    s = torch.cuda.Stream()
+    md.md_set_stream(ctx, s)
+    q, p = dev(q0), dev(p0)
+    f = torch.empty_like(q)
+    with torch.cuda.stream(s):
+        md.md_force(ctx, q, f)
+    s.synchronize()
+    qe, pe, fe = q.clone(), p.clone(), f.clone()
+    with torch.cuda.stream(s):
+        md.md_step(ctx, qe, pe, fe, 0.05, 4)
+    s.synchronize()
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        fo = oracle.force(RING, q0[:, sl], 0.01)
+        qo, po, _ = oracle.step(RING, q0[:, sl], p0[:, sl], fo, 0.05, 4, 0.01)
+        assert np.abs(host(qe)[:, sl] - qo).max() < 1e-5
+        assert np.abs(host(pe)[:, sl] - po).max() < 1e-4
+    g = torch.cuda.CUDAGraph()
+    qg, pg, fg = q.clone(), p.clone(), f.clone()
+    with torch.cuda.graph(g, stream=s):
+        md.md_step(ctx, qg, pg, fg, 0.05, 2)
+    for rep in range(3):
+        qg.copy_(q); pg.copy_(p); fg.copy_(f)
+        torch.cuda.synchronize()
+        g.replay(); g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(qg), host(qe))
+        np.testing.assert_array_equal(host(pg), host(pe))
+    ctx.close()
+
+
+def test_symmetric_ensemble_launch_form_and_refusals():
+    small = md.md_batch_init(RING, md.MIXED_KAHAN, [0, 500, 1500, 2000], [0.01] * 3)
+    assert md.md_get_launch(small) == md.LAUNCH_STAGED          # more diagonal tiles than tile pairs
+    big = md.md_batch_init(RING, md.MIXED_KAHAN, [0, 8000, 16000], [0.01] * 2)
+    assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
+    md.md_set_launch(big, md.LAUNCH_STAGED)
+    assert md.md_get_launch(big) == md.LAUNCH_STAGED
+    with pytest.raises(md.MDError):
+        md.md_set_launch(big, md.LAUNCH_FUSED)
+    for model, prec in [(GRAV2D, md.FP64), (RING, md.MIXED_PAIRF64), (GRAV2D, md.MIXED_PAIRF64)]:
+        c = md.md_batch_init(model, prec, [0, 3000, 9000], [0.01] * 2)
+        assert md.md_get_launch(c) == md.LAUNCH_STAGED
+        with pytest.raises(md.MDError):
+            md.md_set_launch(c, md.LAUNCH_SYMMETRIC)
+        c.close()
+    for c in (small, big):
+        c.close()
