@@ -133,6 +133,8 @@ int md_init(md_ctx **out, int model, int prec, int64_t n, double eps,
  * min(32, N_max/64).  md_batch_init copies its work lists into the workspace with
  * asynchronous copies on hip_stream (the host arrays may be freed on return);
  * md_set_tiles on a batch context re-uploads the tile-dependent lists the same way.
+ * The workspace figure includes the symmetric launch form's tile-pair lists and
+ * slots when the ensemble can take it (md_set_launch).
  * Errors as md_init (MD_EINVAL for a bad offsets/eps array).
  */
 size_t md_batch_workspace_bytes(int model, int prec, int nb, const int64_t *offsets, const double *eps);
@@ -202,13 +204,20 @@ int md_max_j_split(int64_t n);
  *                     FP32 form positions at 1e30 (exact zeros), the 2D FP64
  *                     form positions at 1e150 (terms of about 5e-151); 2D
  *                     positions must stay far below both.  Tiles
- *                     (md_set_tiles) do not apply to it.  MD_EUNSUPPORTED for
- *                     other models, precisions, batches or n;
+ *                     (md_set_tiles) do not apply to it.  Ensembles
+ *                     (md_batch_init) take tile pairs within each realization:
+ *                     Ring with MD_MIXED, MD_MIXED_KAHAN (the compensated sums
+ *                     kept on both sides) or MD_FP64, 2D with MD_MIXED or
+ *                     MD_MIXED_KAHAN, every N_b <= 524288.  MD_EUNSUPPORTED for
+ *                     other models, precisions or n;
  *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 8192 (the
  *                     built-in tiles there are the fused form's), symmetric
- *                     when it applies and n >= MD_SYMMETRIC_AUTO_N, else staged.
+ *                     when it applies and n >= MD_SYMMETRIC_AUTO_N, else staged;
+ *                     for ensembles, symmetric when it applies and their tile
+ *                     pairs a < b outnumber their diagonal tiles.
  * md_get_launch returns the form md_step will take (STAGED, FUSED or
- * SYMMETRIC), or a negative status.  HMF and batch contexts are always STAGED.
+ * SYMMETRIC), or a negative status.  HMF contexts are always STAGED, ensembles
+ * STAGED or SYMMETRIC.
  */
 enum md_launch { MD_LAUNCH_AUTO = 0, MD_LAUNCH_STAGED = 1, MD_LAUNCH_FUSED = 2, MD_LAUNCH_SYMMETRIC = 3 };
 #define MD_SYMMETRIC_AUTO_N 49152
