@@ -94,8 +94,13 @@ def tune(ctx: md.Context, q: torch.Tensor, configs: Optional[Iterable] = None, r
          cache: Optional[str] = DEFAULT_CACHE, measure: str = "step") -> tuple:
     """Time every configuration (one md_step, or md_force with measure="force"),
     leave the fastest applied to ctx, record it in the cache (if given); returns
-    (best_tiles, [(tiles, ms), ...] sorted by time)."""
+    (best_tiles, [(tiles, ms), ...] sorted by time).  A context in the symmetric
+    launch form has no tile choice: it is timed once as it stands (set the staged
+    form with md_set_launch first to tune that form's tiles)."""
     timer = time_step if measure == "step" else time_force
+    if md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC:
+        tiles = md.md_get_tiles(ctx)
+        return tiles, [(tiles, timer(ctx, q, reps))]
     table = []
     for t in (configs if configs is not None else candidates(ctx)):
         try:

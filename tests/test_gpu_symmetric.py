@@ -349,3 +349,16 @@ def test_symmetric_ensemble_launch_form_and_refusals():
         c.close()
     for c in (small, big):
         c.close()
+
+
+def test_autotuner_times_the_symmetric_form_once():
+    """The symmetric form has no tile choice: tune() times it once and leaves the tiles."""
+    from paper_1212_0262_amd import autotune
+    n = md.SYMMETRIC_AUTO_N
+    q, _ = inputs.grav2d_disk(n, seed=81)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, EPS)
+    assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
+    tiles = md.md_get_tiles(ctx)
+    best, table = autotune.tune(ctx, dev(q), configs=[(1, 4, 8, 128), (2, 2, 4, 128)], reps=1, cache=None)
+    assert len(table) == 1 and tuple(best) == tuple(tiles) and md.md_get_tiles(ctx) == tuple(tiles)
+    ctx.close()
