@@ -98,7 +98,7 @@ enum md_status {
  * Workspace bytes a context for (model, prec, n) needs; 0 for an invalid
  * combination.  The figure covers every tile configuration md_set_tiles
  * accepts for this n, and every launch form the context can take: for
- * MD_GRAV2D and MD_RING with MD_MIXED or MD_FP64 and 2048 <= n <= 524288 it
+ * MD_GRAV2D and MD_RING with MD_MIXED or MD_FP64 and 2048 <= n <= 1048576 it
  * includes the symmetric form's partial slots, 8 d n'^2 / 1024 bytes with n' = n
  * rounded up to a multiple of 1024 (1.07 GB for 2D at n = 262144).
  */
@@ -187,7 +187,7 @@ int md_max_j_split(int64_t n);
  *                     (MD_EUNSUPPORTED otherwise; md_set_tiles then refuses
  *                     tiles outside that range);
  *   MD_LAUNCH_SYMMETRIC  2D gravity or Ring, MD_MIXED or MD_FP64,
- *                     2048 <= n <= 524288: each pair is evaluated once and
+ *                     2048 <= n <= 1048576: each pair is evaluated once and
  *                     added to both particles with opposite signs (the terms of
  *                     the gradient of eq. 3 and of eq. 9 are odd in the pair's
  *                     difference), which halves the pair evaluations of the
@@ -208,7 +208,7 @@ int md_max_j_split(int64_t n);
  *                     (md_batch_init) take tile pairs within each realization:
  *                     Ring with MD_MIXED, MD_MIXED_KAHAN (the compensated sums
  *                     kept on both sides) or MD_FP64, 2D with MD_MIXED or
- *                     MD_MIXED_KAHAN, every N_b <= 524288.  MD_EUNSUPPORTED for
+ *                     MD_MIXED_KAHAN, every N_b <= 1048576.  MD_EUNSUPPORTED for
  *                     other models, precisions or n;
  *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 8192 (the
  *                     built-in tiles there are the fused form's), symmetric

@@ -45,7 +45,7 @@ constexpr int kFusedLdsBytes = 49152;   // LDS per fused block (split evenly bet
 constexpr int64_t kFusedAutoN = 8192;   // MD_LAUNCH_AUTO takes the fused form up to this n
 constexpr int kSymTile = 1024;          // particles per tile of the symmetric 2D form (4 waves x 64 x 4 i)
 constexpr int64_t kSymMinN = 2048;      // the symmetric form needs two tiles at least
-constexpr int64_t kSymMaxN = 524288;    // and at most 512 tiles (its partial slots: 16 n^2 / 1024 bytes)
+constexpr int64_t kSymMaxN = 1 << 20;   // and at most 1024 tiles (its partial slots: 8 d n^2 / 1024 bytes)
 constexpr int64_t kSymAutoN = MD_SYMMETRIC_AUTO_N;  // MD_LAUNCH_AUTO takes it from this n
 
 // Lane groups per wavefront of the fused stage for j_split j ranges: the largest

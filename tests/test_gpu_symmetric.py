@@ -153,9 +153,10 @@ def test_symmetric_trajectory_matches_oracle(prec, model, eps, dt):
 
 @pytest.mark.parametrize("model,eps", MODELS)
 def test_symmetric_at_the_maximum_size(model, eps):
-    """n = 524288, the largest n the form accepts (512 tiles; the Ring slots take
-    2.1 GB): sampled rows of the automatic (symmetric) mixed form against the oracle."""
-    n = 524_288
+    """n = 2^20, the largest n the form accepts (1024 tiles; the slots take 8 GB
+    for Ring, 16 GB for 2D): sampled rows of the automatic (symmetric) mixed form
+    against the oracle."""
+    n = 1 << 20
     q, _ = _state(model, n, seed=41)
     ctx = md.md_init(model, md.MIXED, n, eps)
     assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
@@ -190,7 +191,7 @@ def test_launch_form_and_refusals():
     for model, prec, n in [(GRAV2D, md.MIXED_KAHAN, 50_000), (GRAV2D, md.MIXED_PAIRF64, 50_000),
                            (RING, md.MIXED_KAHAN, 50_000), (RING, md.MIXED_PAIRF64, 50_000),
                            (GRAV2D, md.MIXED, 2047), (GRAV2D, md.FP64, 2047), (RING, md.FP64, 2047),
-                           (GRAV2D, md.MIXED, 524_289), (RING, md.MIXED, 524_289)]:
+                           (GRAV2D, md.MIXED, (1 << 20) + 1), (RING, md.MIXED, (1 << 20) + 1)]:
         ctx = md.md_init(model, prec, n, EPS)
         assert md.md_get_launch(ctx) != md.LAUNCH_SYMMETRIC
         with pytest.raises(md.MDError):
