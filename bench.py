@@ -749,7 +749,7 @@ def grav2d_workload(md, torch, args):
         off = nt * (nt - 1) // 2 * SYM_TILE ** 2
         diag = nt * SYM_TILE ** 2
         executed = SYM_FLOPS_PER_EVAL * off + FLOPS_PER_PAIR * diag
-        kernel = "k_sym2d<true> (tile pairs) + k_sym2d<false> (diagonal tiles)"
+        kernel = "k_sym<2, float, AccTile, true> (tile pairs) + k_sym<2, float, AccTile, false> (diagonal tiles)"
         instr = {"valu_fp32": 8, "trans": 1, "per": "pair evaluated (tile pairs: both particles)"}
         evals = off + diag
     else:
