@@ -363,3 +363,42 @@ def test_autotuner_times_the_symmetric_form_once():
     best, table = autotune.tune(ctx, dev(q), configs=[(1, 4, 8, 128), (2, 2, 4, 128)], reps=1, cache=None)
     assert len(table) == 1 and tuple(best) == tuple(tiles) and md.md_get_tiles(ctx) == tuple(tiles)
     ctx.close()
+
+
+# ------------------------------------------------------------ random cases --
+
+hypothesis = pytest.importorskip("hypothesis")
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=25, deadline=None, derandomize=True)
+@given(model=st.sampled_from([RING, GRAV2D]), prec=st.sampled_from([md.MIXED, md.FP64]),
+       n=st.integers(min_value=2048, max_value=7000), eps_scale=st.sampled_from([0.1, 1.0, 10.0]),
+       seed=st.integers(min_value=0, max_value=10_000))
+def test_random_symmetric_systems_match_oracle(model, prec, n, eps_scale, seed):
+    """Random sizes (one to seven tiles, ragged or not), eps and seeds: the
+    symmetric form against the oracle with the staged form's tolerances."""
+    eps = (1e-3 if model == GRAV2D else 0.01) * eps_scale
+    q, _ = _state(model, n, seed=seed)
+    fg = _force(q, md.LAUNCH_SYMMETRIC, prec, model, eps)
+    assert rel_inf(fg, oracle.force(model, q, eps)) < FORCE_TOL[(model, prec)]
+
+
+@settings(max_examples=15, deadline=None, derandomize=True)
+@given(prec=st.sampled_from([md.MIXED, md.MIXED_KAHAN, md.FP64]),
+       sizes=st.lists(st.integers(min_value=1, max_value=4500), min_size=1, max_size=6),
+       seed=st.integers(min_value=0, max_value=10_000))
+def test_random_symmetric_ensembles_match_oracle(prec, sizes, seed):
+    """Random Ring ensembles (any mix of single-particle, single-tile and
+    multi-tile realizations) in the symmetric form, per realization against the
+    oracle."""
+    q, _, off = _ensemble(RING, sizes, seed=seed)
+    eps_b = np.full(len(sizes), 0.01)
+    f = _batch_force(RING, prec, q, off, eps_b, md.LAUNCH_SYMMETRIC)
+    tol = 5e-12 if prec == md.FP64 else FORCE_TOL[(RING, md.MIXED)]
+    for b, n in enumerate(sizes):
+        sl = slice(off[b], off[b + 1])
+        if n == 1:
+            assert np.all(f[:, sl] == 0.0)
+        else:
+            assert rel_inf(f[:, sl], oracle.force(RING, q[:, sl], 0.01)) < tol, (b, n)
