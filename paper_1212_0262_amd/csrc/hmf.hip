@@ -169,25 +169,29 @@ __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restr
 }
 
 // M[0..1] = (sum of the g partial pairs) / n, in a fixed order (one block of
-// 1024 threads; thread t adds partials t, t + 1024, ... in that order).  All of a
-// thread's loads are issued before the adds (g <= kHmfGrid = 32 * 1024).
+// 1024 threads; thread t adds partials t, t + 1024, ... in that order).  Loads go
+// out kFinBatch per thread at a time, which keeps the kernel in registers (no
+// private segment) at 1024 threads; g <= kHmfGrid takes at most 4 batches.
+constexpr int kFinBatch = 8;
+
 __global__ __launch_bounds__(1024) void k_hmf_finalize(const double *__restrict__ red, int g, int n,
                                                        double *__restrict__ M)
 {
     __shared__ double lds[2][16];
-    constexpr int kPer = kHmfGrid / 1024;
-    double vc[kPer], vs[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int b = threadIdx.x + 1024 * k;
-        vc[k] = b < g ? red[2 * b] : 0.0;
-        vs[k] = b < g ? red[2 * b + 1] : 0.0;
-    }
     double c = 0.0, s = 0.0;
+    for (int b0 = 0; b0 < g; b0 += 1024 * kFinBatch) {
+        double vc[kFinBatch], vs[kFinBatch];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        c += vc[k];
-        s += vs[k];
+        for (int k = 0; k < kFinBatch; ++k) {
+            const int b = b0 + threadIdx.x + 1024 * k;
+            vc[k] = b < g ? red[2 * b] : 0.0;
+            vs[k] = b < g ? red[2 * b + 1] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kFinBatch; ++k) {
+            c += vc[k];
+            s += vs[k];
+        }
     }
     c = block_sum(c, lds[0]);
     s = block_sum(s, lds[1]);
