@@ -96,14 +96,20 @@ __device__ __forceinline__ void pair_2d(T xi, T yi, T xj, T yj, T eps, A &ax, A 
 
 // Ring (eq. 9): the term sin(ti - tj) / (1 - cos(ti - tj) + eps)^{3/2} as the
 // factors p q, from the cosines and sines of both angles.  one_eps = 1 + eps.
-// p (the numerator) is exactly antisymmetric in i, j and q symmetric.
-template <typename T>
+// q is symmetric in i, j.  With EXACT the numerator p is two rounded products and
+// a difference, so exactly antisymmetric (and exactly 0 for i = j): needed where a
+// pair is evaluated once per ordered pair.  Without it p is one product and one
+// FMA (one rounding fewer, one instruction fewer), for a pair evaluated once for
+// both of its particles, never i with itself.
+template <typename T, bool EXACT = true>
 __device__ __forceinline__ void ring_factors_eq9(T ci, T si, T cj, T sj, T one_eps, T &p, T &q)
 {
     T num;
-    {
+    if constexpr (EXACT) {
 #pragma clang fp contract(off)
         num = si * cj - ci * sj;
+    } else {
+        num = fma_(si, cj, -(ci * sj));
     }
     const T u = fma_(-ci, cj, fma_(-si, sj, one_eps));
     const T r = rsq_(u);
@@ -119,14 +125,17 @@ __device__ __forceinline__ void ring_factors_eq9(T ci, T si, T cj, T sj, T one_e
 // the sqrt2 goes into the prefactor, and eps2 = 2 eps.  Unlike eq. 9's angle-sum
 // form, 1 - cos d is formed without cancelling against 1: its rounding error
 // scales with |d|, which matters in FP32 for close pairs.  Factors: p = a b
-// (antisymmetric), q = r'^3 (symmetric).
-template <typename T>
+// (antisymmetric), q = r'^3 (symmetric).  EXACT as for eq. 9: without it a is one
+// product and one FMA.
+template <typename T, bool EXACT = true>
 __device__ __forceinline__ void ring_factors_half(T ai, T bi, T aj, T bj, T eps2, T &p, T &q)
 {
     T a;
-    {
+    if constexpr (EXACT) {
 #pragma clang fp contract(off)
         a = ai * bj - bi * aj;
+    } else {
+        a = fma_(ai, bj, -(bi * aj));
     }
     const T b = fma_(bi, bj, ai * aj);
     const T r = rsq_(fma_(a, a, eps2));
@@ -137,11 +146,11 @@ __device__ __forceinline__ void ring_factors_half(T ai, T bi, T aj, T bj, T eps2
 // The Ring pair term's factors in the context's precision: eq. 9 on (cos t, sin t)
 // in FP64; the half-angle form on sqrt2 (cos(t/2), sin(t/2)) in FP32 (then e holds
 // 2 eps, else 1 + eps).
-template <typename T>
+template <typename T, bool EXACT = true>
 __device__ __forceinline__ void ring_factors(T c0, T s0, T c1, T s1, T e, T &p, T &q)
 {
-    if constexpr (sizeof(T) == 8) ring_factors_eq9(c0, s0, c1, s1, e, p, q);
-    else ring_factors_half(s0, c0, s1, c1, e, p, q);
+    if constexpr (sizeof(T) == 8) ring_factors_eq9<T, EXACT>(c0, s0, c1, s1, e, p, q);
+    else ring_factors_half<T, EXACT>(s0, c0, s1, c1, e, p, q);
 }
 
 // Adds the Ring pair term (i = 0, j = 1) to the accumulator a.
@@ -258,8 +267,8 @@ __device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[k
                         sj[1].add(dy, w);
                     }
                 } else {
-                    T p, q;
-                    ring_factors(u0[k], u1[k], v0, v1, e, p, q);
+                    T p, q;  // a tile pair meets each pair once, never i with itself
+                    ring_factors<T, !SYM>(u0[k], u1[k], v0, v1, e, p, q);
                     acc[0][k].add(p, q);
                     if (SYM) sj[0].add(-p, q);
                 }
