@@ -16,8 +16,9 @@ the relative energy error |E - E0| / |E0| (and the better conditioned
 |E - E0| / (K0 + |V0|)) is reported for both; the mixed figure counts only if
 its error is <= 1e-5.
 
-Also reported: the pair kernel's fraction of the FP32 vector peak (roofline), the
-SIMD cycles it spends per pair and wavefront, and
+Also reported: the pair kernel's fraction of the FP32 vector peak (roofline: its
+own launches timed by the library with HIP events on its stream, and the interactions
+one launch covers), the SIMD cycles it spends per pair and wavefront, and
 the FP64 CPU oracle's pair throughput on a bounded sample of force rows of the
 same configuration (cpu_baseline).
 
@@ -109,6 +110,8 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup, launch=None):
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    # the library brackets each launch of its pair kernel with HIP events on the same stream
+    md.md_timing_begin(ctx, 3 * steps + 4)
     t0 = time.perf_counter()
     ev0.record(stream)
     md.md_step(ctx, q, p, f, DT, steps)
@@ -116,6 +119,7 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup, launch=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
+    kernel_ms, kernel_launches, kernel_name = md.md_timing_end(ctx)
     e1 = md.md_energy(ctx, q, p).cpu().numpy()
     tiles = md.md_get_tiles(ctx)
     launch = LAUNCH_NAMES[md.md_get_launch(ctx)]
@@ -125,7 +129,9 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup, launch=None):
         "ms_total": ms, "wall_s": wall, "ms_per_step": ms / steps,
         "gpairs_per_s": pairs / (ms * 1e-3) / 1e9,
         "pair_launches": 3 * steps,
-        "pair_ms_avg": ms / (3 * steps),  # upper bound: includes the O(N) update kernels and gaps
+        "pair_ms_avg": ms / (3 * steps),  # one force evaluation: every kernel of it, and the gaps
+        "kernel_ms_avg": kernel_ms / max(kernel_launches, 1), "kernel_launches": kernel_launches,
+        "kernel_name": kernel_name,
         "E0": e0.tolist(), "E1": e1.tolist(),
         "dE_E": abs(e1[2] - e0[2]) / abs(e0[2]),
         "dE_KV": abs(e1[2] - e0[2]) / (abs(e0[0]) + abs(e0[1])),
@@ -266,15 +272,20 @@ def hmf_workload(md, torch, args):
         del qw, pw, fw
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        md.md_timing_begin(ctx, 3 * args.steps + 4)  # the stage passes, timed by the library
         ev0.record()
         md.md_step(ctx, q, p, f, HMF_DT, args.steps)
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
+        pass_ms, passes, pass_name = md.md_timing_end(ctx)
         e1 = md.md_energy(ctx, q, p).cpu().numpy()
         ps = HMF_N * args.steps / (ms * 1e-3)
+        pass_GBs = HMF_N * HMF_BYTES[name] / 3 / (pass_ms / passes * 1e-3) / 1e9
         res[name] = {"ms": ms, "ms_per_step": ms / args.steps, "particle_steps_per_s": ps,
                      "algorithmic_GBs": ps * HMF_BYTES[name] / 1e9,
+                     "pass_ms_avg": pass_ms / passes, "passes_timed": passes, "pass_timed_as": pass_name,
+                     "pass_algorithmic_GBs": pass_GBs,
                      "dE_E": float(abs(e1[2] - e0[2]) / abs(e0[2]))}
         ctx.close()
     cpu = None
@@ -295,8 +306,12 @@ def hmf_workload(md, torch, args):
         "unit": "particle-steps/s", "ms_per_step": round(fp["ms_per_step"], 5), "dtype": "f64",
         "config": {"workload": "hmf waterbag N=1e7 dt=0.1 seed=2", "model": "hmf", "n": HMF_N, "dt": HMF_DT,
                    "precision": "fp64"},
-        "roofline": {"bound": "hbm", "achieved": round(fp["algorithmic_GBs"], 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(fp["algorithmic_GBs"] / PEAK_HBM_GBS, 4), "traffic": None,
+        # the stage pass's own launches (timed by the library), 32 bytes per particle each
+        "roofline": {"bound": "hbm", "achieved": round(fp["pass_algorithmic_GBs"], 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(fp["pass_algorithmic_GBs"] / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "k_hmf_pass<double, 2>", "kernel_timed_as": fp["pass_timed_as"],
+                     "kernel_ms_avg": round(fp["pass_ms_avg"], 5), "bytes_per_launch": HMF_N * HMF_BYTES["fp64"] // 3,
+                     "step_GBs": round(fp["algorithmic_GBs"], 1),
                      "bytes_per_particle_step": HMF_BYTES["fp64"]},
         "cpu_baseline": cpu, "hmf": res,
     }
@@ -742,22 +757,27 @@ def grav2d_workload(md, torch, args):
         cpu = cpu_baseline(q0)
         log(f"bench: cpu {cpu['value']:.3f} Gpairs/s on {cpu['cores']} threads")
 
-    achieved = FLOPS_PER_PAIR * N * N / (mixed["pair_ms_avg"] * 1e-3) / 1e12
+    # The dominant kernel's own launches, timed live by the library (HIP events on its stream).
+    kernel_s = mixed["kernel_ms_avg"] * 1e-3
     if mixed["launch"] == "symmetric":
-        # each pair is evaluated once for both particles; diagonal tiles take every ordered pair
+        # the tile-pair kernel evaluates each pair of two different tiles once for both particles:
+        # it covers every interaction but those within a tile (the diagonal-tile kernel's)
         nt = -(-N // SYM_TILE)
-        off = nt * (nt - 1) // 2 * SYM_TILE ** 2
-        diag = nt * SYM_TILE ** 2
-        executed = SYM_FLOPS_PER_EVAL * off + FLOPS_PER_PAIR * diag
-        kernel = "k_sym<2, float, AccTile, true> (tile pairs) + k_sym<2, float, AccTile, false> (diagonal tiles)"
-        instr = {"valu_fp32": 8, "trans": 1, "per": "pair evaluated (tile pairs: both particles)"}
-        evals = off + diag
+        last = N - (nt - 1) * SYM_TILE
+        units = N * N - (nt - 1) * SYM_TILE ** 2 - last * last
+        evals = nt * (nt - 1) // 2 * SYM_TILE ** 2
+        executed = SYM_FLOPS_PER_EVAL * evals
+        kernel = "k_sym<2, float, AccTile, true> (tile pairs)"
+        instr = {"valu_fp32": 8, "trans": 1, "per": "pair evaluated (both particles)"}
     else:
+        units = N * N
+        evals = N * N
         executed = FLOPS_PER_PAIR * N * N
         kernel = "k_pair_2d<float, AccTile, ipl>"
         instr = {"valu_fp32": VALU_PER_PAIR, "trans": TRANS_PER_PAIR, "per": "pair"}
-        evals = N * N
-    executed_tf = executed / (mixed["pair_ms_avg"] * 1e-3) / 1e12
+    achieved = FLOPS_PER_PAIR * units / kernel_s / 1e12
+    executed_tf = executed / kernel_s / 1e12
+    evaluation_tf = FLOPS_PER_PAIR * N * N / (mixed["pair_ms_avg"] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": round(mixed["gpairs_per_s"], 3),
@@ -774,14 +794,18 @@ def grav2d_workload(md, torch, args):
             "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": traffic_from_profile(mixed["launch"], mixed["tiles"]),
-            "kernel": kernel,
-            "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": N * N,
-            # what the kernels execute: the symmetric form evaluates each pair once
+            "kernel": kernel, "kernel_timed_as": mixed["kernel_name"],
+            "kernel_ms_avg": round(mixed["kernel_ms_avg"], 4), "kernel_launches": mixed["kernel_launches"],
+            "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": units,
+            # what the kernel executes: the symmetric form evaluates each pair once for both particles
             "executed_flops_per_launch": executed, "pair_evaluations_per_launch": evals,
             "executed_tflops": round(executed_tf, 3), "frac_executed": round(executed_tf / PEAK_FP32_TFLOPS, 4),
             "instr_per_evaluation": instr,
             # SIMD cycles per interaction (pair of the N^2 count) and wavefront lane
-            "cycles_per_pair_wave": round(SIMD_CYCLES_PER_S * 64 / (N * N / (mixed["pair_ms_avg"] * 1e-3)), 2),
+            "cycles_per_pair_wave": round(SIMD_CYCLES_PER_S * 64 * kernel_s / units, 2),
+            # one whole force evaluation (this kernel, the diagonal tiles, the update) from the timed region
+            "evaluation_ms": round(mixed["pair_ms_avg"], 4), "evaluation_tflops": round(evaluation_tf, 3),
+            "evaluation_frac": round(evaluation_tf / PEAK_FP32_TFLOPS, 4),
         },
         "energy": {
             "mixed_dE_E": mixed["dE_E"], "mixed_dE_over_K0_plus_absV0": mixed["dE_KV"],
@@ -810,6 +834,7 @@ def grav2d_workload(md, torch, args):
             "pair_tflops": round(FLOPS_PER_PAIR * N * N / (fp64["pair_ms_avg"] * 1e-3) / 1e12, 3),
             "frac_fp64_peak": round(FLOPS_PER_PAIR * N * N / (fp64["pair_ms_avg"] * 1e-3) / 1e12
                                     / PEAK_FP64_TFLOPS, 4),
+            "kernel_timed_as": fp64["kernel_name"], "kernel_ms_avg": round(fp64["kernel_ms_avg"], 4),
         }
         out["mixed_vs_fp64"] = {
             "speedup": round(mixed["gpairs_per_s"] / fp64["gpairs_per_s"], 3),

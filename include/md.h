@@ -304,6 +304,26 @@ int md_step_record(md_ctx *c, double *q, double *p, double *f, double dt, int64_
 int md_step_vjp_recorded(md_ctx *c, const double *q0, double dt, int64_t nsteps, double *lam_q,
                          double *lam_p, const double *stage, size_t stage_bytes);
 
+/* Timing of the dominant kernel, for measurement (it is no part of the method).
+ * md_timing_begin: from now on the first max_launches launches of the context's
+ * dominant kernel (1 <= max_launches <= 65536) are each bracketed by two HIP
+ * events recorded on the context's stream; later launches run untimed.  The
+ * dominant kernel is the one that evaluates the pairs: the tile-pair kernel of the
+ * symmetric form (not its diagonal tiles), the pair kernel of the staged form, the
+ * fused kernel, the HMF stage pass (not its finalize); for ensembles the tile-pair
+ * or the pair kernel.  Launches enqueued while the stream is being captured into
+ * a graph are not timed.  It creates 2 max_launches HIP events (host-side
+ * objects: no workspace or device memory is taken); calling it again starts over.
+ * md_timing_end: waits for the last timed launch, writes the summed duration of
+ * the timed launches (ms) to *ms_total and their number to *launches, copies the
+ * timed kernel's name (NUL-terminated, at most name_bytes bytes) to name unless
+ * name is NULL, then destroys the events and turns timing off.
+ * Errors: MD_EINVAL for a null context or output or max_launches out of range;
+ * MD_ESTATE from md_timing_end when timing is not on; MD_EDEVICE when an event
+ * call fails (detail in md_last_error; timing is off afterwards). */
+int md_timing_begin(md_ctx *c, int max_launches);
+int md_timing_end(md_ctx *c, double *ms_total, int *launches, char *name, size_t name_bytes);
+
 /* Destroy a context (does not touch the workspace).  NULL is accepted. */
 int md_destroy(md_ctx *c);
 

@@ -600,6 +600,28 @@ Tiles default_tiles(int model, int prec, int64_t n)
     return t;
 }
 
+Timing::~Timing()
+{
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+int timed_begin(md_ctx *c, const char *kernel)
+{
+    Timing *t = c->timing;
+    if (!t || 2 * (size_t)(t->used + 1) > t->ev.size()) return -1;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c->stream, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return -1;
+    if (hipEventRecord(t->ev[2 * (size_t)t->used], c->stream) != hipSuccess) return -1;
+    t->kernel = kernel;
+    return t->used++;
+}
+
+void timed_end(md_ctx *c, int slot)
+{
+    if (slot >= 0 && c->timing) (void)hipEventRecord(c->timing->ev[2 * (size_t)slot + 1], c->stream);
+}
+
 }  // namespace md
 
 using namespace md;
@@ -972,6 +994,56 @@ int md_step_vjp_recorded(md_ctx *c, const double *q0, double dt, int64_t nsteps,
     const size_t slot = vjp_slot(c);
     return c->model == MD_HMF ? reverse_hmf(c, q0, stage, slot, dt, nsteps, lam_q, lam_p)
                               : reverse_pairs(c, q0, stage, slot, dt, nsteps, lam_q, lam_p);
+}
+
+int md_timing_begin(md_ctx *c, int max_launches)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (max_launches < 1 || max_launches > 65536)
+        return fail(c, MD_EINVAL, "md_timing_begin: max_launches = %d outside [1, 65536]", max_launches);
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_timing_begin: device");
+    delete c->timing;
+    c->timing = nullptr;
+    Timing *t = new (std::nothrow) Timing;
+    if (!t) return fail(c, MD_ENOMEM, "md_timing_begin: host allocation");
+    t->ev.assign(2 * (size_t)max_launches, nullptr);
+    for (hipEvent_t &e : t->ev) {
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            delete t;
+            return dev_fail(c, r, "md_timing_begin: hipEventCreate");
+        }
+    }
+    c->timing = t;
+    return MD_OK;
+}
+
+int md_timing_end(md_ctx *c, double *ms_total, int *launches, char *name, size_t name_bytes)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (!ms_total || !launches) return fail(c, MD_EINVAL, "md_timing_end: null output");
+    if (!c->timing) return fail(c, MD_ESTATE, "md_timing_end: timing is not on (md_timing_begin)");
+    DeviceGuard g(c->dev);
+    Timing *t = c->timing;
+    c->timing = nullptr;
+    double total = 0.0;
+    hipError_t e = g.err;
+    for (int i = 0; e == hipSuccess && i < t->used; ++i) {
+        float ms = 0.0f;
+        e = hipEventSynchronize(t->ev[2 * (size_t)i + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t->ev[2 * (size_t)i], t->ev[2 * (size_t)i + 1]);
+        total += ms;
+    }
+    const int used = t->used;
+    if (name && name_bytes) snprintf(name, name_bytes, "%s", t->kernel);
+    delete t;
+    if (e != hipSuccess) return dev_fail(c, e, "md_timing_end");
+    *ms_total = total;
+    *launches = used;
+    return MD_OK;
 }
 
 int md_destroy(md_ctx *c)

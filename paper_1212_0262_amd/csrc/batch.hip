@@ -390,9 +390,14 @@ hipError_t sym_launch(md_ctx *c)
     const int npad = (int)c->npad;
     const PairItem *items = reinterpret_cast<const PairItem *>(B.d_sitems);
     const dim3 block(kSymWaves * kWave);
-    if (B.n_soff > 0)
+    if (B.n_soff > 0) {
+        const int ts = timed_begin(c, "k_batch_sym (tile pairs)");
         hipLaunchKernelGGL((k_batch_sym<MODEL, T, A, true>), dim3((unsigned)B.n_soff), block, 0, c->stream, items, r0,
                            r0 + npad, B.d_eps, npad, c->part);
+        const hipError_t err = hipGetLastError();
+        timed_end(c, ts);
+        if (err != hipSuccess) return err;
+    }
     hipLaunchKernelGGL((k_batch_sym<MODEL, T, A, false>), dim3((unsigned)B.n_sdiag), block, 0, c->stream,
                        items + B.n_soff, r0, r0 + npad, B.d_eps, npad, c->part);
     return hipGetLastError();
@@ -411,6 +416,9 @@ hipError_t pair_launch(md_ctx *c, const void *src)
     const int npad = (int)c->npad, jt = c->tiles.jtile;
     const dim3 grid((unsigned)B.n_items), block((unsigned)(kWave * c->tiles.waves));
     const PairItem *items = reinterpret_cast<const PairItem *>(B.d_items);
+    const int ts = timed_begin(c, c->model == MD_GRAV2D ? "k_batch_pair_2d"
+                                  : sizeof(T) == 4     ? "k_batch_pair_ring_win"
+                                                       : "k_batch_pair_ring");
     if (c->model == MD_GRAV2D) {
         const T *x = static_cast<const T *>(src);
         const T *y = x + (src == c->ops ? npad : c->n);
@@ -434,7 +442,9 @@ hipError_t pair_launch(md_ctx *c, const void *src)
         default: hipLaunchKernelGGL((k_batch_pair_ring<T, A, 4>), grid, block, 0, c->stream, items, cs, B.d_eps, npad, jt, c->part); break;
         }
     }
-    return hipGetLastError();
+    const hipError_t err = hipGetLastError();
+    timed_end(c, ts);
+    return err;
 }
 
 }  // namespace

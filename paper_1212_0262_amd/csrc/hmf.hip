@@ -314,6 +314,7 @@ hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, dou
     const int n = (int)c->n;
     const int g = hmf_grid(c->n);
     const PassArgs a{kick1, kick2, drift, flags};
+    const int ts = timed_begin(c, "k_hmf_pass");
     if (f32state) {
         const int w = vec_width(true, c->th32, c->p32, f_in, f_out);
         if (w == 4)
@@ -332,6 +333,7 @@ hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, dou
                                c->scal, a, n, c->red, snap);
     }
     hipError_t e = hipGetLastError();
+    timed_end(c, ts);
     if (e == hipSuccess && (flags & HMF_REDUCE)) {
         hipLaunchKernelGGL(k_hmf_finalize, dim3(1), dim3(1024), 0, c->stream, c->red, g, n, c->scal);
         e = hipGetLastError();

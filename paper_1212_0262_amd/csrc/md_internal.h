@@ -95,6 +95,16 @@ struct Batch {
 
 }  // namespace md
 
+namespace md {
+// Events of md_timing_begin: a start and an end event per timed launch.
+struct Timing {
+    std::vector<hipEvent_t> ev;
+    int used = 0;
+    const char *kernel = "";
+    ~Timing();
+};
+}  // namespace md
+
 struct md_ctx {
     int model = 0, prec = 0, dev = 0;
     int64_t n = 0, npad = 0;
@@ -115,8 +125,13 @@ struct md_ctx {
     bool sym_pad = false;                // the symmetric form's pad operands are written
     md::Tiles tiles;
     md::Batch *batch = nullptr;  // non-null for a batched ensemble (owned)
+    md::Timing *timing = nullptr;  // non-null while md_timing_begin is on (owned)
     std::string err;
-    ~md_ctx() { delete batch; }
+    ~md_ctx()
+    {
+        delete batch;
+        delete timing;
+    }
 };
 
 namespace md {
@@ -136,6 +151,12 @@ inline double force_prefactor(int model, int prec, int64_t n)
     if (model == MD_GRAV2D) return -2.0 / (double)n;
     return prec == MD_FP64 ? -1.0 / (2.0 * 1.4142135623730951 * (double)n) : -1.0 / (2.0 * (double)n);
 }
+
+// Timing of the dominant kernel: timed_begin records the start event of one launch
+// and returns its slot (-1 when timing is off, its events are used up, or the
+// stream is being captured); timed_end(c, slot) records the end event.
+int timed_begin(md_ctx *c, const char *kernel);
+void timed_end(md_ctx *c, int slot);
 
 // Launchers return hipSuccess or the launch error.  All enqueue on c->stream.
 // pair.hip

@@ -338,18 +338,26 @@ hipError_t sym_launch(md_ctx *c)
     const int n = (int)c->n, npad = (int)c->npad, ntile = npad / kSymTile;
     T *ops = static_cast<T *>(c->ops);
     if (!c->sym_pad) {  // once per context: the update kernels never write past n
-        if (npad > n)
+        if (npad > n) {
             hipLaunchKernelGGL((k_fill_pad<MODEL, T>), dim3((unsigned)((npad - n + 255) / 256)), dim3(256), 0,
                                c->stream, ops, n, npad);
+            const hipError_t err = hipGetLastError();
+            if (err != hipSuccess) return err;
+        }
         c->sym_pad = true;
     }
     const T e = MODEL == MD_GRAV2D ? (T)c->eps : sizeof(T) == 4 ? (T)(2.0 * c->eps) : (T)(1.0 + c->eps);
     const dim3 block(kSymWaves * kWave);
     const int noff = ntile * (ntile - 1) / 2;
     using A = std::conditional_t<sizeof(T) == 4, AccTile, AccF64>;
-    if (noff > 0)
+    if (noff > 0) {
+        const int ts = timed_begin(c, MODEL == MD_GRAV2D ? "k_sym (2D, tile pairs)" : "k_sym (Ring, tile pairs)");
         hipLaunchKernelGGL((k_sym<MODEL, T, A, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad,
                            npad, ntile, e, c->part);
+        const hipError_t err = hipGetLastError();
+        timed_end(c, ts);
+        if (err != hipSuccess) return err;
+    }
     hipLaunchKernelGGL((k_sym<MODEL, T, A, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad, npad,
                        ntile, e, c->part);
     return hipGetLastError();
@@ -647,6 +655,7 @@ hipError_t fused_ipl(md_ctx *c, int flags, double kick1, double kick2, double dr
     case 4: MD_FUSED(I_, 4); break;             \
     default: MD_FUSED(I_, 8); break;            \
     }
+    const int ts = timed_begin(c, "k_fused");
     switch (t.ipl) {
     case 1: MD_FUSED_L(1); break;
     case 2: MD_FUSED_L(2); break;
@@ -654,13 +663,16 @@ hipError_t fused_ipl(md_ctx *c, int flags, double kick1, double kick2, double dr
     }
 #undef MD_FUSED_L
 #undef MD_FUSED
-    return hipGetLastError();
+    const hipError_t err = hipGetLastError();
+    timed_end(c, ts);
+    return err;
 }
 
 template <typename T, typename A>
 hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
 {
     const int n = (int)c->n, npad = (int)c->npad, jt = c->tiles.jtile;
+    const int ts = timed_begin(c, c->model == MD_GRAV2D ? "k_pair_2d" : sizeof(T) == 4 ? "k_pair_win" : "k_pair_ring");
     if (c->model == MD_GRAV2D) {
         const T *x = static_cast<const T *>(src);
         const T *y = x + (src == c->ops ? npad : n);
@@ -692,7 +704,9 @@ hipError_t pair_ipl(md_ctx *c, const void *src, dim3 grid, dim3 block, int jlen)
         default: hipLaunchKernelGGL((k_pair_ring<T, A, 4>), grid, block, 0, c->stream, cs, n, npad, jlen, jt, one_eps, c->part); break;
         }
     }
-    return hipGetLastError();
+    const hipError_t err = hipGetLastError();
+    timed_end(c, ts);
+    return err;
 }
 
 }  // namespace

@@ -57,6 +57,8 @@ SIGNATURES = {
     "md_record_stage_bytes": (_SZ, [_V, _I64]),
     "md_step_record": (_I, [_V, _V, _V, _V, _D, _I64, _V, _SZ]),
     "md_step_vjp_recorded": (_I, [_V, _V, _D, _I64, _V, _V, _V, _SZ]),
+    "md_timing_begin": (_I, [_V, _I]),
+    "md_timing_end": (_I, [_V, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.c_char_p, _SZ]),
     "md_destroy": (_I, [_V]),
     "md_strerror": (ctypes.c_char_p, [_I]),
     "md_last_error": (ctypes.c_char_p, [_V]),
@@ -311,6 +313,21 @@ def md_step_vjp_recorded(ctx: Context, q0: torch.Tensor, dt: float, nsteps: int,
     ctx._check(load().md_step_vjp_recorded(ctx.handle, ctx._arr(q0, "q0"), float(dt), int(nsteps),
                                            ctx._arr(lam_q, "lam_q"), ctx._arr(lam_p, "lam_p"), stage.data_ptr(),
                                            stage.numel() * stage.element_size()), "md_step_vjp_recorded")
+
+
+def md_timing_begin(ctx: Context, max_launches: int) -> None:
+    """Time the first max_launches launches of the context's dominant kernel (HIP
+    events on its stream); read the result with md_timing_end."""
+    ctx._check(load().md_timing_begin(ctx.handle, int(max_launches)), "md_timing_begin")
+
+
+def md_timing_end(ctx: Context) -> tuple:
+    """(summed ms, launches timed, kernel name) since md_timing_begin; waits for the
+    last timed launch and turns timing off."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
+    name = ctypes.create_string_buffer(64)
+    ctx._check(load().md_timing_end(ctx.handle, ctypes.byref(ms), ctypes.byref(n), name, 64), "md_timing_end")
+    return ms.value, n.value, name.value.decode()
 
 
 def md_destroy(ctx: Context) -> None:

@@ -179,3 +179,10 @@ def test_no_kernel_has_a_private_segment():
     names = " ".join(k["kernel"] for k in kernels)
     for kern in ("k_hmf_pass", "k_hmf_finalize", "k_update", "k_sym", "k_fused", "k_batch_sym"):
         assert kern in names, kern
+
+
+def test_timing_entry_points_reject_null_context():
+    lib = _lib()
+    ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
+    assert lib.md_timing_begin(None, 4) == md.EINVAL
+    assert lib.md_timing_end(None, ctypes.byref(ms), ctypes.byref(n), None, 0) == md.EINVAL
