@@ -338,6 +338,12 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_batch_sym(const PairItem 
     const T pad = sym_pad<MODEL, T>();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int ib = it.i0 + wave * kWave * kSymIpl + lane;
+    // A diagonal tile's wavefront whose i are all past the realization's end has no
+    // work (no barriers without SYM).  The j tile stops after its last 64-j block
+    // that holds a particle: the pads' terms are zero.
+    if (!SYM && it.i0 + wave * kWave * kSymIpl >= it.i1) return;
+    // (j1 is the realization's end: only its last tile is shorter than kSymTile)
+    const int nblk = min(kSymTile / kWave, (it.j1 - it.j0 + kWave - 1) / kWave);
     T u0[kSymIpl], u1[kSymIpl];
     A acc[D][kSymIpl];
 #pragma unroll
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_batch_sym(const PairItem 
         u1[k] = i < it.i1 ? r1[ic] : pad;
     }
     sym_tile<MODEL, T, A, SYM>(
-        u0, u1, e, lane,
+        u0, u1, e, lane, nblk,
         [&](int blk, T &v0, T &v1) {
             const int j = it.j0 + blk * kWave + lane;
             const int jc = min(j, it.j1 - 1);

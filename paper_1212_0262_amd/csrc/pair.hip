@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
     }
     const int jl = b * kSymTile + lane;
     sym_tile<MODEL, T, A, SYM>(
-        u0, u1, e, lane,
+        u0, u1, e, lane, kSymTile / kWave,
         [&](int blk, T &v0, T &v1) {
             v0 = r0[jl + blk * kWave];
             v1 = r1[jl + blk * kWave];

@@ -233,17 +233,19 @@ __host__ __device__ constexpr T sym_pad()
     return sizeof(T) == 4 ? T(1e30f) : T(1e150);
 }
 
+// nblk (1 .. kSymTile / kWave, uniform across the block): the 64-j blocks of the j
+// tile to stream; a ragged tile stops after its last block that holds a particle.
 template <int MODEL, typename T, typename A, bool SYM, typename Load, typename JSum>
-__device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[kSymIpl], T e, int lane, Load &&load,
-                                         JSum &&jsum, A (&acc)[MODEL == MD_GRAV2D ? 2 : 1][kSymIpl])
+__device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[kSymIpl], T e, int lane, int nblk,
+                                         Load &&load, JSum &&jsum, A (&acc)[MODEL == MD_GRAV2D ? 2 : 1][kSymIpl])
 {
-    constexpr int D = MODEL == MD_GRAV2D ? 2 : 1, NBLK = kSymTile / kWave;
+    constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
     const int next = ((lane + 1) & (kWave - 1)) * 4;  // ds_bpermute byte address of lane l + 1
     T v0n, v1n;
     load(0, v0n, v1n);
-    for (int blk = 0; blk < NBLK; ++blk) {
+    for (int blk = 0; blk < nblk; ++blk) {
         T v0 = v0n, v1 = v1n;
-        if (blk + 1 < NBLK) load(blk + 1, v0n, v1n);
+        if (blk + 1 < nblk) load(blk + 1, v0n, v1n);
         A sj[D];  // j-side sums of the j this lane holds
 #pragma unroll 16
         for (int s = 0; s < kWave; ++s) {
@@ -279,7 +281,7 @@ __device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[k
             for (int d = 0; d < D; ++d) sj[d].fold();
             jsum(blk, (lane + kWave - 1) & (kWave - 1), sj);
         }
-        if (blk & 1) {  // every 128 j
+        if ((blk & 1) || blk + 1 == nblk) {  // every 128 j, and at the end
 #pragma unroll
             for (int k = 0; k < kSymIpl; ++k)
 #pragma unroll
