@@ -192,9 +192,7 @@ __global__ __launch_bounds__(256) void k_adj_update(const double *__restrict__ p
     for (int d = 0; d < D; ++d) {
         const size_t k = (size_t)d * n + i;
         if (flags & (ADJ_OUT | ADJ_KICK)) {
-            double s = 0.0;
-            for (int b = 0; b < S; ++b) s += part[(size_t)(b * D + d) * npad + i];
-            const double hw = pref * s;
+            const double hw = pref * slot_sum<D>(part, S, d, npad, i);
             if (flags & ADJ_OUT) out[k] = hw;
             if (flags & ADJ_KICK) {
                 double l = lq[k] - h * hw;

@@ -158,9 +158,7 @@ __global__ __launch_bounds__(256) void k_batch_update(const int4 *__restrict__ r
         const size_t k = (size_t)d * ntot + i;
         double fd = 0.0;
         if (flags & UPD_F_FROM_PART) {
-            double s = 0.0;
-            for (int c = 0; c < S; ++c) s += part[(size_t)(c * D + d) * npad + i];
-            fd = pref * s;
+            fd = pref * slot_sum<D>(part, S, d, npad, i);
         } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
             fd = f[k];
         }

@@ -135,4 +135,25 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return t;
 }
 
+// The sum over b = 0 .. S-1 of part[(b D + d) npad + i], added in order of b.  The
+// loads go out 16 at a time: one load, wait and add per slot leaves the update
+// kernels bound by the memory latency (the symmetric 2D form at N = 262,144 adds
+// 256 slots per coordinate).
+template <int D>
+__device__ __forceinline__ double slot_sum(const double *__restrict__ part, int S, int d, int npad, int i)
+{
+    constexpr int U = 16;
+    double s = 0.0;
+    int b = 0;
+    for (; b + U <= S; b += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = part[(size_t)((b + u) * D + d) * npad + i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; b < S; ++b) s += part[(size_t)(b * D + d) * npad + i];
+    return s;
+}
+
 }  // namespace md

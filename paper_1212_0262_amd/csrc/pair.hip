@@ -441,9 +441,7 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ part,
     for (int d = 0; d < D; ++d) {
         double fd = 0.0;
         if (flags & UPD_F_FROM_PART) {
-            double s = 0.0;
-            for (int b = 0; b < S; ++b) s += part[(size_t)(b * D + d) * npad + i];
-            fd = pref * s;
+            fd = pref * slot_sum<D>(part, S, d, npad, i);
         } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
             fd = f[(size_t)d * n + i];
         }
