@@ -5,8 +5,8 @@ to ``paper_1212_0262_amd/_build/``; the library lands next to this file, in-tree
 so that it travels with the source tree.  The compiler's resource-usage remarks
 (registers, LDS, scratch, occupancy of every kernel) go to
 ``_build/kernel_resources.json``; a kernel with a private segment (scratch) fails
-the build.  Measured on the HMF step, whose one-block finalize once spilled 28
-bytes per lane: 34.1 -> 30.7 us per step at N = 1e5 (FP64) and 104 -> 99 us at
+the build.  Measured on the HMF step, whose one-block reduction kernel once
+spilled 28 bytes per lane: 34.1 -> 30.7 us per step at N = 1e5 (FP64) and 104 -> 99 us at
 N = 1e7 (FP32 state) without the spill, about 1.2 us per dispatch.
 """
 from __future__ import annotations

@@ -53,7 +53,7 @@ bool sym_capable(int model, int prec, int64_t n)
 }
 
 struct Layout {
-    size_t red, scal, ops, wops, part, th32, p32, fops0, fops1, total;
+    size_t red, scal, macc, ops, wops, part, th32, p32, fops0, fops1, total;
 };
 
 Layout layout(int model, int prec, int64_t n)
@@ -65,6 +65,8 @@ Layout layout(int model, int prec, int64_t n)
     off = align_up(off + sizeof(double) * kRedSlots);
     L.scal = off;
     off = align_up(off + sizeof(double) * 32);
+    L.macc = off;
+    if (model == MD_HMF) off = align_up(off + sizeof(long long) * kMWords);
     L.ops = off;
     if (model == MD_RING) off = align_up(off + 2 * npad * (prec == MD_FP64 ? sizeof(double) : sizeof(float)));
     else if (model == MD_GRAV2D && prec != MD_FP64) off = align_up(off + 2 * npad * sizeof(float));
@@ -313,19 +315,23 @@ int step_hmf(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nste
     int64_t slot = 0;
     auto next = [&]() { return snap ? snap + (size_t)(slot++) * snap_stride : nullptr; };
     if (f32) MD_TRY(launch_hmf_convert(c, q, p, true), "step: convert in");
-    MD_TRY(launch_hmf_pass(c, HMF_KICK_F | HMF_DRIFT | HMF_WRITE | HMF_REDUCE, B0 * dt, 0.0, D0 * dt, q, p, f,
+    int k = 0;  // pass index: pass k reads the magnetization sums of pass k - 1
+    MD_TRY(launch_hmf_begin(c), "step: magnetization sums");
+    MD_TRY(launch_hmf_pass(c, k++, HMF_KICK_F | HMF_DRIFT | HMF_WRITE | HMF_REDUCE, B0 * dt, 0.0, D0 * dt, q, p, f,
                            nullptr, f32, next()),
            "step: first pass");
     for (int64_t s = 0; s < nsteps; ++s) {
-        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D1 * dt, q, p, nullptr, nullptr, f32, next()), "step: pass");
-        MD_TRY(launch_hmf_pass(c, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32, next()), "step: pass");
+        MD_TRY(launch_hmf_pass(c, k++, stage, B1 * dt, 0.0, D1 * dt, q, p, nullptr, nullptr, f32, next()),
+               "step: pass");
+        MD_TRY(launch_hmf_pass(c, k++, stage, B1 * dt, 0.0, D0 * dt, q, p, nullptr, nullptr, f32, next()),
+               "step: pass");
         if (s + 1 < nsteps)
-            MD_TRY(launch_hmf_pass(c, stage | HMF_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, nullptr, nullptr, f32,
-                                   next()),
+            MD_TRY(launch_hmf_pass(c, k++, stage | HMF_KICK2, B0 * dt, B0 * dt, D0 * dt, q, p, nullptr, nullptr,
+                                   f32, next()),
                    "step: pass");
         else
-            MD_TRY(launch_hmf_pass(c, HMF_KICK_M | HMF_STORE_F | HMF_WRITE, B0 * dt, 0.0, 0.0, q, p, nullptr, f,
-                                   f32),
+            MD_TRY(launch_hmf_pass(c, k++, HMF_KICK_M | HMF_STORE_F | HMF_WRITE, B0 * dt, 0.0, 0.0, q, p, nullptr,
+                                   f, f32),
                    "step: last pass");
     }
     if (f32) MD_TRY(launch_hmf_convert(c, q, p, false), "step: convert out");
@@ -343,8 +349,10 @@ int step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_t n
     MD_TRY(hipMemcpyAsync(pw, p0, len * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "vjp: copy p");
     int st;
     if (c->model == MD_HMF) {
-        MD_TRY(launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, qw, nullptr, nullptr, nullptr, false), "vjp: reduce");
-        MD_TRY(launch_hmf_pass(c, HMF_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, nullptr, fw, false), "vjp: force");
+        MD_TRY(launch_hmf_begin(c), "vjp: magnetization sums");
+        MD_TRY(launch_hmf_pass(c, 0, HMF_REDUCE, 0.0, 0.0, 0.0, qw, nullptr, nullptr, nullptr, false),
+               "vjp: reduce");
+        MD_TRY(launch_hmf_pass(c, 1, HMF_STORE_F, 0.0, 0.0, 0.0, qw, nullptr, nullptr, fw, false), "vjp: force");
         st = step_hmf(c, qw, pw, fw, dt, nsteps, P, slot);
         if (st != MD_OK) return st;
         return reverse_hmf(c, q0, P, slot, dt, nsteps, lq, lp);
@@ -661,6 +669,7 @@ int md_init(md_ctx **out, int model, int prec, int64_t n, double eps, void *hip_
     c->ws_bytes = workspace_bytes;
     c->red = reinterpret_cast<double *>(c->ws + L.red);
     c->scal = reinterpret_cast<double *>(c->ws + L.scal);
+    c->macc = (L.ops > L.macc) ? reinterpret_cast<long long *>(c->ws + L.macc) : nullptr;
     c->ops = (L.wops > L.ops) ? static_cast<void *>(c->ws + L.ops) : nullptr;
     c->wops = (L.part > L.wops) ? reinterpret_cast<float *>(c->ws + L.wops) : nullptr;
     c->part = (L.th32 > L.part) ? reinterpret_cast<double *>(c->ws + L.part) : nullptr;
@@ -849,8 +858,10 @@ int md_force(md_ctx *c, const double *q, double *f)
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_force: set device");
     double *qm = const_cast<double *>(q);
     if (c->model == MD_HMF) {
-        MD_TRY(launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, qm, nullptr, nullptr, nullptr, false), "force: reduce");
-        MD_TRY(launch_hmf_pass(c, HMF_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, nullptr, f, false), "force: store");
+        MD_TRY(launch_hmf_begin(c), "force: magnetization sums");
+        MD_TRY(launch_hmf_pass(c, 0, HMF_REDUCE, 0.0, 0.0, 0.0, qm, nullptr, nullptr, nullptr, false),
+               "force: reduce");
+        MD_TRY(launch_hmf_pass(c, 1, HMF_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, nullptr, f, false), "force: store");
         return MD_OK;
     }
     MD_TRY(update_(c, UPD_PREP, 0.0, 0.0, 0.0, qm, nullptr, nullptr), "force: operands");

@@ -113,8 +113,9 @@ hipError_t launch_energy(md_ctx *c, const double *q, const double *p, double *ou
     double *redK = c->red + kRedSlots / 2;
     int nv;
     if (c->model == MD_HMF) {
-        // block partials of sum cos, sum sin of q (double-buffered halves of red)
-        hipError_t e = launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr,
+        // block partials of sum cos, sum sin of q (added here in FP64, in a fixed order; the pass's
+        // fixed-point sums are not read)
+        hipError_t e = launch_hmf_pass(c, 0, HMF_REDUCE, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr,
                                        nullptr, false);
         if (e != hipSuccess) return e;
         nv = hmf_grid(c->n);
@@ -140,8 +141,10 @@ hipError_t launch_energy(md_ctx *c, const double *q, const double *p, double *ou
 
 hipError_t launch_magnetization(md_ctx *c, const double *q, double *out2)
 {
-    hipError_t e = launch_hmf_pass(c, HMF_REDUCE, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr,
-                                   nullptr, false);
+    hipError_t e = launch_hmf_begin(c);
+    if (e == hipSuccess)
+        e = launch_hmf_pass(c, 0, HMF_REDUCE, 0.0, 0.0, 0.0, const_cast<double *>(q), nullptr, nullptr, nullptr,
+                            false);
     if (e != hipSuccess) return e;
     return launch_hmf_magnetization(c, out2);
 }

@@ -9,10 +9,20 @@
 // would add 32 B of HBM traffic per particle per stage to a bandwidth-bound
 // pass; two sincos evaluations cost less.  The magnetization is a grid-wide
 // dependency: each pass ends with FP64 block partials (wavefront butterfly, then
-// a fixed serial order over wavefronts) and a one-block kernel sums them in a
-// fixed order into M.  The kernel boundary is the only synchronisation: no
-// atomics, and no device-wide fences (on this GPU a device-scope release writes
-// back the L2 of the issuing XCD, which costs more than a launch).
+// a fixed serial order over wavefronts), which every block adds in fixed point
+// (limbs of 2^-32 and 2^-64, 64-bit integer atomics into kMSlots slots) to one of
+// three buffers, and every block of the next pass sums the slots exactly, in
+// integers, and converts the total once to FP64 (no launch between passes).
+// Integer sums do not depend on the order of the atomics, so M is reproducible,
+// and it is the exact sum of the FP64 block partials rounded once.  That is for
+// grids of at most kHmfInPassM blocks (N <= 2.1e6); on larger ones every block
+// re-deriving M costs more than a launch, so a one-block kernel sums the FP64
+// block partials in a fixed order instead (M then differs in its last bits from
+// the fixed-point total; either way it is fixed per N, so runs are
+// reproducible).  The kernel boundary is the only synchronisation: no
+// device-wide fences (on this GPU a device-scope release writes back the L2 of
+// the issuing XCD).  The FP64 block partials are always stored (the energy sums
+// them in its own fixed order).
 //
 // Memory access: each lane moves W consecutive elements (16-byte vector loads and
 // stores: W = 2 in FP64, 4 in FP32), U vectors per grid-stride iteration, over a
@@ -84,24 +94,87 @@ __device__ __forceinline__ void particle(T &t, T &p, double fin, double *fout, T
     }
 }
 
+static_assert(kMSlots * kMLimbs == 256, "the 256 limb words: one per thread of a pass block");
+static_assert(kMSlots == kWave, "one slot per lane of the wavefront that converts the sums");
+
+// x = (hi + lo 2^-32) 2^-32, hi = floor(x 2^32), 0 <= lo <= 2^32: exact for |x| < 2^20
+// down to 2^-64 (the bits below are rounded).
+__device__ __forceinline__ void to_limbs(double x, long long &hi, long long &lo)
+{
+    const double y = x * 0x1p32;
+    const double h = floor(y);
+    hi = (long long)h;
+    lo = (long long)rint((y - h) * 0x1p32);
+}
+
+// M = (the total of the limb sums in acc) / n, by each wavefront on its own (no
+// barrier): lane l loads slot l, a butterfly adds the slots in 64-bit integers
+// (exact, so every lane holds the same total in any order).
+__device__ __forceinline__ void limbs_sum(long long (&v)[kMLimbs], int n, double &mx, double &my)
+{
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1)
+#pragma unroll
+        for (int l = 0; l < kMLimbs; ++l) v[l] += __shfl_xor(v[l], m);
+    mx = ((double)v[0] * 0x1p-32 + (double)v[1] * 0x1p-64) / (double)n;
+    my = ((double)v[2] * 0x1p-32 + (double)v[3] * 0x1p-64) / (double)n;
+}
+
+// The same total by the 256 threads of a block: one word each, then four threads
+// add the 64 slots of one limb (a barrier before and after).
+__device__ __forceinline__ void limbs_sum_block(const long long *__restrict__ acc, int n, long long *lds, double &mx,
+                                                double &my)
+{
+    const int t = threadIdx.x;
+    lds[t] = acc[t];
+    __syncthreads();
+    if (t < kMLimbs) {
+        long long v = 0;
+        for (int k = 0; k < kMSlots; ++k) v += lds[k * kMLimbs + t];
+        lds[kMSlots * kMLimbs + t] = v;
+    }
+    __syncthreads();
+    const long long *L = lds + kMSlots * kMLimbs;
+    mx = ((double)L[0] * 0x1p-32 + (double)L[1] * 0x1p-64) / (double)n;
+    my = ((double)L[2] * 0x1p-32 + (double)L[3] * 0x1p-64) / (double)n;
+}
+
 // One kick/drift/reduce pass over all particles (grid-stride over a grid fixed
 // per n, so every partial sum is reproducible).  T: state type; W: elements per
-// vector access.  M[0..1] holds the magnetization for HMF_KICK_M / HMF_STORE_F;
-// HMF_REDUCE writes the block partials (sum cos, sum sin) to red[2b], red[2b+1].
-template <typename T, int W>
+// vector access.  HMF_KICK_M / HMF_STORE_F take the magnetization from the limb
+// sums mrd if given (block 0 also stores it to M), else from M[0..1]; HMF_REDUCE writes the block
+// partials (sum cos, sum sin) to red[2b], red[2b+1] and adds their limbs to mwr;
+// block 0 zeroes mzero (if given) for a later pass.  Launched with 256 threads.
+// LIMBS: the fixed-point sums (small grids); without it the kernel reads M[0..1]
+// and leaves the partials to the one-block kernel, with no code of the limbs.
+template <typename T, int W, bool LIMBS>
 __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restrict__ p,
                                                   const double *__restrict__ f_in, double *__restrict__ f_out,
-                                                  const double *__restrict__ M, PassArgs a, int n,
-                                                  double *__restrict__ red, T *__restrict__ snap)
+                                                  const long long *__restrict__ mrd, long long *__restrict__ mwr,
+                                                  long long *__restrict__ mzero, double *__restrict__ M,
+                                                  PassArgs a, int n, double *__restrict__ red, T *__restrict__ snap)
 {
     __shared__ double lds[2][4];
+    __shared__ long long mlds[LIMBS ? kMSlots * kMLimbs + kMLimbs : 1];
     const int flags = a.flags;
     const T k1 = (T)a.kick1, k2 = (T)a.kick2, dr = (T)a.drift;
     T mx = 0, my = 0;
     if (flags & (HMF_KICK_M | HMF_STORE_F)) {
-        mx = (T)M[0];
-        my = (T)M[1];
+        if constexpr (LIMBS) {
+            double dmx, dmy;
+            limbs_sum_block(mrd, n, mlds, dmx, dmy);
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                M[0] = dmx;
+                M[1] = dmy;
+            }
+            mx = (T)dmx;
+            my = (T)dmy;
+        } else {
+            mx = (T)M[0];
+            my = (T)M[1];
+        }
     }
+    if (LIMBS && blockIdx.x == 0) mzero[threadIdx.x] = 0;
     const bool need_p = flags & (HMF_KICK_F | HMF_KICK_M | HMF_DRIFT);
     const bool write = flags & HMF_WRITE;
     double sc = 0.0, ss = 0.0;
@@ -165,6 +238,39 @@ __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restr
             red[2 * blockIdx.x] = bc;
             red[2 * blockIdx.x + 1] = bs;
         }
+        if (LIMBS && threadIdx.x == 0) {
+            unsigned long long *w = reinterpret_cast<unsigned long long *>(mwr + (blockIdx.x % kMSlots) * kMLimbs);
+            long long hi, lo;
+            to_limbs(bc, hi, lo);
+            atomicAdd(w, (unsigned long long)hi);  // two's complement: the signed sum, exactly
+            atomicAdd(w + 1, (unsigned long long)lo);
+            to_limbs(bs, hi, lo);
+            atomicAdd(w + 2, (unsigned long long)hi);
+            atomicAdd(w + 3, (unsigned long long)lo);
+        }
+    }
+}
+
+// Zeroes one limb buffer (the first of a call's passes adds into it).
+__global__ __launch_bounds__(256) void k_hmf_zero_limbs(long long *__restrict__ acc) { acc[threadIdx.x] = 0; }
+
+// M from the limb sums of one buffer (one wavefront, lane l loads slot l), to
+// M[0..1] and (if given) out[0..1].
+__global__ __launch_bounds__(64) void k_hmf_limbs_to_m(const long long *__restrict__ acc, int n,
+                                                       double *__restrict__ out, double *__restrict__ M)
+{
+    double mx, my;
+    long long v[kMLimbs];
+#pragma unroll
+    for (int l = 0; l < kMLimbs; ++l) v[l] = acc[threadIdx.x * kMLimbs + l];
+    limbs_sum(v, n, mx, my);
+    if (threadIdx.x == 0) {
+        if (out) {
+            out[0] = mx;
+            out[1] = my;
+        }
+        M[0] = mx;
+        M[1] = my;
     }
 }
 
@@ -308,33 +414,53 @@ int hmf_grid(int64_t n)
 
 const double *hmf_partials(const md_ctx *c) { return c->red; }
 
-hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, double drift, double *th,
+// The passes of this context sum M in fixed point (small grids) rather than
+// through the one-block kernel over the FP64 partials.
+static bool hmf_in_pass(const md_ctx *c) { return hmf_grid(c->n) <= kHmfInPassM; }
+
+hipError_t launch_hmf_begin(md_ctx *c)
+{
+    if (!hmf_in_pass(c)) return hipSuccess;
+    hipLaunchKernelGGL(k_hmf_zero_limbs, dim3(1), dim3(kMSlots * kMLimbs), 0, c->stream, c->macc);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmf_pass(md_ctx *c, int k, int flags, double kick1, double kick2, double drift, double *th,
                            double *p, const double *f_in, double *f_out, bool f32state, double *snap)
 {
     const int n = (int)c->n;
     const int g = hmf_grid(c->n);
     const PassArgs a{kick1, kick2, drift, flags};
+    constexpr int B = kMSlots * kMLimbs;  // words per limb buffer
+    // Small grids: M from the limb sums inside the pass, no other launch.  Large
+    // ones: the one-block kernel over the FP64 partials after a reducing pass, and
+    // M read from c->scal.
+    const bool in_pass = hmf_in_pass(c);
+    const long long *mrd = in_pass ? c->macc + (size_t)((k + 2) % 3) * B : nullptr;
+    long long *mwr = in_pass ? c->macc + (size_t)(k % 3) * B : nullptr;
+    long long *mzero = in_pass ? c->macc + (size_t)((k + 1) % 3) * B : nullptr;
     const int ts = timed_begin(c, "k_hmf_pass");
+#define MD_HMF_PASS(T_, W_, TH_, P_, SNAP_)                                                                          \
+    do {                                                                                                         \
+        if (in_pass)                                                                                             \
+            hipLaunchKernelGGL((k_hmf_pass<T_, W_, true>), dim3(g), dim3(256), 0, c->stream, TH_, P_, f_in, f_out, \
+                               mrd, mwr, mzero, c->scal, a, n, c->red, SNAP_);                                   \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_hmf_pass<T_, W_, false>), dim3(g), dim3(256), 0, c->stream, TH_, P_, f_in,      \
+                               f_out, mrd, mwr, mzero, c->scal, a, n, c->red, SNAP_);                            \
+    } while (0)
     if (f32state) {
-        const int w = vec_width(true, c->th32, c->p32, f_in, f_out);
-        if (w == 4)
-            hipLaunchKernelGGL((k_hmf_pass<float, 4>), dim3(g), dim3(256), 0, c->stream, c->th32, c->p32, f_in,
-                               f_out, c->scal, a, n, c->red, (float *)nullptr);
-        else
-            hipLaunchKernelGGL((k_hmf_pass<float, 1>), dim3(g), dim3(256), 0, c->stream, c->th32, c->p32, f_in,
-                               f_out, c->scal, a, n, c->red, (float *)nullptr);
+        if (vec_width(true, c->th32, c->p32, f_in, f_out) == 4) MD_HMF_PASS(float, 4, c->th32, c->p32, (float *)nullptr);
+        else MD_HMF_PASS(float, 1, c->th32, c->p32, (float *)nullptr);
     } else {
-        const int w = vec_width(false, th, p, f_in, f_out);  // snap: element stores, any alignment
-        if (w == 2)
-            hipLaunchKernelGGL((k_hmf_pass<double, 2>), dim3(g), dim3(256), 0, c->stream, th, p, f_in, f_out,
-                               c->scal, a, n, c->red, snap);
-        else
-            hipLaunchKernelGGL((k_hmf_pass<double, 1>), dim3(g), dim3(256), 0, c->stream, th, p, f_in, f_out,
-                               c->scal, a, n, c->red, snap);
+        // snap: element stores, any alignment
+        if (vec_width(false, th, p, f_in, f_out) == 2) MD_HMF_PASS(double, 2, th, p, snap);
+        else MD_HMF_PASS(double, 1, th, p, snap);
     }
+#undef MD_HMF_PASS
     hipError_t e = hipGetLastError();
     timed_end(c, ts);
-    if (e == hipSuccess && (flags & HMF_REDUCE)) {
+    if (e == hipSuccess && !in_pass && (flags & HMF_REDUCE)) {
         hipLaunchKernelGGL(k_hmf_finalize, dim3(1), dim3(1024), 0, c->stream, c->red, g, n, c->scal);
         e = hipGetLastError();
     }
@@ -343,8 +469,10 @@ hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, dou
 
 hipError_t launch_hmf_magnetization(md_ctx *c, double *out2)
 {
-    hipError_t e = hipMemcpyAsync(out2, c->scal, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
-    return e;
+    if (!hmf_in_pass(c))  // the reducing pass's one-block kernel left M in c->scal
+        return hipMemcpyAsync(out2, c->scal, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    hipLaunchKernelGGL(k_hmf_limbs_to_m, dim3(1), dim3(kWave), 0, c->stream, c->macc, (int)c->n, out2, c->scal);
+    return hipGetLastError();
 }
 
 hipError_t launch_hmf_convert(md_ctx *c, double *th, double *p, bool to_f32)

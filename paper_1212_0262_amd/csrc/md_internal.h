@@ -38,6 +38,15 @@ constexpr int kWave = 64;           // lanes per wavefront (CDNA)
 constexpr int kMaxJSplit = 64;
 constexpr int kRedSlots = 1 << 17;   // doubles of reduction scratch (HMF pass partials: first half)
 constexpr int kHmfGrid = 32768;      // most blocks of an HMF pass (2 FP64 partials each)
+// The HMF magnetization sums in fixed point (grids of at most kHmfInPassM blocks):
+// each reducing block adds its partial sums of cos and sin, as limbs of 2^-32 and
+// 2^-64, to slot (block mod kMSlots) with 64-bit integer atomics (exact, so the
+// total does not depend on the order), in one of three buffers that rotate over
+// the passes of a call.
+constexpr int kMSlots = 64;
+constexpr int kMLimbs = 4;  // sum cos: 2^-32 and 2^-64 limbs; sum sin: the same
+constexpr int kMWords = 3 * kMSlots * kMLimbs;
+constexpr int kHmfInPassM = 1024;  // grids of at most this many blocks use the fixed-point sums
 constexpr int kEnergyBlock = 256;
 constexpr int64_t kFusedMaxN = 65536;   // contexts up to this n carry the fused stage's operand buffers
 constexpr int kFusedMaxWaves = 16;      // wavefronts per fused block
@@ -118,6 +127,7 @@ struct md_ctx {
     double *part = nullptr;   // pair partials [jsplit][d][npad]; symmetric form: [npad / kSymTile][d][npad]
     double *red = nullptr;    // reduction partials [kRedSlots]
     double *scal = nullptr;   // small device scalars (HMF magnetization, ...)
+    long long *macc = nullptr;  // HMF magnetization sums, fixed point: [3][kMSlots][kMLimbs]
     float *th32 = nullptr;    // HMF FP32 state
     float *p32 = nullptr;
     void *fops[2] = {nullptr, nullptr};  // fused stage operands, alternating (n <= kFusedMaxN): [2][npad] of T
@@ -172,13 +182,19 @@ hipError_t launch_update_fused(md_ctx *c, int flags, double kick1, double kick2,
 hipError_t launch_fused(md_ctx *c, int flags, double kick1, double kick2, double drift, double *q, double *p,
                         double *f, const void *in, void *out, double *snap);
 // hmf.hip
+// The passes of one call are numbered k = 0, 1, ...: pass k takes M from the limb
+// sums pass k - 1 added, adds its own to buffer k mod 3 and zeroes buffer
+// (k + 1) mod 3.  launch_hmf_begin zeroes buffer 0 before the first pass of a call
+// whose passes read M.
 // snap (nullable, FP64 state only): with HMF_DRIFT, the drifted angles are also written there.
-hipError_t launch_hmf_pass(md_ctx *c, int flags, double kick1, double kick2, double drift,
+hipError_t launch_hmf_begin(md_ctx *c);
+hipError_t launch_hmf_pass(md_ctx *c, int k, int flags, double kick1, double kick2, double drift,
                            double *th, double *p, const double *f_in, double *f_out,
                            bool f32state, double *snap = nullptr);
 hipError_t launch_hmf_hvp_sums(md_ctx *c, const double *th, const double *w);
 hipError_t launch_hmf_adj_update(md_ctx *c, const double *th, int flags, double h, double h2, double a,
                                  double *lq, double *lp, double *out);
+// M from the limb sums of a call's pass 0, to out2[0..1] and the context scalars.
 hipError_t launch_hmf_magnetization(md_ctx *c, double *out2);
 const double *hmf_partials(const md_ctx *c);  // block partials of the latest reducing pass
 hipError_t launch_hmf_convert(md_ctx *c, double *th, double *p, bool to_f32);

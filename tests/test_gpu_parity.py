@@ -322,6 +322,27 @@ def test_ring_mixed_both_staged_kernels(n):
         assert rel_inf(fg[:, rows], fo) < FORCE_TOL[(RING, prec)], prec
 
 
+@pytest.mark.parametrize("n", [2_097_152, 2_097_153])
+def test_hmf_both_magnetization_sums(n):
+    """N = 2,097,152 is the largest N whose passes take the magnetization from the
+    fixed-point sums inside the next pass (1024 blocks of 2048 particles); one
+    particle more and a one-block kernel adds the FP64 block partials instead.
+    Both against the oracle (3 FP64 steps), both reproducible bit for bit, and in
+    both the force md_step leaves equals md_force at the final positions bit for
+    bit (the same block sums give the same M)."""
+    q, p = inputs.hmf_waterbag(n, seed=21)
+    f = oracle.force(HMF, q)
+    qo, po, fo = oracle.step(HMF, q, p, f, 0.1, 3, 0.0)
+    runs = [gpu_run(HMF, md.FP64, q, p, 0.0, 0.1, 3) for _ in range(2)]
+    qg, pg, fg, _ = runs[0]
+    assert np.abs(qg - qo).max() < 1e-10
+    assert np.abs(pg - po).max() < 1e-10
+    assert np.abs(fg - fo).max() < 1e-10
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(gpu_force(HMF, md.FP64, qg, 0.0), fg)
+
+
 def test_hmf_config_reduced():
     """HMF waterbag (theta in [-1, 1], p in [-1.2, 1.2]), dt = 0.1, FP64 vs oracle
     on 10^5 particles, 30 steps."""
