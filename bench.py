@@ -309,7 +309,7 @@ def hmf_workload(md, torch, args):
         # the stage pass's own launches (timed by the library), 32 bytes per particle each
         "roofline": {"bound": "hbm", "achieved": round(fp["pass_algorithmic_GBs"], 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(fp["pass_algorithmic_GBs"] / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": "k_hmf_pass<double, 2>", "kernel_timed_as": fp["pass_timed_as"],
+                     "kernel": "k_hmf_pass<double, 2, false>", "kernel_timed_as": fp["pass_timed_as"],
                      "kernel_ms_avg": round(fp["pass_ms_avg"], 5), "bytes_per_launch": HMF_N * HMF_BYTES["fp64"] // 3,
                      "step_GBs": round(fp["algorithmic_GBs"], 1),
                      "bytes_per_particle_step": HMF_BYTES["fp64"]},
