@@ -107,9 +107,9 @@ __device__ __forceinline__ void to_limbs(double x, long long &hi, long long &lo)
     lo = (long long)rint((y - h) * 0x1p32);
 }
 
-// M = (the total of the limb sums in acc) / n, by each wavefront on its own (no
-// barrier): lane l loads slot l, a butterfly adds the slots in 64-bit integers
-// (exact, so every lane holds the same total in any order).
+// M = (the total of the limb sums) / n, by a wavefront whose lane l holds the limbs
+// of slot l: a butterfly adds the slots in 64-bit integers (exact, so every lane
+// ends with the same total, in any order).
 __device__ __forceinline__ void limbs_sum(long long (&v)[kMLimbs], int n, double &mx, double &my)
 {
 #pragma unroll
@@ -141,12 +141,12 @@ __device__ __forceinline__ void limbs_sum_block(const long long *__restrict__ ac
 
 // One kick/drift/reduce pass over all particles (grid-stride over a grid fixed
 // per n, so every partial sum is reproducible).  T: state type; W: elements per
-// vector access.  HMF_KICK_M / HMF_STORE_F take the magnetization from the limb
-// sums mrd if given (block 0 also stores it to M), else from M[0..1]; HMF_REDUCE writes the block
-// partials (sum cos, sum sin) to red[2b], red[2b+1] and adds their limbs to mwr;
-// block 0 zeroes mzero (if given) for a later pass.  Launched with 256 threads.
-// LIMBS: the fixed-point sums (small grids); without it the kernel reads M[0..1]
-// and leaves the partials to the one-block kernel, with no code of the limbs.
+// vector access.  HMF_REDUCE writes the block partials (sum cos, sum sin) to
+// red[2b], red[2b+1].  LIMBS (small grids): HMF_KICK_M / HMF_STORE_F take the
+// magnetization from the limb sums mrd (block 0 also stores it to M), HMF_REDUCE
+// adds the partials' limbs to mwr, and block 0 zeroes mzero for a later pass.
+// Without LIMBS the kernel reads M[0..1] and leaves the partials to the one-block
+// kernel (no code of the limbs).  Launched with 256 threads.
 template <typename T, int W, bool LIMBS>
 __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restrict__ p,
                                                   const double *__restrict__ f_in, double *__restrict__ f_out,
