@@ -437,11 +437,13 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ part,
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double fs[D];
+    if (flags & UPD_F_FROM_PART) slot_sums<D>(part, S, npad, i, fs);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         double fd = 0.0;
         if (flags & UPD_F_FROM_PART) {
-            fd = pref * slot_sum<D>(part, S, d, npad, i);
+            fd = pref * fs[d];
         } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
             fd = f[(size_t)d * n + i];
         }
