@@ -249,8 +249,11 @@ int md_step(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nstep
 int md_energy(md_ctx *c, const double *q, const double *p, double *out_dev3);
 
 /*
- * HMF magnetization of eq. 7 at positions q: out_dev2[0] = Mx, out_dev2[1] = My
- * (FP64 reduction).  MD_HMF contexts only.
+ * HMF magnetization of eq. 7 at positions q: out_dev2[0] = Mx, out_dev2[1] = My.
+ * The sum is reproducible bit for bit and the same one md_force and md_step use:
+ * for n <= 2097152 the exact sum of the FP64 block partials (in 64-bit fixed
+ * point) rounded once to FP64, above that the block partials added in FP64 in a
+ * fixed order.  MD_HMF contexts only.
  */
 int md_magnetization(md_ctx *c, const double *q, double *out_dev2);
 
@@ -310,7 +313,7 @@ int md_step_vjp_recorded(md_ctx *c, const double *q0, double dt, int64_t nsteps,
  * events recorded on the context's stream; later launches run untimed.  The
  * dominant kernel is the one that evaluates the pairs: the tile-pair kernel of the
  * symmetric form (not its diagonal tiles), the pair kernel of the staged form, the
- * fused kernel, the HMF stage pass (not its finalize); for ensembles the tile-pair
+ * fused kernel, the HMF stage pass (not the one-block sum after it); for ensembles the tile-pair
  * or the pair kernel.  Launches enqueued while the stream is being captured into
  * a graph are not timed.  It creates 2 max_launches HIP events (host-side
  * objects: no workspace or device memory is taken); calling it again starts over.
