@@ -212,7 +212,11 @@ int md_max_j_split(int64_t n);
  *                     other models, precisions or n;
  *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 8192 (the
  *                     built-in tiles there are the fused form's), symmetric
- *                     when it applies and n >= MD_SYMMETRIC_AUTO_N, else staged;
+ *                     when it applies and n reaches the model's threshold
+ *                     (MD_SYMMETRIC_AUTO_N for 2D gravity; for the Ring
+ *                     MD_SYMMETRIC_AUTO_N_RING with MD_MIXED and
+ *                     MD_SYMMETRIC_AUTO_N_RING64 with MD_FP64: measured
+ *                     crossovers on MI355X), else staged;
  *                     for ensembles, symmetric when it applies and their tile
  *                     pairs a < b outnumber their diagonal tiles.
  * md_get_launch returns the form md_step will take (STAGED, FUSED or
@@ -221,6 +225,8 @@ int md_max_j_split(int64_t n);
  */
 enum md_launch { MD_LAUNCH_AUTO = 0, MD_LAUNCH_STAGED = 1, MD_LAUNCH_FUSED = 2, MD_LAUNCH_SYMMETRIC = 3 };
 #define MD_SYMMETRIC_AUTO_N 49152
+#define MD_SYMMETRIC_AUTO_N_RING 36864
+#define MD_SYMMETRIC_AUTO_N_RING64 32768
 int md_set_launch(md_ctx *c, int mode);
 int md_get_launch(const md_ctx *c);
 

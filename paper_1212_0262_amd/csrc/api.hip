@@ -182,7 +182,7 @@ int form_of(const md_ctx *c)
         const bool s = c->launch == MD_LAUNCH_SYMMETRIC || (c->launch == MD_LAUNCH_AUTO && batch_sym_auto(*c->batch));
         return s && c->batch->sym ? MD_LAUNCH_SYMMETRIC : MD_LAUNCH_STAGED;
     }
-    if (c->launch == MD_LAUNCH_SYMMETRIC || (c->launch == MD_LAUNCH_AUTO && c->n >= kSymAutoN))
+    if (c->launch == MD_LAUNCH_SYMMETRIC || (c->launch == MD_LAUNCH_AUTO && c->n >= sym_auto_n(c->model, c->prec)))
         if (sym_ok(c)) return MD_LAUNCH_SYMMETRIC;
     if (c->launch == MD_LAUNCH_STAGED || c->launch == MD_LAUNCH_SYMMETRIC || !fused_ok(c, c->tiles))
         return MD_LAUNCH_STAGED;

@@ -55,7 +55,12 @@ constexpr int64_t kFusedAutoN = 8192;   // MD_LAUNCH_AUTO takes the fused form u
 constexpr int kSymTile = 1024;          // particles per tile of the symmetric 2D form (4 waves x 64 x 4 i)
 constexpr int64_t kSymMinN = 2048;      // the symmetric form needs two tiles at least
 constexpr int64_t kSymMaxN = 1 << 20;   // and at most 1024 tiles (its partial slots: 8 d n^2 / 1024 bytes)
-constexpr int64_t kSymAutoN = MD_SYMMETRIC_AUTO_N;  // MD_LAUNCH_AUTO takes it from this n
+// MD_LAUNCH_AUTO takes the symmetric form from this n (measured crossovers)
+inline int64_t sym_auto_n(int model, int prec)
+{
+    if (model != MD_RING) return MD_SYMMETRIC_AUTO_N;
+    return prec == MD_FP64 ? MD_SYMMETRIC_AUTO_N_RING64 : MD_SYMMETRIC_AUTO_N_RING;
+}
 
 // Lane groups per wavefront of the fused stage for j_split j ranges: the largest
 // power of two <= 8 dividing j_split (more, smaller i tiles: more blocks).

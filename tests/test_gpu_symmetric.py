@@ -176,10 +176,14 @@ def test_launch_form_and_refusals():
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
     big64 = md.md_init(GRAV2D, md.FP64, md.SYMMETRIC_AUTO_N, EPS)
     assert md.md_get_launch(big64) == md.LAUNCH_SYMMETRIC
-    ring = md.md_init(RING, md.MIXED, md.SYMMETRIC_AUTO_N, 0.01)
-    assert md.md_get_launch(ring) == md.LAUNCH_SYMMETRIC
-    ring64 = md.md_init(RING, md.FP64, md.SYMMETRIC_AUTO_N, 0.01)
-    assert md.md_get_launch(ring64) == md.LAUNCH_SYMMETRIC
+    # the Ring's own thresholds (its symmetric form gains more per pair than 2D's)
+    for prec, n0 in ((md.MIXED, md.SYMMETRIC_AUTO_N_RING), (md.FP64, md.SYMMETRIC_AUTO_N_RING64)):
+        ring = md.md_init(RING, prec, n0, 0.01)
+        assert md.md_get_launch(ring) == md.LAUNCH_SYMMETRIC
+        ring_below = md.md_init(RING, prec, n0 - 1, 0.01)
+        assert md.md_get_launch(ring_below) == md.LAUNCH_STAGED
+        ring.close()
+        ring_below.close()
     below = md.md_init(GRAV2D, md.MIXED, md.SYMMETRIC_AUTO_N - 1, EPS)
     assert md.md_get_launch(below) != md.LAUNCH_SYMMETRIC
     md.md_set_launch(below, md.LAUNCH_SYMMETRIC)
@@ -200,7 +204,7 @@ def test_launch_form_and_refusals():
     batch = md.md_batch_init(GRAV2D, md.FP64, [0, 3000, 6000], EPS)  # no symmetric FP64 2D ensembles
     with pytest.raises(md.MDError):
         md.md_set_launch(batch, md.LAUNCH_SYMMETRIC)
-    for c in (big, big64, ring, ring64, below, batch):
+    for c in (big, big64, below, batch):
         c.close()
 
 
