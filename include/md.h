@@ -224,7 +224,7 @@ int md_max_j_split(int64_t n);
  * STAGED or SYMMETRIC.
  */
 enum md_launch { MD_LAUNCH_AUTO = 0, MD_LAUNCH_STAGED = 1, MD_LAUNCH_FUSED = 2, MD_LAUNCH_SYMMETRIC = 3 };
-#define MD_SYMMETRIC_AUTO_N 49152
+#define MD_SYMMETRIC_AUTO_N 43008
 #define MD_SYMMETRIC_AUTO_N_RING 36864
 #define MD_SYMMETRIC_AUTO_N_RING64 32768
 int md_set_launch(md_ctx *c, int mode);
