@@ -584,15 +584,17 @@ Tiles default_tiles(int model, int prec, int64_t n)
     t.jtile = 128;
     if (n <= kFusedAutoN) {
         // the automatic fused launch: the most j ranges (8 lane groups x 8 wavefronts
-        // per block) measured fastest from N = 512 to 8192; two i per lane above 4096
-        t.ipl = n > 4096 ? 2 : 1;
+        // per block) measured fastest from N = 512 to 4096 (above that the staged form
+        // with the tiles below is faster: its update adds the slots 16 loads at a time)
+        t.ipl = 1;
         t.jsplit = max_j_split(n) < 64 ? max_j_split(n) : 64;
         return t;
     }
     t.ipl = n >= 65536 ? 2 : 1;
     if (n < 131072) {
-        // staged, N = 8193 .. 131071: 32 j ranges measured best or within 3% for both
-        // models and both precisions (autotuner at N = 10240, 20480, 51200, 102400)
+        // staged, N = 4097 .. 131071: 32 j ranges measured best or within 3% for both
+        // models and both precisions (autotuner at N = 10240, 20480, 51200, 102400;
+        // N = 6144 and 8192 against 16 and 64 j ranges and two i per lane)
         t.jsplit = max_j_split(n) < 32 ? max_j_split(n) : 32;
         return t;
     }

@@ -91,7 +91,7 @@ def test_fused_tile_shapes(model, eps, dt, ipl, split, jtile):
 
 def test_auto_launch_form_and_validation():
     small = md.md_init(RING, md.FP64, 2048, 0.01)
-    assert md.md_get_launch(small) == md.LAUNCH_FUSED          # n <= 8192 and the built-in tiles fit
+    assert md.md_get_launch(small) == md.LAUNCH_FUSED          # n <= 4096 and the built-in tiles fit
     assert md.md_get_tiles(small) == (1, 4, 64, 128)
     big = md.md_init(GRAV2D, md.FP64, 32768, 1e-3)
     assert md.md_get_launch(big) == md.LAUNCH_STAGED           # above the automatic size
