@@ -593,9 +593,12 @@ Tiles default_tiles(int model, int prec, int64_t n)
     t.ipl = n >= 65536 ? 2 : 1;
     if (n < 131072) {
         // staged, N = 4097 .. 131071: 32 j ranges measured best or within 3% for both
-        // models and both precisions (autotuner at N = 10240, 20480, 51200, 102400;
-        // N = 6144 and 8192 against 16 and 64 j ranges and two i per lane)
-        t.jsplit = max_j_split(n) < 32 ? max_j_split(n) : 32;
+        // models and both precisions (autotuner at N = 51200, 102400; N = 4096 to 8192
+        // against 16 and 64 j ranges and two i per lane); 64 j ranges measured 1.4-3.5%
+        // faster at N = 10240 and 20480 (every model and precision), since the update
+        // adds the slots 16 loads at a time
+        const int js = (n > 8192 && n <= 20480) ? 64 : 32;
+        t.jsplit = max_j_split(n) < js ? max_j_split(n) : js;
         return t;
     }
     const int64_t wi = (n + kWave * t.ipl - 1) / (kWave * t.ipl);
