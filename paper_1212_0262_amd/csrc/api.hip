@@ -595,9 +595,10 @@ Tiles default_tiles(int model, int prec, int64_t n)
         // staged, N = 4097 .. 131071: 32 j ranges measured best or within 3% for both
         // models and both precisions (autotuner at N = 51200, 102400; N = 4096 to 8192
         // against 16 and 64 j ranges and two i per lane); 64 j ranges measured 1.4-3.5%
-        // faster at N = 10240 and 20480 (every model and precision), since the update
-        // adds the slots 16 loads at a time
-        const int js = (n > 8192 && n <= 20480) ? 64 : 32;
+        // faster at N = 10240 and 20480 and up to 2.6% faster (2D FP64 level) from 24576
+        // to 40960, every model and precision, since the update adds the slots 16
+        // loads at a time
+        const int js = (n > 8192 && n <= 40960) ? 64 : 32;
         t.jsplit = max_j_split(n) < js ? max_j_split(n) : js;
         return t;
     }

@@ -101,7 +101,7 @@ def test_auto_launch_form_and_validation():
         md.md_set_tiles(big, 1, 4, 17, 128)
     with pytest.raises(md.MDError):                             # 13 wavefronts x 4 KiB of partials > 48 KiB
         md.md_set_tiles(big, 4, 4, 13, 128)
-    assert md.md_get_tiles(big)[2] == 32                        # unchanged by the refused calls
+    assert md.md_get_tiles(big)[2] == 64                        # unchanged by the refused calls
     md.md_set_launch(big, md.LAUNCH_STAGED)
     md.md_set_tiles(big, 1, 4, 17, 128)
     assert md.md_get_launch(big) == md.LAUNCH_STAGED
