@@ -25,6 +25,7 @@ same configuration (cpu_baseline).
 Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 2] [--no-fp64] [--no-cpu] [--no-variants]
                        [--launch auto|staged|symmetric]
        python bench.py --workload ring|hmf|ensemble|adjoint|paper_errors   (the other workloads)
+       python bench.py --workload copy_calibration   (a plain copy of known size, for the traffic counters)
 """
 from __future__ import annotations
 
@@ -57,6 +58,8 @@ SYM_TILE = 1024              # particles per tile of the symmetric form
 SYM_FLOPS_PER_EVAL = 14      # symmetric form, per pair evaluated: 2 sub, 2 FMA (r^2), 2 FMA (i side), 2 FMA (j side)
 PAIR_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("pair.hip", "pair_terms.h", "device.h")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "grav2d_pair_mixed_n262144_pmc.txt")
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+GATE_BAR = {"mixed": 1e-5, "fp64": 1e-6}   # |E - E_oracle| / |E0| at every report time
 
 
 def log(msg: str) -> None:
@@ -139,6 +142,57 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup, launch=None):
     }
 
 
+def oracle_golden(n):
+    """The FP64 oracle's energies along this run (tests/golden, written by
+    tests/golden/make_grav2d_golden.py from the oracle alone), or None."""
+    path = os.path.join(GOLDEN_DIR, f"grav2d_disk_seed3_n{n}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        g = json.load(fh)
+    if g["n"] != n or g["seed"] != SEED or g["eps"] != EPS or g["dt"] != DT or g["sigma"] != SIGMA:
+        return None
+    return g
+
+
+def gate_run(md, torch, prec, q0, p0, golden):
+    """Untimed: the run from the initial state in chunks of the golden's report
+    interval, md_energy at every report time; returns the energies [times][K, V, E]."""
+    import numpy as np
+    ctx = md.md_init(md.GRAV2D, prec, N, EPS)
+    q, p = torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda()
+    f = torch.empty_like(q)
+    md.md_force(ctx, q, f)
+    E = [md.md_energy(ctx, q, p).cpu().numpy()]
+    for s0, s1 in zip(golden["steps"][:-1], golden["steps"][1:]):
+        md.md_step(ctx, q, p, f, DT, s1 - s0)
+        E.append(md.md_energy(ctx, q, p).cpu().numpy())
+    ctx.close()
+    return np.array(E)
+
+
+def oracle_gate(md, torch, q0, p0, golden, precs):
+    """Energies of each precision form against the oracle's at every report time
+    (relative energy error of Sec. 4, against |E0| and against K0 + |V0|)."""
+    import numpy as np
+    Eo = np.array([golden["K"], golden["V"], golden["E"]]).T
+    E0, KV0 = abs(Eo[0, 2]), abs(Eo[0, 0]) + abs(Eo[0, 1])
+    out = {"report_steps": golden["steps"], "oracle_E0": Eo[0].tolist(),
+           "oracle_max_dE_E0": float(np.abs(Eo[:, 2] - Eo[0, 2]).max() / E0)}
+    for name, prec in precs:
+        log(f"bench: oracle gate {name} ({golden['steps'][-1]} steps, energies every {golden['every']})")
+        E = gate_run(md, torch, prec, q0, p0, golden)
+        d = np.abs(E[:, 2] - Eo[:, 2])
+        out[name] = {"max_dE_vs_oracle_over_absE0": float(d.max() / E0),
+                     "max_dE_vs_oracle_over_K0_plus_absV0": float(d.max() / KV0),
+                     "E0_vs_oracle_over_K0_plus_absV0": float(np.abs(E[0] - Eo[0]).max() / KV0),
+                     "max_dE_E0": float(np.abs(E[:, 2] - E[0, 2]).max() / E0),
+                     "bar": GATE_BAR[name], "pass": bool(d.max() <= GATE_BAR[name] * E0)}
+        log(f"bench: {name} vs oracle: max |E - E_oracle| / |E0| = {d.max() / E0:.2e} "
+            f"(bar {GATE_BAR[name]:.0e}), / (K0+|V0|) = {d.max() / KV0:.2e}")
+    return out
+
+
 def cpu_baseline(q0, target_s: float = 10.0):
     """FP64 oracle pair throughput on sampled force rows of the same configuration."""
     import numpy as np
@@ -170,6 +224,10 @@ HMF_BYTES = {"fp64": 96, "f32state": 48}   # per particle-step: 3 passes x (read
 RING_N = 2048
 RING_EPS = 0.01
 RING_DT = 0.05
+RING_FLOPS_PER_PAIR = 11          # eq. 9 in FP64, plus one rsqrt
+RING_FP64_CYCLES_PER_PAIR = 13 * 4.6 + 16.0
+LAUNCH_FLOOR_US = 1.55
+kWAVE = 64
 PEAK_HBM_GBS = 8000.0
 
 
@@ -192,11 +250,13 @@ def ring_workload(md, torch, args):
         md.md_step(ctx, qw, pw, fw, RING_DT, max(1, args.warmup))
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        md.md_timing_begin(ctx, 3 * args.steps + 4)  # the pair (fused) kernel's own launches
         ev0.record()
         md.md_step(ctx, q, p, f, RING_DT, args.steps)
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
+        k_ms, k_n, k_name = md.md_timing_end(ctx)
         e1 = md.md_energy(ctx, q, p).cpu().numpy()
         # the same steps captured as one HIP graph (launch-bound at this N)
         qg, pg, fg = qw.clone(), pw.clone(), fw.clone()
@@ -229,6 +289,7 @@ def ring_workload(md, torch, args):
         torch.cuda.synchronize()
         staged_ms = ev0.elapsed_time(ev1)
         res[name] = {"ms": ms, "us_per_step": 1e3 * ms / args.steps, **res_graph, "launch": form,
+                     "kernel_timed_as": k_name, "kernel_us_avg": 1e3 * k_ms / max(k_n, 1), "kernel_launches": k_n,
                      "staged_us_per_step": 1e3 * staged_ms / args.steps,
                      "gpairs_per_s": 3.0 * RING_N ** 2 * args.steps / (ms * 1e-3) / 1e9,
                      "dE_E": float(abs(e1[2] - e0[2]) / abs(e0[2])), "tiles": list(md.md_get_tiles(ctx))}
@@ -245,12 +306,31 @@ def ring_workload(md, torch, args):
         cpu = {"value": (3 * nst + 1) * RING_N ** 2 / dt / 1e9, "unit": "Gpair-interactions/s", "cores": 1,
                "kind": "oracle", "sample": f"{nst} FP64 Yoshida steps of the full N={RING_N} system, 1 thread"}
     fp = res["fp64"]
+    # roofline of the FP64 pair (fused) kernel: 11 flops + 1 rsqrt per ordered pair (eq. 9:
+    # 3 for the numerator, 4 for 1 + eps - cos d, 2 for the cube, 2 to accumulate); at
+    # this N it is bound by latency, so the kernel time is set beside two floors: the
+    # VALU floor of its instruction mix (13 FP64 VALU of 4.6 cycles + v_rsq_f64 of 16
+    # cycles per pair and wavefront, measured costs) and the gap between back-to-back
+    # launches (1.55 us measured for empty kernels)
+    k_s = fp["kernel_us_avg"] * 1e-6
+    tf = RING_FLOPS_PER_PAIR * RING_N ** 2 / k_s / 1e12
+    valu_floor_us = RING_N ** 2 * RING_FP64_CYCLES_PER_PAIR / kWAVE / SIMD_CYCLES_PER_S * 1e6
+    roof = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "kernel": fp["kernel_timed_as"], "kernel_us_avg": round(fp["kernel_us_avg"], 3),
+            "kernel_launches": fp["kernel_launches"], "flops_per_pair": RING_FLOPS_PER_PAIR,
+            "pairs_per_launch": RING_N ** 2,
+            "latency": {"evaluation_us": round(fp["kernel_us_avg"], 3), "valu_floor_us": round(valu_floor_us, 3),
+                        "launch_floor_us": LAUNCH_FLOOR_US,
+                        "step_us_eager": round(fp["us_per_step"], 3),
+                        "step_us_graph": round(fp["graph_us_per_step"], 3),
+                        "evaluations_per_step": 3}}
     return {
         "metric": "Gpair-interactions/s (Ring N=2048, FP64)", "value": round(fp["gpairs_per_s"], 3),
         "unit": "Gpair-interactions/s", "ms_per_step": round(fp["us_per_step"] / 1e3, 5), "dtype": "f64",
         "config": {"workload": "ring waterbag N=2048 eps=0.01 dt=0.05 seed=1", "model": "ring", "n": RING_N,
                    "eps": RING_EPS, "dt": RING_DT, "precision": "fp64", "tiles": fp["tiles"]},
-        "roofline": None, "cpu_baseline": cpu, "ring": res,
+        "roofline": roof, "cpu_baseline": cpu, "ring": res,
     }
 
 
@@ -320,6 +400,8 @@ def hmf_workload(md, torch, args):
 ENS_NB = 256
 ENS_EPS = 0.01
 ENS_DT = 0.05
+ENS_SYM_KAHAN_FLOPS = 21      # half-angle Ring term 11 (+ rsqrt), two compensated adds of 5
+ENS_STAGED_KAHAN_FLOPS = 16   # term 11 (+ rsqrt), one compensated add
 
 
 def ensemble_workload(md, torch, args):
@@ -364,11 +446,13 @@ def ensemble_workload(md, torch, args):
         qe, pe, fe = q.clone(), p.clone(), f.clone()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        md.md_timing_begin(ctx, 3 * args.steps + 4)  # the dominant (tile-pair) kernel's launches
         ev0.record(stream)
         md.md_step(ctx, qe, pe, fe, ENS_DT, args.steps)
         ev1.record(stream)
         torch.cuda.synchronize()
         eager_ms = ev0.elapsed_time(ev1)
+        k_ms, k_n, k_name = md.md_timing_end(ctx)
         # capture the whole run as one graph on the real buffers, then replay it once (timed)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
@@ -423,6 +507,23 @@ def ensemble_workload(md, torch, args):
         cpu = {"value": npairs / dt / 1e9, "unit": "Gpair-interactions/s", "cores": oracle.get_threads(),
                "kind": "oracle", "sample": "force + 2 FP64 Yoshida steps of the 8 smallest realizations"}
     ctx.close()
+    # roofline of the tile-pair kernel (symmetric form, Kahan): the pairs of particles in
+    # different tiles of a realization, each evaluated once for both: 11 flops + 1 rsqrt
+    # for the half-angle term, 5 for each of the two compensated adds
+    tile_pairs = 0.0
+    for nb_ in sizes.astype(np.int64):
+        t = np.full(-(-int(nb_) // SYM_TILE), SYM_TILE, dtype=np.float64)
+        t[-1] = nb_ - SYM_TILE * (len(t) - 1)
+        tile_pairs += (float(nb_) ** 2 - float((t * t).sum())) / 2
+    k_s = k_ms / max(k_n, 1) * 1e-3
+    sym = launch == "symmetric"
+    flops = (ENS_SYM_KAHAN_FLOPS * tile_pairs) if sym else (ENS_STAGED_KAHAN_FLOPS * pairs_per_eval)
+    tf = flops / k_s / 1e12
+    roof = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel_timed_as": k_name,
+            "kernel_ms_avg": round(k_ms / max(k_n, 1), 4), "kernel_launches": k_n,
+            "flops_per_evaluation": ENS_SYM_KAHAN_FLOPS if sym else ENS_STAGED_KAHAN_FLOPS,
+            "evaluations_per_launch": tile_pairs if sym else pairs_per_eval}
     return {
         "metric": "Gpair-interactions/s (Ring ensemble, 256 realizations, graph-replayed)",
         "value": round(pairs / (graph_ms * 1e-3) / 1e9, 3), "unit": "Gpair-interactions/s",
@@ -431,7 +532,7 @@ def ensemble_workload(md, torch, args):
                    "model": "ring", "nb": ENS_NB, "n_total": int(off[-1]), "pairs_per_eval": pairs_per_eval,
                    "precision": "mixed_kahan", "launch": launch, "staged_tiles_tuned": list(best),
                    "staged_tiles_default": list(default_tiles)},
-        "roofline": None, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu,
         "ensemble": {"graph_ms": graph_ms, "eager_ms": eager_ms, "graph_equals_eager": same,
                      "step_ms": t_auto, "staged_step_ms_default_tiles": t_default,
                      "staged_step_ms_tuned": table[0][1], "speedup_vs_tuned_staged": table[0][1] / t_auto,
@@ -452,6 +553,7 @@ ADJ_N = 32_768
 ADJ_EPS = 1e-3
 ADJ_DT = 0.01
 ADJ_CKPT = 50
+ADJ_HVP_FLOPS = 22
 
 
 def adjoint_workload(md, torch, args):
@@ -517,6 +619,23 @@ def adjoint_workload(md, torch, args):
         ad = float(np.sum(gq * v[:2]) + np.sum(gp * v[2:]))
         fd = (J(q0 + hbest * v[:2], p0 + hbest * v[2:]) - J(q0 - hbest * v[:2], p0 - hbest * v[2:])) / (2 * hbest)
         rel.append(abs(ad - fd) / max(abs(fd), 1e-300))
+    # roofline of the Hessian-vector product's pair kernel (FP64; 22 flops + 1 reciprocal
+    # per ordered pair: r, |r|^2 + eps, w_i - w_j, r.(w_i - w_j)/s, 2 t/s, four accumulating FMAs)
+    wv = torch.from_numpy(np.random.default_rng(7).normal(size=(2, ADJ_N))).cuda()
+    hv = torch.empty_like(qd)
+    md.md_hvp(ctx, qd, wv, hv)
+    torch.cuda.synchronize()
+    md.md_timing_begin(ctx, 20)
+    for _ in range(20):
+        md.md_hvp(ctx, qd, wv, hv)
+    torch.cuda.synchronize()
+    k_ms, k_n, k_name = md.md_timing_end(ctx)
+    k_s = k_ms / max(k_n, 1) * 1e-3
+    tf = ADJ_HVP_FLOPS * ADJ_N ** 2 / k_s / 1e12
+    roof = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None, "kernel_timed_as": k_name,
+            "kernel_ms_avg": round(k_ms / max(k_n, 1), 4), "kernel_launches": k_n,
+            "flops_per_pair": ADJ_HVP_FLOPS, "pairs_per_launch": ADJ_N ** 2}
     ctx.close()
     cpu = None
     if not args.no_cpu:
@@ -547,7 +666,7 @@ def adjoint_workload(md, torch, args):
         "value": round(t_grad, 4), "unit": "s", "ms_per_step": round(1e3 * t_grad / nst, 4), "dtype": "f64",
         "config": {"workload": "grav2d adjoint N=32768 eps=1e-3 dt=0.01 uniform disk seed=5, checkpoints every 50",
                    "model": "grav2d", "n": ADJ_N, "steps": nst, "checkpoint_every": ADJ_CKPT, "precision": "fp64"},
-        "roofline": None, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu,
         "adjoint": {"K_T": float(K), "forward_s": t_fwd, "gradient_s": t_grad,
                     "gradient_over_forward": t_grad / t_fwd,
                     "recorded_gradient_s": t_rec, "recorded_over_forward": t_rec / t_fwd,
@@ -647,74 +766,31 @@ def paper_errors_workload(md, torch, args):
     }
 
 
-# Seconds per step on one GK104 (half of a GTX 690), from the paper's Tables 1-3:
-# context for the MI355X numbers at the same N, not a target (other hardware,
-# initial conditions and eps not stated).
-PAPER_1GPU_S = {
-    "hmf": {100_000: 6.3e-4, 1_000_000: 4.0e-3, 10_000_000: 3.7e-2, 50_000_000: 1.81e-1},
-    "ring": {10_240: 0.04, 51_200: 0.95, 102_400: 3.9, 512_000: 97.5},
-    "grav2d": {10_240: 0.023, 20_480: 0.047, 102_400: 0.99, 512_000: 26.8, 1_024_000: 106.5},
-}
-
-
-def paper_tables_workload(md, torch, args):
-    """md_step time per step at every N of the paper's timing tables (Sec. 4,
-    Tables 1-3), FP64 and mixed, on synthetic states of the configurations'
-    shapes (HMF and Ring waterbags, 2D uniform disk; eps = 0.01 Ring, 1e-3 2D),
-    with the paper's single-GPU time beside each as context."""
-    from paper_1212_0262_amd import inputs
-    rows = []
-    budget_s = 1.5  # timed seconds per (model, precision, N)
-    for model_name, model in (("hmf", md.HMF), ("ring", md.RING), ("grav2d", md.GRAV2D)):
-        precs = (("fp64", md.FP64), ("mixed", md.MIXED_F32STATE if model == md.HMF else md.MIXED))
-        eps = {"hmf": 0.0, "ring": 0.01, "grav2d": 1e-3}[model_name]
-        dt = {"hmf": 0.1, "ring": 0.05, "grav2d": 0.01}[model_name]
-        for n, paper_s in PAPER_1GPU_S[model_name].items():
-            if model == md.HMF:
-                q0, p0 = inputs.hmf_waterbag(n, seed=2)
-            elif model == md.RING:
-                q0, p0 = inputs.ring_waterbag(n, seed=1)
-            else:
-                q0, p0 = inputs.grav2d_disk(n, seed=3)
-            row = {"model": model_name, "n": n, "paper_1gpu_s_per_step": paper_s}
-            for pname, prec in precs:
-                ctx = md.md_init(model, prec, n, eps)
-                q, p = torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda()
-                f = torch.empty_like(q)
-                md.md_force(ctx, q, f)
-                md.md_step(ctx, q, p, f, dt, 1)
-                torch.cuda.synchronize()
-                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                ev0.record()
-                md.md_step(ctx, q, p, f, dt, 1)
-                ev1.record()
-                torch.cuda.synchronize()
-                one = ev0.elapsed_time(ev1) * 1e-3
-                steps = max(1, min(200, int(budget_s / max(one, 1e-6))))
-                ev0.record()
-                md.md_step(ctx, q, p, f, dt, steps)
-                ev1.record()
-                torch.cuda.synchronize()
-                t = ev0.elapsed_time(ev1) * 1e-3 / steps
-                row[pname + "_s_per_step"] = t
-                row[pname + "_speedup_vs_paper_1gpu"] = paper_s / t
-                if model != md.HMF:
-                    row[pname + "_gpairs_per_s"] = 3.0 * n * n / t / 1e9
-                row[pname + "_tiles"] = list(md.md_get_tiles(ctx))
-                row[pname + "_launch"] = LAUNCH_NAMES.get(md.md_get_launch(ctx), "staged")
-                ctx.close()
-            log(f"bench: {model_name} N={n}: fp64 {row['fp64_s_per_step']:.3e} s, mixed {row['mixed_s_per_step']:.3e} s "
-                f"per step (paper 1 GPU {paper_s:g} s)")
-            rows.append(row)
-    d2 = [r for r in rows if r["model"] == "grav2d"]
-    return {
-        "metric": "Gpair-interactions/s (2D gravity N=1,024,000, mixed), and every N of the paper's Tables 1-3",
-        "value": round(d2[-1]["mixed_gpairs_per_s"], 3), "unit": "Gpair-interactions/s",
-        "ms_per_step": round(1e3 * d2[-1]["mixed_s_per_step"], 4), "dtype": "f32",
-        "config": {"workload": "the N of the paper's timing tables: HMF 1e5-5e7, Ring 10,240-512,000, "
-                               "2D 10,240-1,024,000; FP64 and mixed"},
-        "roofline": None, "cpu_baseline": None, "paper_tables": rows,
-    }
+def copy_calibration_workload(md, torch, args):
+    """A plain device copy of known size, for the HBM-traffic counters: run it under
+    rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE); the elementwise kernel reads and
+    writes exactly 512 MiB per dispatch, so the counter per dispatch divided by
+    that size is the factor that turns the counter into bytes for the library's
+    kernels measured the same way."""
+    mib, reps = 512, 3
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)  # one read and one write of n float32 values
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    gbs = 2 * mib * (1 << 20) / (ms * 1e-3) / 1e9
+    return {"metric": "GB/s of a plain device copy (512 MiB read + 512 MiB written per dispatch)",
+            "value": round(gbs, 1), "unit": "GB/s", "ms_per_step": round(ms, 4), "dtype": "f32",
+            "config": {"workload": "copy calibration: torch.mul(src, 1.0, out=dst), 2^27 float32, 3 dispatches"},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+            "cpu_baseline": None}
 
 
 def grav2d_workload(md, torch, args):
@@ -751,6 +827,14 @@ def grav2d_workload(md, torch, args):
         log("bench: mixed, staged launch")
         staged = run_variant(md, torch, md.MIXED, q0, p0, args.steps, args.warmup, md.LAUNCH_STAGED)
         log(f"bench: mixed staged {staged['gpairs_per_s']:.1f} Gpairs/s")
+    golden = oracle_golden(N)
+    gate = None
+    if golden is not None:
+        gate = oracle_gate(md, torch, q0, p0, golden,
+                           [("mixed", md.MIXED)] + ([] if args.no_fp64 else [("fp64", md.FP64)]))
+        if args.steps in golden["steps"]:  # the timed run itself, at its last step
+            k = golden["steps"].index(args.steps)
+            gate["timed_run_dE_vs_oracle_over_absE0"] = abs(mixed["E1"][2] - golden["E"][k]) / abs(golden["E"][0])
     cpu = None
     if not args.no_cpu:
         log("bench: cpu baseline (oracle)")
@@ -775,7 +859,7 @@ def grav2d_workload(md, torch, args):
         executed = FLOPS_PER_PAIR * N * N
         kernel = "k_pair_2d<float, AccTile, ipl>"
         instr = {"valu_fp32": VALU_PER_PAIR, "trans": TRANS_PER_PAIR, "per": "pair"}
-    achieved = FLOPS_PER_PAIR * units / kernel_s / 1e12
+    interaction_tf = FLOPS_PER_PAIR * units / kernel_s / 1e12
     executed_tf = executed / kernel_s / 1e12
     evaluation_tf = FLOPS_PER_PAIR * N * N / (mixed["pair_ms_avg"] * 1e-3) / 1e12
     out = {
@@ -790,16 +874,20 @@ def grav2d_workload(md, torch, args):
             "model": "grav2d", "n": N, "eps": EPS, "dt": DT, "precision": "mixed",
             "launch": mixed["launch"], "tiles_ipl_waves_jsplit_jtile": mixed["tiles"],
         },
+        # achieved: the flops the kernel executes (the symmetric form evaluates each pair
+        # once for both particles: 14 flops per evaluation), per launch / its live duration
         "roofline": {
-            "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "bound": "alu", "achieved": round(executed_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(executed_tf / PEAK_FP32_TFLOPS, 4),
             "traffic": traffic_from_profile(mixed["launch"], mixed["tiles"]),
             "kernel": kernel, "kernel_timed_as": mixed["kernel_name"],
             "kernel_ms_avg": round(mixed["kernel_ms_avg"], 4), "kernel_launches": mixed["kernel_launches"],
-            "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": units,
-            # what the kernel executes: the symmetric form evaluates each pair once for both particles
             "executed_flops_per_launch": executed, "pair_evaluations_per_launch": evals,
-            "executed_tflops": round(executed_tf, 3), "frac_executed": round(executed_tf / PEAK_FP32_TFLOPS, 4),
+            "flops_per_evaluation": executed // max(evals, 1),
+            # the metric's convention: 10 flops per interaction (ordered pair) the launch covers
+            "interaction_flops": FLOPS_PER_PAIR, "interactions_per_launch": units,
+            "interaction_equivalent_tflops": round(interaction_tf, 3),
+            "interaction_equivalent_frac": round(interaction_tf / PEAK_FP32_TFLOPS, 4),
             "instr_per_evaluation": instr,
             # SIMD cycles per interaction (pair of the N^2 count) and wavefront lane
             "cycles_per_pair_wave": round(SIMD_CYCLES_PER_S * 64 * kernel_s / units, 2),
@@ -810,6 +898,8 @@ def grav2d_workload(md, torch, args):
         "energy": {
             "mixed_dE_E": mixed["dE_E"], "mixed_dE_over_K0_plus_absV0": mixed["dE_KV"],
             "E0": mixed["E0"],
+            # the accuracy gate: each form's energy against the FP64 oracle's at every report time
+            "oracle_gate": gate if gate is not None else "no oracle golden for this N (tests/golden)",
             # E0 = K0 + V0 nearly cancels for this state (the log potential's mean over the disk
             # offsets the kinetic energy), which inflates |E - E0| / |E0|
             "E0_ill_conditioned": bool(abs(mixed["E0"][2]) < 0.01 * (abs(mixed["E0"][0]) + abs(mixed["E0"][1]))),
@@ -843,15 +933,17 @@ def grav2d_workload(md, torch, args):
             / (abs(fp64["E0"][0]) + abs(fp64["E0"][1])),
             "max_abs_dq": dq, "max_abs_dp": dp,
         }
-        # precision gate: the energy error the mixed form adds to the FP64 run
-        out["energy"]["gate_mixed_vs_fp64_dE_over_E0_le_1e-5"] = bool(prec_err <= 1e-5)
+        # beside the oracle gate: the energy difference the mixed form makes to the GPU's FP64 run
+        out["energy"]["mixed_vs_gpu_fp64_dE_over_E0_le_1e-5"] = bool(prec_err <= 1e-5)
         out["accumulation_variants"] = {
-            "mixed_tile_fold": {"value": round(mixed["gpairs_per_s"], 3), "energy_diff_over_absE0": prec_err,
-                                "gate_le_1e-5": bool(prec_err <= 1e-5)}}
+            "mixed_tile_fold": {"value": round(mixed["gpairs_per_s"], 3), "launch": mixed["launch"],
+                                "energy_diff_over_absE0": prec_err, "gate_le_1e-5": bool(prec_err <= 1e-5)}}
         for name, v in variants.items():
             err = abs(v["E1"][2] - fp64["E1"][2]) / abs(fp64["E0"][2])
             out["accumulation_variants"][name] = {
                 "value": round(v["gpairs_per_s"], 3), "ms_per_step": round(v["ms_per_step"], 4),
+                "launch": v["launch"], "kernel_timed_as": v["kernel_name"],
+                "kernel_ms_avg": round(v["kernel_ms_avg"], 4),
                 "pair_tflops": round(FLOPS_PER_PAIR * N * N / (v["pair_ms_avg"] * 1e-3) / 1e12, 3),
                 "dE_E": v["dE_E"], "energy_diff_over_absE0": err, "gate_le_1e-5": bool(err <= 1e-5),
                 "max_abs_dq_vs_fp64": (v["final_q"] - fp64["final_q"]).abs().max().item()}
@@ -864,7 +956,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 100 grav2d, 50 ring, 1000 hmf)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=["grav2d", "ring", "hmf", "ensemble", "adjoint", "paper_errors",
-                                           "paper_tables"],
+                                           "copy_calibration"],
                     default="grav2d")
     ap.add_argument("--no-fp64", action="store_true", help="grav2d: skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -880,7 +972,7 @@ def main() -> int:
         return 2
     if args.steps is None:
         args.steps = {"grav2d": 100, "ring": 50, "hmf": 1000, "ensemble": 200, "adjoint": 1000,
-                      "paper_errors": 0, "paper_tables": 0}[args.workload]
+                      "paper_errors": 0, "copy_calibration": 3}[args.workload]
 
     import torch
 
@@ -892,7 +984,7 @@ def main() -> int:
     md.load()
     fn = {"grav2d": grav2d_workload, "ring": ring_workload, "hmf": hmf_workload,
           "ensemble": ensemble_workload, "adjoint": adjoint_workload,
-          "paper_errors": paper_errors_workload, "paper_tables": paper_tables_workload}[args.workload]
+          "paper_errors": paper_errors_workload, "copy_calibration": copy_calibration_workload}[args.workload]
     out = fn(md, torch, args)
     hib = out["unit"] not in ("s", "relative")
     line = {"metric": out.pop("metric"), "value": out.pop("value"), "unit": out.pop("unit"), "n_gpus": 1,

@@ -30,8 +30,9 @@
  * Streams and synchronisation
  *   Every call only enqueues kernels on the HIP stream given to md_init (NULL =
  *   the legacy default stream) and returns without waiting; results are ready
- *   once that stream has reached them.  No call allocates or synchronises the
- *   host, so calls may be captured into a HIP graph.
+ *   once that stream has reached them.  No call allocates, and no call but
+ *   md_check and md_timing_end synchronises the host, so the others may be
+ *   captured into a HIP graph.
  *
  * Errors
  *   Every function returns an md_status; nothing is thrown across the ABI.
@@ -89,8 +90,8 @@ enum md_status {
     MD_EINVAL = -1,       /* bad argument (null/misaligned pointer, n < 1, eps <= 0, ...) */
     MD_EDEVICE = -2,      /* a HIP call or kernel launch failed */
     MD_ENOMEM = -3,       /* workspace smaller than md_workspace_bytes, or host alloc failed */
-    MD_ESTATE = -4,       /* reserved: call out of order */
-    MD_ENONFINITE = -5,   /* reserved: a host-read energy was not finite */
+    MD_ESTATE = -4,       /* call out of order (md_step before any md_force, md_check with nothing to check) */
+    MD_ENONFINITE = -5,   /* md_check: the last energies or magnetization were not finite */
     MD_EUNSUPPORTED = -6  /* model/precision combination or tile configuration not built */
 };
 
@@ -98,7 +99,7 @@ enum md_status {
  * Workspace bytes a context for (model, prec, n) needs; 0 for an invalid
  * combination.  The figure covers every tile configuration md_set_tiles
  * accepts for this n, and every launch form the context can take: for
- * MD_GRAV2D and MD_RING with MD_MIXED or MD_FP64 and 2048 <= n <= 1048576 it
+ * MD_GRAV2D and MD_RING with 2048 <= n <= 1048576 it
  * includes the symmetric form's partial slots, 8 d n'^2 / 1024 bytes with n' = n
  * rounded up to a multiple of 1024 (1.07 GB for 2D at n = 262144).
  */
@@ -186,7 +187,7 @@ int md_max_j_split(int64_t n);
  *                     partials per wavefront within 48 KiB / wavefronts
  *                     (MD_EUNSUPPORTED otherwise; md_set_tiles then refuses
  *                     tiles outside that range);
- *   MD_LAUNCH_SYMMETRIC  2D gravity or Ring, MD_MIXED or MD_FP64,
+ *   MD_LAUNCH_SYMMETRIC  2D gravity or Ring, every precision form they accept,
  *                     2048 <= n <= 1048576: each pair is evaluated once and
  *                     added to both particles with opposite signs (the terms of
  *                     the gradient of eq. 3 and of eq. 9 are odd in the pair's
@@ -195,7 +196,12 @@ int md_max_j_split(int64_t n);
  *                     one block takes a tile pair (a, b), a < b, and writes its
  *                     i-side and j-side sums to separate FP64 slots, the blocks
  *                     of the diagonal tiles take every pair of their tile; the
- *                     elementwise kernel adds the slots in a fixed order.  No
+ *                     elementwise kernel adds the slots in a fixed order.  The
+ *                     accumulation of the precision form applies on both sides
+ *                     (MD_MIXED: FP32 runs of at most 256 terms added in FP64;
+ *                     MD_MIXED_KAHAN: compensated FP32 sums over the tile, the
+ *                     compensation moving with the j-side sums; MD_MIXED_PAIRF64:
+ *                     every FP32 term added in FP64).  No
  *                     atomics: bit-reproducible run to run, but the sums are
  *                     grouped differently from the staged form (results agree
  *                     to the precision's rounding, not bit for bit).  The
@@ -203,7 +209,9 @@ int md_max_j_split(int64_t n);
  *                     Ring form gives them zero operands (exact zeros), the 2D
  *                     FP32 form positions at 1e30 (exact zeros), the 2D FP64
  *                     form positions at 1e150 (terms of about 5e-151); 2D
- *                     positions must stay far below both.  Tiles
+ *                     positions must stay far below both.  Every operand refresh
+ *                     (the first stage of md_force and md_step) writes the
+ *                     pads.  Tiles
  *                     (md_set_tiles) do not apply to it.  Ensembles
  *                     (md_batch_init) take tile pairs within each realization:
  *                     Ring with MD_MIXED, MD_MIXED_KAHAN (the compensated sums
@@ -214,7 +222,7 @@ int md_max_j_split(int64_t n);
  *                     built-in tiles there are the fused form's), symmetric
  *                     when it applies and n reaches the model's threshold
  *                     (MD_SYMMETRIC_AUTO_N for 2D gravity; for the Ring
- *                     MD_SYMMETRIC_AUTO_N_RING with MD_MIXED and
+ *                     MD_SYMMETRIC_AUTO_N_RING with the FP32 forms and
  *                     MD_SYMMETRIC_AUTO_N_RING64 with MD_FP64: measured
  *                     crossovers on MI355X), else staged;
  *                     for ensembles, symmetric when it applies and their tile
@@ -242,7 +250,9 @@ int md_force(md_ctx *c, const double *q, double *f);
  * force(q) (from md_force or the previous md_step); on exit q, p hold the state
  * at t + nsteps*dt and f = force(q).  Three force evaluations per step; the
  * force at the end of a step is reused at the start of the next.  dt may be
- * negative (reverse integration).  nsteps = 0 is a no-op.
+ * negative (reverse integration).  nsteps = 0 is a no-op.  MD_ESTATE if the
+ * context has never run md_force (the library cannot check f itself; this
+ * catches the missing first evaluation the step list of Sec. 3 starts from).
  */
 int md_step(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nsteps);
 
@@ -250,16 +260,29 @@ int md_step(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nstep
  * Energies of the state (q, p): out_dev3[0] = K = (1/2) sum p^2,
  * out_dev3[1] = V of eqs. 1-3 (HMF through eq. 5), out_dev3[2] = K + V.
  * Always FP64 arithmetic and FP64 accumulation, whatever `prec` is.
- * out_dev3: device pointer to 3 doubles.
+ * out_dev3: device pointer to 3 doubles.  Also records on the device whether the
+ * three values are finite, for md_check.
  */
 int md_energy(md_ctx *c, const double *q, const double *p, double *out_dev3);
+
+/*
+ * Whether the energies (md_energy) or the magnetization (md_magnetization) most
+ * recently enqueued on this context were finite.  Waits on the host for the
+ * context's stream, so it cannot be captured into a graph.  Returns MD_OK if every
+ * value was finite, MD_ENONFINITE if one was NaN or infinite (the state has left
+ * FP64's range, e.g. after too large a step dt; the relative energy error of
+ * Sec. 4 is then meaningless).  MD_ESTATE if neither call has run on this
+ * context, or if the stream is being captured; MD_EDEVICE if the read fails.
+ */
+int md_check(md_ctx *c);
 
 /*
  * HMF magnetization of eq. 7 at positions q: out_dev2[0] = Mx, out_dev2[1] = My.
  * The sum is reproducible bit for bit and the same one md_force and md_step use:
  * for n <= 2097152 the exact sum of the FP64 block partials (in 64-bit fixed
  * point) rounded once to FP64, above that the block partials added in FP64 in a
- * fixed order.  MD_HMF contexts only.
+ * fixed order.  MD_HMF contexts only.  Records finiteness for md_check as
+ * md_energy does.
  */
 int md_magnetization(md_ctx *c, const double *q, double *out_dev2);
 
@@ -297,7 +320,8 @@ int md_step_vjp(md_ctx *c, const double *q0, const double *p0, double dt, int64_
  * count of doubles: md_record_stage_bytes; e.g. 1.6 GB for the 2D system at
  * n = 32768 over 1000 steps).
  *
- * md_step_record: md_step (same arguments, same results bit for bit) that also
+ * md_step_record: md_step (same arguments, same results bit for bit, the same
+ * MD_ESTATE before any md_force) that also
  * writes the positions after each of its 3 nsteps drifts into `stage` (caller
  * device memory of at least md_record_stage_bytes(c, nsteps) bytes).  HMF needs
  * an MD_FP64 context.
@@ -320,7 +344,9 @@ int md_step_vjp_recorded(md_ctx *c, const double *q0, double dt, int64_t nsteps,
  * dominant kernel is the one that evaluates the pairs: the tile-pair kernel of the
  * symmetric form (not its diagonal tiles), the pair kernel of the staged form, the
  * fused kernel, the HMF stage pass (not the one-block sum after it); for ensembles the tile-pair
- * or the pair kernel.  Launches enqueued while the stream is being captured into
+ * or the pair kernel; in md_hvp and the reverse sweeps, the Ring and 2D
+ * Hessian-vector product's pair kernel (the timed launches of a call sequence are
+ * those of every such kernel it runs, and the name is the last one's).  Launches enqueued while the stream is being captured into
  * a graph are not timed.  It creates 2 max_launches HIP events (host-side
  * objects: no workspace or device memory is taken); calling it again starts over.
  * md_timing_end: waits for the last timed launch, writes the summed duration of

@@ -23,7 +23,9 @@ import torch
 
 from . import md
 
-DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles_cache.json")
+# The cache lives outside the package: $MD_TILES_CACHE, else ~/.cache/mdgpu/tiles_cache.json.
+DEFAULT_CACHE = os.environ.get("MD_TILES_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "mdgpu",
+                                                                  "tiles_cache.json")
 
 
 def _arch() -> str:
@@ -118,6 +120,7 @@ def tune(ctx: md.Context, q: torch.Tensor, configs: Optional[Iterable] = None, r
                 data = json.load(fh)
         data[shape_key(ctx)] = {"tiles": list(best), "ms": table[0][1]}
         tmp = cache + ".tmp"
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         with open(tmp, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
         os.replace(tmp, cache)

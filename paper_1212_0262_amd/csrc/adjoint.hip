@@ -232,6 +232,7 @@ hipError_t hvp_launch(md_ctx *c, const void *qsrc, const void *wsrc, dim3 grid, 
 {
     const int n = (int)c->n, npad = (int)c->npad, jt = c->tiles.jtile;
     const bool fp64 = c->prec == MD_FP64;
+    const int ts = timed_begin(c, c->model == MD_GRAV2D ? "k_hvp_2d" : "k_hvp_ring");
     if (c->model == MD_GRAV2D) {
         const T *x = static_cast<const T *>(qsrc);
         const T *y = x + (fp64 ? n : npad);
@@ -253,7 +254,9 @@ hipError_t hvp_launch(md_ctx *c, const void *qsrc, const void *wsrc, dim3 grid, 
         default: hipLaunchKernelGGL((k_hvp_ring<T, A, 4>), grid, block, 0, c->stream, cs, w, n, npad, jlen, jt, one_eps, c->part); break;
         }
     }
-    return hipGetLastError();
+    const hipError_t err = hipGetLastError();
+    timed_end(c, ts);
+    return err;
 }
 
 }  // namespace

@@ -45,11 +45,12 @@ bool prec_ok(int model, int prec)
 
 bool model_ok(int model) { return model == MD_HMF || model == MD_RING || model == MD_GRAV2D; }
 
-// Contexts that can take the symmetric 2D form (and carry its partial slots).
+// Contexts that can take the symmetric form (and carry its partial slots): Ring
+// and 2D in every precision form they accept.
 bool sym_capable(int model, int prec, int64_t n)
 {
-    return (model == MD_GRAV2D || model == MD_RING) && (prec == MD_MIXED || prec == MD_FP64) && n >= kSymMinN &&
-           n <= kSymMaxN;
+    return (model == MD_GRAV2D || model == MD_RING) && prec >= MD_FP64 && prec <= MD_MIXED_PAIRF64 &&
+           n >= kSymMinN && n <= kSymMaxN;
 }
 
 struct Layout {
@@ -826,8 +827,8 @@ int md_set_launch(md_ctx *c, int mode)
         return fail(c, MD_EINVAL, "md_set_launch: unknown mode %d", mode);
     if (mode == MD_LAUNCH_SYMMETRIC && !sym_ok(c))
         return fail(c, MD_EUNSUPPORTED,
-                    "md_set_launch: the symmetric launch needs a 2D or Ring system, MD_MIXED or MD_FP64 (ensembles: "
-                    "MD_MIXED, MD_MIXED_KAHAN, Ring MD_FP64), %lld <= n <= %lld (ensembles: every N_b <= %lld)",
+                    "md_set_launch: the symmetric launch needs a 2D or Ring system, %lld <= n <= %lld (ensembles: "
+                    "MD_MIXED, MD_MIXED_KAHAN, Ring MD_FP64, every N_b <= %lld)",
                     (long long)kSymMinN, (long long)kSymMaxN, (long long)kSymMaxN);
     if (mode == MD_LAUNCH_FUSED && !fused_ok(c, c->tiles))
         return fail(c, MD_EUNSUPPORTED,
@@ -868,11 +869,13 @@ int md_force(md_ctx *c, const double *q, double *f)
         MD_TRY(launch_hmf_pass(c, 0, HMF_REDUCE, 0.0, 0.0, 0.0, qm, nullptr, nullptr, nullptr, false),
                "force: reduce");
         MD_TRY(launch_hmf_pass(c, 1, HMF_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, nullptr, f, false), "force: store");
+        c->forced = true;
         return MD_OK;
     }
     MD_TRY(update_(c, UPD_PREP, 0.0, 0.0, 0.0, qm, nullptr, nullptr), "force: operands");
     MD_TRY(pair_(c, q), "force: pair kernel");
     MD_TRY(update_(c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, f), "force: combine");
+    c->forced = true;
     return MD_OK;
 }
 
@@ -885,6 +888,7 @@ int md_step(md_ctx *c, double *q, double *p, double *f, double dt, int64_t nstep
     if (!isfinite(dt)) return fail(c, MD_EINVAL, "md_step: dt must be finite");
     if (nsteps < 0) return fail(c, MD_EINVAL, "md_step: nsteps must be >= 0");
     if (nsteps == 0) return MD_OK;
+    if (!c->forced) return fail(c, MD_ESTATE, "md_step: f must hold force(q): call md_force on this context first");
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_step: set device");
     return c->model == MD_HMF ? step_hmf(c, q, p, f, dt, nsteps) : step_pairs(c, q, p, f, dt, nsteps);
@@ -899,6 +903,8 @@ int md_energy(md_ctx *c, const double *q, const double *p, double *out_dev3)
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_energy: set device");
     MD_TRY(c->batch ? batch_energy(c, q, p, out_dev3) : launch_energy(c, q, p, out_dev3), "energy");
+    MD_TRY(launch_finite_flag(c, out_dev3, 3 * (c->batch ? c->batch->nb : 1)), "energy: finiteness");
+    c->checkable = true;
     return MD_OK;
 }
 
@@ -912,6 +918,25 @@ int md_magnetization(md_ctx *c, const double *q, double *out_dev2)
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_magnetization: set device");
     MD_TRY(launch_magnetization(c, q, out_dev2), "magnetization");
+    MD_TRY(launch_finite_flag(c, out_dev2, 2), "magnetization: finiteness");
+    c->checkable = true;
+    return MD_OK;
+}
+
+int md_check(md_ctx *c)
+{
+    if (!c) return MD_EINVAL;
+    c->err.clear();
+    if (!c->checkable) return fail(c, MD_ESTATE, "md_check: no md_energy or md_magnetization on this context yet");
+    DeviceGuard g(c->dev);
+    if (g.err != hipSuccess) return dev_fail(c, g.err, "md_check: set device");
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    MD_TRY(hipStreamIsCapturing(c->stream, &st), "md_check: capture status");
+    if (st != hipStreamCaptureStatusNone) return fail(c, MD_ESTATE, "md_check: the stream is being captured");
+    unsigned flag = 0;
+    MD_TRY(hipMemcpyAsync(&flag, finite_flag(c), sizeof flag, hipMemcpyDeviceToHost, c->stream), "md_check: read");
+    MD_TRY(hipStreamSynchronize(c->stream), "md_check: wait");
+    if (flag) return fail(c, MD_ENONFINITE, "md_check: the last energies or magnetization were not finite");
     return MD_OK;
 }
 
@@ -984,6 +1009,8 @@ int md_step_record(md_ctx *c, double *q, double *p, double *f, double dt, int64_
     if (stage_bytes < md_record_stage_bytes(c, nsteps))
         return fail(c, MD_ENOMEM, "md_step_record: stage buffer needs %zu bytes", md_record_stage_bytes(c, nsteps));
     if (nsteps == 0) return MD_OK;
+    if (!c->forced)
+        return fail(c, MD_ESTATE, "md_step_record: f must hold force(q): call md_force on this context first");
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_step_record: set device");
     const size_t slot = vjp_slot(c);

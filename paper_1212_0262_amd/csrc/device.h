@@ -157,16 +157,17 @@ __device__ __forceinline__ double slot_sum(const double *__restrict__ part, int 
 }
 
 // slot_sum for every coordinate d < D at once: the loads of all coordinates go
-// out together (16 D in flight), each coordinate still added in order of b.
-template <int D>
-__device__ __forceinline__ void slot_sums(const double *__restrict__ part, int S, int npad, int i, double (&s)[D])
+// out together (16 D in flight), each coordinate still added in FP64 in order of b.
+// Slots of FP32 (the symmetric form's MD_MIXED slots) or FP64.
+template <int D, typename SlotT = double>
+__device__ __forceinline__ void slot_sums(const SlotT *__restrict__ part, int S, int npad, int i, double (&s)[D])
 {
     constexpr int U = 16;
 #pragma unroll
     for (int d = 0; d < D; ++d) s[d] = 0.0;
     int b = 0;
     for (; b + U <= S; b += U) {
-        double v[D][U];
+        SlotT v[D][U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -174,11 +175,11 @@ __device__ __forceinline__ void slot_sums(const double *__restrict__ part, int S
 #pragma unroll
         for (int d = 0; d < D; ++d)
 #pragma unroll
-            for (int u = 0; u < U; ++u) s[d] += v[d][u];
+            for (int u = 0; u < U; ++u) s[d] += (double)v[d][u];
     }
     for (; b < S; ++b)
 #pragma unroll
-        for (int d = 0; d < D; ++d) s[d] += part[(size_t)(b * D + d) * npad + i];
+        for (int d = 0; d < D; ++d) s[d] += (double)part[(size_t)(b * D + d) * npad + i];
 }
 
 }  // namespace md

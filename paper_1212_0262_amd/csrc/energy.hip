@@ -93,7 +93,23 @@ __global__ __launch_bounds__(256) void k_energy_finalize(const double *__restric
     }
 }
 
+// flag = 1 if any of v[0 .. count) is not finite, else 0 (one block).
+__global__ __launch_bounds__(256) void k_finite_flag(const double *__restrict__ v, int count,
+                                                     unsigned *__restrict__ flag)
+{
+    int bad = 0;
+    for (int k = threadIdx.x; k < count; k += blockDim.x) bad |= !isfinite(v[k]);
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) *flag = bad ? 1u : 0u;
+}
+
 }  // namespace
+
+hipError_t launch_finite_flag(md_ctx *c, const double *vals, int count)
+{
+    hipLaunchKernelGGL(k_finite_flag, dim3(1), dim3(256), 0, c->stream, vals, count, finite_flag(c));
+    return hipGetLastError();
+}
 
 // Layout of the reduction scratch: [0, kRedSlots/2) potential partials,
 // [kRedSlots/2, kRedSlots/2 + kKinGrid) kinetic partials.

@@ -137,7 +137,8 @@ struct md_ctx {
     float *p32 = nullptr;
     void *fops[2] = {nullptr, nullptr};  // fused stage operands, alternating (n <= kFusedMaxN): [2][npad] of T
     int launch = 0;                      // md_launch: auto / staged / fused / symmetric
-    bool sym_pad = false;                // the symmetric form's pad operands are written
+    bool forced = false;                 // md_force has run (md_step needs f = force(q))
+    bool checkable = false;              // an energy or magnetization has set the finiteness flag
     md::Tiles tiles;
     md::Batch *batch = nullptr;  // non-null for a batched ensemble (owned)
     md::Timing *timing = nullptr;  // non-null while md_timing_begin is on (owned)
@@ -222,6 +223,11 @@ hipError_t launch_adj_update(md_ctx *c, int flags, double h, double h2, double a
                              double *out, const double *pos);
 // energy.hip
 hipError_t launch_energy(md_ctx *c, const double *q, const double *p, double *out3);
+// The finiteness flag (an unsigned in the context scalars): launch_finite_flag sets
+// it to 1 if any of vals[0 .. count) is NaN or infinite, else to 0.
+constexpr int kScalFlag = 16;  // index in c->scal
+inline unsigned *finite_flag(md_ctx *c) { return reinterpret_cast<unsigned *>(c->scal + kScalFlag); }
+hipError_t launch_finite_flag(md_ctx *c, const double *vals, int count);
 hipError_t launch_magnetization(md_ctx *c, const double *q, double *out2);
 
 }  // namespace md

@@ -228,13 +228,16 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 // One launch of k_sym<MODEL, T, A, true> takes every tile pair (a, b), a < b, of
 // a single system (the scheme of sym_tile in pair_terms.h); k_sym<..., false>
 // takes the diagonal tiles (a, a): every ordered pair of the tile, i side only.
-//   i side: the tile's sum goes to slot b of the i particles (FP32: partials over
-//     128 j folded into FP64);
-//   j side: FP32 sum over the 256 i of a wavefront, the 4 wavefronts added in
-//     FP64 in a fixed order at the end of the tile (FP64 form: after every 64-j
-//     block, through a small LDS buffer), into slot a of the j particles.
+//   i side: the tile's sum goes to slot b of the i particles (MD_MIXED: partials
+//     over 128 j folded into FP64);
+//   j side: the sum over the 256 i of a wavefront, the 4 wavefronts added in
+//     FP64 in a fixed order at the end of the tile (MD_MIXED, FP32 wavefront
+//     sums) or after every 64-j block through a small LDS buffer (the other
+//     accumulations), into slot a of the j particles.
 // Each particle thus receives one slot per tile and the update kernel adds them
-// in slot order: a fixed order, no atomics.
+// in FP64 in slot order: a fixed order, no atomics.  The slots of MD_MIXED are
+// FP32 (the tile's sum rounded once: half the bytes the update reads back, for
+// a rounding below that of the FP32 partials themselves); the others are FP64.
 // Pad particles (n .. npad - 1) contribute nothing:
 //   2D FP32: at (1e30, 1e30): r^2 overflows to +inf for any pair with a pad
 //     particle, the reciprocal is 0 and both terms are exactly zero (a pad-pad
@@ -256,16 +259,23 @@ __device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
     b = r + 1 + (t - row0(r));
 }
 
-// r0, r1: the operand rows ([2][npad], padded); part: slots [ntile][D][npad].
+// Slot type of the symmetric form with accumulator A.
+template <typename A>
+using sym_slot_t = std::conditional_t<std::is_same_v<A, AccTile>, float, double>;
+
+// r0, r1: the operand rows ([2][npad], padded); part: slots [ntile][D][npad] of
+// sym_slot_t<A>.
 template <int MODEL, typename T, typename A, bool SYM>
 __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1,
-                                                           int npad, int ntile, T e, double *__restrict__ part)
+                                                           int npad, int ntile, T e, sym_slot_t<A> *__restrict__ part)
 {
-    constexpr bool F32 = sizeof(T) == 4;
+    // JW32 (MD_MIXED): the wavefronts' FP32 j-side sums of the whole tile, added at
+    // its end; otherwise (Kahan, per-pair FP64, FP64) their FP64 values after every
+    // 64-j block (a Kahan sum's value carries its compensation: FP32 would drop it)
+    constexpr bool JW32 = std::is_same_v<A, AccTile>;
     constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
-    // FP32: the wavefronts' j-side sums of the whole tile; FP64: of one 64-j block
-    __shared__ float jw32[SYM && F32 ? kSymWaves : 1][D][SYM && F32 ? kSymTile : 1];
-    __shared__ double jw64[SYM && !F32 ? kSymWaves : 1][D][SYM && !F32 ? kWave : 1];
+    __shared__ float jw32[SYM && JW32 ? kSymWaves : 1][D][SYM && JW32 ? kSymTile : 1];
+    __shared__ double jw64[SYM && !JW32 ? kSymWaves : 1][D][SYM && !JW32 ? kWave : 1];
     int a, b;
     if (SYM) sym_tile_pair(blockIdx.x, ntile, a, b);
     else a = b = blockIdx.x;
@@ -286,7 +296,7 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
             v1 = r1[jl + blk * kWave];
         },
         [&](int blk, int m, A (&sj)[D]) {
-            if constexpr (F32) {
+            if constexpr (JW32) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) jw32[wave][d][blk * kWave + m] = (float)sj[d].get();
             } else {
@@ -298,7 +308,7 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
                     double t = 0.0;
 #pragma unroll
                     for (int w = 0; w < kSymWaves; ++w) t += jw64[w][d][mm];
-                    part[(size_t)(D * a + d) * npad + b * kSymTile + blk * kWave + mm] = t;
+                    part[(size_t)(D * a + d) * npad + b * kSymTile + blk * kWave + mm] = (sym_slot_t<A>)t;
                 }
                 __syncthreads();
             }
@@ -307,8 +317,8 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
 #pragma unroll
     for (int k = 0; k < kSymIpl; ++k)
 #pragma unroll
-        for (int d = 0; d < D; ++d) part[(size_t)(D * b + d) * npad + i0 + k * kWave] = acc[d][k].get();
-    if constexpr (SYM && F32) {
+        for (int d = 0; d < D; ++d) part[(size_t)(D * b + d) * npad + i0 + k * kWave] = (sym_slot_t<A>)acc[d][k].get();
+    if constexpr (SYM && JW32) {
         __syncthreads();
         for (int m = threadIdx.x; m < kSymTile; m += kSymWaves * kWave) {
 #pragma unroll
@@ -316,50 +326,34 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
                 double t = 0.0;
 #pragma unroll
                 for (int w = 0; w < kSymWaves; ++w) t += (double)jw32[w][d][m];
-                part[(size_t)(D * a + d) * npad + b * kSymTile + m] = t;
+                part[(size_t)(D * a + d) * npad + b * kSymTile + m] = (sym_slot_t<A>)t;
             }
         }
     }
 }
 
-template <int MODEL, typename T>
-__global__ void k_fill_pad(T *__restrict__ ops, int n, int npad)
-{
-    const int i = n + blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < npad) {
-        ops[i] = sym_pad<MODEL, T>();
-        ops[npad + i] = sym_pad<MODEL, T>();
-    }
-}
-
-template <int MODEL, typename T>
+// The pads (particles n .. npad - 1) hold sym_pad's operands: every operand refresh
+// (UPD_PREP in k_update) writes them, so they are in place before any pair launch
+// of the same call, also inside a captured graph.
+template <int MODEL, typename T, typename A>
 hipError_t sym_launch(md_ctx *c)
 {
-    const int n = (int)c->n, npad = (int)c->npad, ntile = npad / kSymTile;
-    T *ops = static_cast<T *>(c->ops);
-    if (!c->sym_pad) {  // once per context: the update kernels never write past n
-        if (npad > n) {
-            hipLaunchKernelGGL((k_fill_pad<MODEL, T>), dim3((unsigned)((npad - n + 255) / 256)), dim3(256), 0,
-                               c->stream, ops, n, npad);
-            const hipError_t err = hipGetLastError();
-            if (err != hipSuccess) return err;
-        }
-        c->sym_pad = true;
-    }
+    const int npad = (int)c->npad, ntile = npad / kSymTile;
+    const T *ops = static_cast<const T *>(c->ops);
     const T e = MODEL == MD_GRAV2D ? (T)c->eps : sizeof(T) == 4 ? (T)(2.0 * c->eps) : (T)(1.0 + c->eps);
     const dim3 block(kSymWaves * kWave);
     const int noff = ntile * (ntile - 1) / 2;
-    using A = std::conditional_t<sizeof(T) == 4, AccTile, AccF64>;
+    sym_slot_t<A> *slots = reinterpret_cast<sym_slot_t<A> *>(c->part);
     if (noff > 0) {
         const int ts = timed_begin(c, MODEL == MD_GRAV2D ? "k_sym (2D, tile pairs)" : "k_sym (Ring, tile pairs)");
         hipLaunchKernelGGL((k_sym<MODEL, T, A, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad,
-                           npad, ntile, e, c->part);
+                           npad, ntile, e, slots);
         const hipError_t err = hipGetLastError();
         timed_end(c, ts);
         if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL((k_sym<MODEL, T, A, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad, npad,
-                       ntile, e, c->part);
+                       ntile, e, slots);
     return hipGetLastError();
 }
 
@@ -428,17 +422,38 @@ __device__ __forceinline__ void stage_elem(int d, int i, int n, int npad, double
 // One kick-drift stage, elementwise over particles (eq. 4 and the step list of
 // Sec. 3): f from the pair partials (times the model prefactor), p += kick * f,
 // q += drift * p, then the pair operands of the new q.
-template <int D, int PREP>
-__global__ __launch_bounds__(256) void k_update(const double *__restrict__ part, int S, int n, int npad,
+// The pad operand of particle i in [n, npad) (the symmetric form's padding; the
+// other forms never read past n).
+template <int PREP>
+__device__ __forceinline__ void stage_pad(int i, int npad, void *__restrict__ ops)
+{
+    if (PREP == PREP_CAST32) {
+        static_cast<float *>(ops)[i] = static_cast<float *>(ops)[npad + i] = sym_pad<MD_GRAV2D, float>();
+    } else if (PREP == PREP_COPY64) {
+        static_cast<double *>(ops)[i] = static_cast<double *>(ops)[npad + i] = sym_pad<MD_GRAV2D, double>();
+    } else if (PREP == PREP_HALF32) {
+        static_cast<float *>(ops)[i] = static_cast<float *>(ops)[npad + i] = sym_pad<MD_RING, float>();
+    } else if (PREP == PREP_SINCOS64) {
+        static_cast<double *>(ops)[i] = static_cast<double *>(ops)[npad + i] = sym_pad<MD_RING, double>();
+    }
+}
+
+// part: the pair partials, S slots [S][D][npad] of SlotT (FP32 for the symmetric
+// form's MD_MIXED slots, else FP64).
+template <int D, int PREP, typename SlotT>
+__global__ __launch_bounds__(256) void k_update(const SlotT *__restrict__ part, int S, int n, int npad,
                                                 double pref, double *__restrict__ f,
                                                 double *__restrict__ p, double *__restrict__ q,
                                                 void *__restrict__ ops, double kick1, double kick2,
                                                 double drift, int flags, double *__restrict__ snap)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n) {  // with UPD_PREP the grid covers the pads too
+        if ((flags & UPD_PREP) && i < npad) stage_pad<PREP>(i, npad, ops);
+        return;
+    }
     double fs[D];
-    if (flags & UPD_F_FROM_PART) slot_sums<D>(part, S, npad, i, fs);
+    if (flags & UPD_F_FROM_PART) slot_sums<D, SlotT>(part, S, npad, i, fs);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         double fd = 0.0;
@@ -609,15 +624,25 @@ hipError_t update(md_ctx *c, int flags, double kick1, double kick2, double drift
                   double *f, double *snap, void *ops, bool fused)
 {
     const int n = (int)c->n;
-    const dim3 block(256), grid((unsigned)((n + 255) / 256));
     const double pref = force_prefactor(c->model, c->prec, n);
-    const int S = !fused && launch_form(c) == MD_LAUNCH_SYMMETRIC ? (int)(c->npad / kSymTile) : c->tiles.jsplit;
+    const bool sym = !fused && launch_form(c) == MD_LAUNCH_SYMMETRIC;
+    const int S = sym ? (int)(c->npad / kSymTile) : c->tiles.jsplit;
+    const bool slots32 = sym && c->prec == MD_MIXED;  // the symmetric form's FP32 slots (sym_slot_t)
     const int npad = (int)c->npad;
     const int pk = prep_kind(c, fused);
     if (pk == PREP_NONE) flags &= ~UPD_PREP;
-#define MD_UPD(D_, P_)                                                                                    \
-    hipLaunchKernelGGL((k_update<D_, P_>), grid, block, 0, c->stream, c->part, S, n, npad, pref, f, p, q, \
-                       ops, kick1, kick2, drift, flags, snap)
+    const int nthreads = (flags & UPD_PREP) ? npad : n;  // an operand refresh also writes the pads
+    const dim3 block(256), grid((unsigned)((nthreads + 255) / 256));
+#define MD_UPD(D_, P_)                                                                                              \
+    do {                                                                                                            \
+        if (slots32)                                                                                                \
+            hipLaunchKernelGGL((k_update<D_, P_, float>), grid, block, 0, c->stream,                                \
+                               reinterpret_cast<const float *>(c->part), S, n, npad, pref, f, p, q, ops, kick1, kick2, \
+                               drift, flags, snap);                                                                 \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_update<D_, P_, double>), grid, block, 0, c->stream, c->part, S, n, npad, pref, f, \
+                               p, q, ops, kick1, kick2, drift, flags, snap);                                        \
+    } while (0)
     if (c->model == MD_GRAV2D) {
         if (pk == PREP_CAST32) MD_UPD(2, PREP_CAST32);
         else if (pk == PREP_COPY64) MD_UPD(2, PREP_COPY64);
@@ -763,9 +788,20 @@ hipError_t launch_fused(md_ctx *c, int flags, double kick1, double kick2, double
 hipError_t launch_pair(md_ctx *c, const double *q)
 {
     if (launch_form(c) == MD_LAUNCH_SYMMETRIC) {
-        if (c->model == MD_GRAV2D)
-            return c->prec == MD_FP64 ? sym_launch<MD_GRAV2D, double>(c) : sym_launch<MD_GRAV2D, float>(c);
-        return c->prec == MD_FP64 ? sym_launch<MD_RING, double>(c) : sym_launch<MD_RING, float>(c);
+        if (c->model == MD_GRAV2D) {
+            switch (c->prec) {
+            case MD_FP64: return sym_launch<MD_GRAV2D, double, AccF64>(c);
+            case MD_MIXED: return sym_launch<MD_GRAV2D, float, AccTile>(c);
+            case MD_MIXED_KAHAN: return sym_launch<MD_GRAV2D, float, AccKahan>(c);
+            default: return sym_launch<MD_GRAV2D, float, AccPair64>(c);
+            }
+        }
+        switch (c->prec) {
+        case MD_FP64: return sym_launch<MD_RING, double, AccF64>(c);
+        case MD_MIXED: return sym_launch<MD_RING, float, AccTile>(c);
+        case MD_MIXED_KAHAN: return sym_launch<MD_RING, float, AccKahan>(c);
+        default: return sym_launch<MD_RING, float, AccPair64>(c);
+        }
     }
     const Tiles &t = c->tiles;
     const int n = (int)c->n;

@@ -53,6 +53,7 @@ SIGNATURES = {
     "md_step": (_I, [_V, _V, _V, _V, _D, _I64]),
     "md_energy": (_I, [_V, _V, _V, _V]),
     "md_magnetization": (_I, [_V, _V, _V]),
+    "md_check": (_I, [_V]),
     "md_hvp": (_I, [_V, _V, _V, _V]),
     "md_vjp_stage_bytes": (_SZ, [_V, _I64]),
     "md_step_vjp": (_I, [_V, _V, _V, _D, _I64, _V, _V, _V, _SZ]),
@@ -249,22 +250,36 @@ def md_step(ctx: Context, q: torch.Tensor, p: torch.Tensor, f: torch.Tensor, dt:
                               float(dt), int(nsteps)), "md_step")
 
 
-def md_energy(ctx: Context, q: torch.Tensor, p: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """{K, V, E} as a device float64 tensor of 3 ([nb, 3] for a batch context);
-    read it on the host to synchronise."""
+def md_check(ctx: Context) -> None:
+    """Waits for the context's stream; raises MDError(ENONFINITE) if the energies or
+    magnetization last written were not finite."""
+    ctx._check(load().md_check(ctx.handle), "md_check")
+
+
+def md_energy(ctx: Context, q: torch.Tensor, p: torch.Tensor, out: Optional[torch.Tensor] = None,
+              check: bool = True) -> torch.Tensor:
+    """{K, V, E} as a device float64 tensor of 3 ([nb, 3] for a batch context).
+    With check (the default) it waits for the stream and raises MDError(ENONFINITE)
+    if a value is not finite (md_check); pass check=False under graph capture."""
     nb = getattr(ctx, "nb", 1)
     if out is None:
         out = torch.empty((nb, 3) if nb > 1 or hasattr(ctx, "nb") else 3, dtype=torch.float64, device=q.device)
     if out.dtype != torch.float64 or out.numel() < 3 * nb or out.device.type != "cuda" or not out.is_contiguous():
         raise ValueError(f"out: expected a contiguous device float64 tensor of at least {3 * nb} elements")
     ctx._check(load().md_energy(ctx.handle, ctx._arr(q, "q"), ctx._arr(p, "p"), out.data_ptr()), "md_energy")
+    if check:
+        md_check(ctx)
     return out
 
 
-def md_magnetization(ctx: Context, q: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+def md_magnetization(ctx: Context, q: torch.Tensor, out: Optional[torch.Tensor] = None,
+                     check: bool = True) -> torch.Tensor:
+    """(Mx, My) as a device float64 tensor of 2; check as md_energy."""
     if out is None:
         out = torch.empty(2, dtype=torch.float64, device=q.device)
     ctx._check(load().md_magnetization(ctx.handle, ctx._arr(q, "q"), out.data_ptr()), "md_magnetization")
+    if check:
+        md_check(ctx)
     return out
 
 

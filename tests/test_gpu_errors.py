@@ -1,0 +1,177 @@
+"""Error semantics of the C ABI on a device context, and the symmetric form's pad
+operands under graph capture.
+
+  * MD_ESTATE: md_step / md_step_record on a context that never ran md_force
+    (the step list of Sec. 3 starts from the force at the initial positions);
+    md_check before any energy or magnetization, or while the stream is being
+    captured.  A refused call changes nothing.
+  * MD_ENONFINITE: md_check after md_energy / md_magnetization of a state holding
+    a NaN or an infinity (set on the host: no device fault is involved); the flag
+    follows the latest call, so a finite energy afterwards reads OK again.
+  * The pads of the symmetric form (particles n .. npad - 1, whose terms vanish)
+    are written by every operand refresh: a context whose first symmetric call is
+    captured into a graph, never replayed, and then run eagerly gives the
+    oracle's forces from a workspace that starts as NaN bytes.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_0262_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+md = pytest.importorskip("paper_1212_0262_amd.md")
+from gpu_helpers import dev, host, rel_inf  # noqa: E402
+from test_gpu_parity import force_tol  # noqa: E402
+
+GRAV2D, RING, HMF = md.GRAV2D, md.RING, md.HMF
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_threads():
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def _nan_workspace(model, prec, n):
+    """A workspace whose every byte is 0xFF: NaN as FP32 and as FP64."""
+    return torch.full((md.md_workspace_bytes(model, prec, n),), 255, dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.parametrize("model,prec,eps", [(GRAV2D, md.MIXED, 1e-3), (RING, md.FP64, 0.01), (HMF, md.FP64, 0.0)])
+def test_step_before_force_is_refused(model, prec, eps):
+    n = 3000
+    q0, p0 = inputs.uniform_state(model if model != HMF else RING, n, seed=5)
+    ctx = md.md_init(model, prec, n, eps)
+    q, p = dev(q0), dev(p0)
+    f = torch.zeros_like(q)
+    lib = md.load()
+    assert lib.md_step(ctx.handle, q.data_ptr(), p.data_ptr(), f.data_ptr(), 0.01, 2) == md.ESTATE
+    assert b"md_force" in lib.md_last_error(ctx.handle)
+    stage = torch.empty(md.md_record_stage_bytes(ctx, 2), dtype=torch.uint8, device="cuda")
+    assert lib.md_step_record(ctx.handle, q.data_ptr(), p.data_ptr(), f.data_ptr(), 0.01, 2, stage.data_ptr(),
+                              stage.numel()) == md.ESTATE
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(q), q0)  # refused before anything was enqueued
+    np.testing.assert_array_equal(host(p), p0)
+    md.md_step(ctx, q, p, f, 0.01, 0)  # zero steps: a no-op, accepted
+    md.md_force(ctx, q, f)
+    md.md_step(ctx, q, p, f, 0.01, 2)
+    assert np.all(np.isfinite(host(q)))
+    ctx.close()
+
+
+def test_check_states():
+    lib = md.load()
+    assert lib.md_check(None) == md.EINVAL
+    n = 2000
+    q0, p0 = inputs.grav2d_disk(n, seed=8)
+    ctx = md.md_init(GRAV2D, md.MIXED, n, 1e-3)
+    assert lib.md_check(ctx.handle) == md.ESTATE  # nothing written yet
+    q, p = dev(q0), dev(p0)
+    e = md.md_energy(ctx, q, p)  # checks: finite
+    assert np.all(np.isfinite(host(e)))
+    assert lib.md_check(ctx.handle) == md.OK
+    # while the stream is being captured md_check cannot wait: refused
+    s = torch.cuda.Stream()
+    md.md_set_stream(ctx, s)
+    f = torch.empty_like(q)
+    with torch.cuda.stream(s):
+        md.md_force(ctx, q, f)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        md.md_force(ctx, q, f)
+        st = lib.md_check(ctx.handle)
+    assert st == md.ESTATE
+    g.replay()
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+@pytest.mark.parametrize("model,prec,eps,where", [
+    (GRAV2D, md.MIXED, 1e-3, "q"), (GRAV2D, md.FP64, 1e-3, "p"), (RING, md.MIXED_KAHAN, 0.01, "q"),
+    (RING, md.FP64, 0.01, "p"), (HMF, md.FP64, 0.0, "q"), (HMF, md.MIXED_F32STATE, 0.0, "p")])
+def test_nonfinite_energy_is_reported(model, prec, eps, where):
+    n = 1500
+    if model == GRAV2D:
+        q0, p0 = inputs.grav2d_disk(n, seed=9)
+    else:
+        q0, p0 = inputs.ring_waterbag(n, seed=9)
+    ctx = md.md_init(model, prec, n, eps)
+    bad_q, bad_p = q0.copy(), p0.copy()
+    if where == "q":
+        bad_q[0, 17] = np.nan
+    else:
+        bad_p[-1, 400] = np.inf
+    with pytest.raises(md.MDError) as ei:
+        md.md_energy(ctx, dev(bad_q), dev(bad_p))
+    assert ei.value.status == md.ENONFINITE
+    # the flag follows the latest call
+    e = host(md.md_energy(ctx, dev(q0), dev(p0)))
+    eo = oracle.energy(model, q0, p0, eps)
+    assert np.abs(e - eo).max() <= 1e-12 * (abs(eo[0]) + abs(eo[1]) + (n / 2 if model == HMF else 0))
+    out = md.md_energy(ctx, dev(bad_q), dev(bad_p), check=False)  # unchecked: the values come back as they are
+    assert not np.all(np.isfinite(host(out)))
+    assert md.load().md_check(ctx.handle) == md.ENONFINITE
+    ctx.close()
+
+
+def test_nonfinite_magnetization_and_batch_energy():
+    n = 4000
+    q0, p0 = inputs.hmf_waterbag(n, seed=10)
+    ctx = md.md_init(HMF, md.FP64, n, 0.0)
+    bad = q0.copy()
+    bad[0, 3] = np.inf
+    with pytest.raises(md.MDError) as ei:
+        md.md_magnetization(ctx, dev(bad))
+    assert ei.value.status == md.ENONFINITE
+    m = host(md.md_magnetization(ctx, dev(q0)))
+    assert np.abs(m - np.array(oracle.magnetization(q0))).max() < 1e-14
+    ctx.close()
+    # ensembles: one realization's NaN is reported for the whole call
+    sizes = [700, 1300, 900]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    q, p = inputs.ring_waterbag(int(off[-1]), seed=11)
+    b = md.md_batch_init(RING, md.MIXED_KAHAN, off, 0.01)
+    md.md_energy(b, dev(q), dev(p))
+    q[0, off[2] + 5] = np.nan
+    with pytest.raises(md.MDError) as ei:
+        md.md_energy(b, dev(q), dev(p))
+    assert ei.value.status == md.ENONFINITE
+    b.close()
+
+
+@pytest.mark.parametrize("model,prec,eps", [(GRAV2D, md.MIXED, 1e-3), (GRAV2D, md.FP64, 1e-3),
+                                            (RING, md.MIXED, 0.01), (RING, md.FP64, 0.01)])
+def test_symmetric_pads_when_first_call_is_captured(model, prec, eps):
+    """Regression: the pads were once written by the first symmetric launch only,
+    so a first call made under capture left them in the graph alone."""
+    n = 5000  # 5 tiles, the last one ragged (120 pads)
+    q0, p0 = inputs.grav2d_disk(n, seed=12) if model == GRAV2D else inputs.ring_waterbag(n, seed=12)
+    ctx = md.md_init(model, prec, n, eps, workspace=_nan_workspace(model, prec, n))
+    md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
+    s = torch.cuda.Stream()
+    md.md_set_stream(ctx, s)
+    q = dev(q0)
+    fg = torch.empty_like(q)
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):  # the context's first call, captured and not replayed yet
+        md.md_force(ctx, q, fg)
+    f = torch.empty_like(q)
+    with torch.cuda.stream(s):
+        md.md_force(ctx, q, f)
+    s.synchronize()
+    fh = host(f)
+    assert np.all(np.isfinite(fh))
+    assert rel_inf(fh, oracle.force(model, q0, eps)) < force_tol(model, prec, n)
+    g.replay()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(fg), fh)
+    ctx.close()

@@ -41,6 +41,11 @@ FORCE_TOL = {
 SIZES = [1, 2, 63, 64, 65, 255, 257, 1000, 2048, 3001]
 
 
+def force_tol(model, prec, n=None):
+    """Force tolerance of (model, precision) at n particles."""
+    return FORCE_TOL[(model, prec)]
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _oracle_threads():
     oracle.set_threads(min(16, os.cpu_count() or 1))

@@ -32,7 +32,7 @@ from test_gpu_parity import FORCE_TOL  # noqa: E402
 GRAV2D, RING = md.GRAV2D, md.RING
 EPS = 1e-3
 TOL = FORCE_TOL[(GRAV2D, md.MIXED)]
-PRECS = [md.MIXED, md.FP64]
+PRECS = [md.MIXED, md.MIXED_KAHAN, md.MIXED_PAIRF64, md.FP64]
 MODELS = [(GRAV2D, 1e-3), (RING, 0.01)]
 
 
@@ -120,7 +120,7 @@ def test_symmetric_repeatable_and_momentum_free(prec, model, eps):
     total = np.abs(fh.sum(axis=1)).max()
     scale = np.abs(fh).sum(axis=1).max()
     print(f"symmetric model={model} prec={prec} |sum f| = {total:.3e} of sum |f| = {scale:.3e}")
-    assert total < (1e-6 if prec == md.MIXED else 1e-13) * scale
+    assert total < (1e-13 if prec == md.FP64 else 1e-6) * scale
     ctx.close()
 
 
@@ -144,7 +144,7 @@ def test_symmetric_trajectory_matches_oracle(prec, model, eps, dt):
     eo = oracle.energy(model, qo, po, eps)
     de = abs(eg[2] - eo[2]) / (abs(e0[0]) + abs(e0[1]))
     print(f"symmetric trajectory model={model} prec={prec}: max|dq|={eq:.3e} max|dp|={ep:.3e} energy diff={de:.3e}")
-    if prec == md.MIXED:
+    if prec != md.FP64:
         assert eq < 1e-5 and ep < 1e-4 and de < 1e-5
     else:  # the FP64 trajectory tolerance of the staged form
         assert eq < 1e-11 and ep < 1e-9 and de < 1e-12
@@ -192,9 +192,17 @@ def test_launch_form_and_refusals():
     assert md.md_get_launch(big) == md.LAUNCH_STAGED
     md.md_set_launch(big, md.LAUNCH_AUTO)
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
-    for model, prec, n in [(GRAV2D, md.MIXED_KAHAN, 50_000), (GRAV2D, md.MIXED_PAIRF64, 50_000),
-                           (RING, md.MIXED_KAHAN, 50_000), (RING, md.MIXED_PAIRF64, 50_000),
-                           (GRAV2D, md.MIXED, 2047), (GRAV2D, md.FP64, 2047), (RING, md.FP64, 2047),
+    # every FP32 accumulation takes the form (the Ring FP32 forms share one threshold)
+    for model, prec, n0 in [(GRAV2D, md.MIXED_KAHAN, md.SYMMETRIC_AUTO_N),
+                            (GRAV2D, md.MIXED_PAIRF64, md.SYMMETRIC_AUTO_N),
+                            (RING, md.MIXED_KAHAN, md.SYMMETRIC_AUTO_N_RING),
+                            (RING, md.MIXED_PAIRF64, md.SYMMETRIC_AUTO_N_RING)]:
+        for n, form in ((n0, md.LAUNCH_SYMMETRIC), (n0 - 1, md.LAUNCH_STAGED)):
+            ctx = md.md_init(model, prec, n, EPS)
+            assert md.md_get_launch(ctx) == form, (model, prec, n)
+            ctx.close()
+    for model, prec, n in [(GRAV2D, md.MIXED, 2047), (GRAV2D, md.FP64, 2047), (RING, md.FP64, 2047),
+                           (RING, md.MIXED_KAHAN, 2047), (GRAV2D, md.MIXED_PAIRF64, 2047),
                            (GRAV2D, md.MIXED, (1 << 20) + 1), (RING, md.MIXED, (1 << 20) + 1)]:
         ctx = md.md_init(model, prec, n, EPS)
         assert md.md_get_launch(ctx) != md.LAUNCH_SYMMETRIC
@@ -406,3 +414,44 @@ def test_random_symmetric_ensembles_match_oracle(prec, sizes, seed):
             assert np.all(f[:, sl] == 0.0)
         else:
             assert rel_inf(f[:, sl], oracle.force(RING, q[:, sl], 0.01)) < tol, (b, n)
+
+
+# ------------------------------------------------------- coincident angles --
+
+def test_ring_fp32_symmetric_coincident_angles():
+    """Ring FP32 forms, symmetric launch: a tile pair forms the half-angle
+    numerator a = 2 sin(d/2) as one product and one FMA (one rounding fewer than
+    the staged form's two rounded products, which make it exactly antisymmetric).
+    For two particles at exactly the same angle in different tiles a is then the
+    rounding error of the product A B, |a| <= 2^-24 |A B|, instead of 0.  The term
+    a b r'^3, with b = A^2 + B^2 = 2 and r' = (a^2 + 2 eps)^{-1/2}, is then at most
+    2^-24 |A B| b (2 eps)^{-3/2}; it is the same for every such pair, added with
+    + on the lower tile's particle and - on the higher one's, so the force
+    (prefactor 1/(2N)) on a particle of an all-equal state, which should vanish,
+    is at most (N - 1)/(2N) times that.  The staged form gives exactly 0 there.  A waterbag state with angles duplicated across tiles still
+    meets the parity tolerance."""
+    n, eps = 40_960, 0.01
+    th = 0.7
+    A = np.float32(np.sqrt(2.0) * np.sin(th / 2))
+    B = np.float32(np.sqrt(2.0) * np.cos(th / 2))
+    b = float(A) ** 2 + float(B) ** 2
+    bound = (n - 1) / (2 * n) * 2.0 ** -24 * abs(float(A) * float(B)) * b * (2 * eps) ** -1.5
+    q = np.full((1, n), th)
+    for prec in (md.MIXED, md.MIXED_KAHAN, md.MIXED_PAIRF64):
+        fs = _force(q, md.LAUNCH_SYMMETRIC, prec, RING, eps)
+        ft = _force(q, md.LAUNCH_STAGED, prec, RING, eps)
+        print(f"all-equal state prec={prec}: max |f| symmetric {np.abs(fs).max():.3e} (bound {bound:.3e}), "
+              f"staged {np.abs(ft).max():.1e}")
+        assert np.all(ft == 0.0)
+        assert np.abs(fs).max() <= 1.01 * bound
+    # a waterbag state where every particle of tile 0 reappears in tiles 5, 17 and 39
+    q, _ = inputs.ring_waterbag(n, seed=19)
+    for t in (5, 17, 39):
+        q[0, t * 1024:(t + 1) * 1024] = q[0, :1024]
+    rows = np.concatenate([np.arange(0, 1024, 97), np.arange(5 * 1024, 6 * 1024, 101), [n - 1]])
+    fo = oracle.force_rows(RING, q, rows, eps)
+    for prec in (md.MIXED, md.MIXED_KAHAN):
+        fs = _force(q, md.LAUNCH_SYMMETRIC, prec, RING, eps)
+        err = rel_inf(fs[:, rows], fo)
+        print(f"duplicated angles prec={prec}: rel_err={err:.3e}")
+        assert err < FORCE_TOL[(RING, prec)], err
