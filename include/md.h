@@ -194,7 +194,8 @@ int md_max_j_split(int64_t n);
  *                     difference), which halves the pair evaluations of the
  *                     all-pairs sum.  The particles are cut into tiles of 1024;
  *                     one block takes a tile pair (a, b), a < b, and writes its
- *                     i-side and j-side sums to separate FP64 slots, the blocks
+ *                     i-side and j-side sums to separate slots (FP32 for
+ *                     MD_MIXED, FP64 otherwise), the blocks
  *                     of the diagonal tiles take every pair of their tile; the
  *                     elementwise kernel adds the slots in a fixed order.  The
  *                     accumulation of the precision form applies on both sides
@@ -282,7 +283,8 @@ int md_check(md_ctx *c);
  * for n <= 2097152 the exact sum of the FP64 block partials (in 64-bit fixed
  * point) rounded once to FP64, above that the block partials added in FP64 in a
  * fixed order.  MD_HMF contexts only.  Records finiteness for md_check as
- * md_energy does.
+ * md_energy does, judged on the FP64 block partials (a NaN cannot pass through
+ * the fixed-point sum, so the output alone would not show it).
  */
 int md_magnetization(md_ctx *c, const double *q, double *out_dev2);
 

@@ -918,7 +918,10 @@ int md_magnetization(md_ctx *c, const double *q, double *out_dev2)
     DeviceGuard g(c->dev);
     if (g.err != hipSuccess) return dev_fail(c, g.err, "md_magnetization: set device");
     MD_TRY(launch_magnetization(c, q, out_dev2), "magnetization");
-    MD_TRY(launch_finite_flag(c, out_dev2, 2), "magnetization: finiteness");
+    // M is finite exactly when the pass's FP64 block partials are: the fixed-point
+    // sums of small grids turn a NaN partial into some finite integer, so the
+    // partials, not the output, decide
+    MD_TRY(launch_finite_flag(c, hmf_partials(c), 2 * hmf_grid(c->n)), "magnetization: finiteness");
     c->checkable = true;
     return MD_OK;
 }
