@@ -4,14 +4,10 @@ the final kinetic energy (autograd.kinetic_energy_gradient) against central fini
 differences of the GPU's own FP64 forward map.
 
 Tolerances (max-norm relative to the largest oracle value):
-  * FP64 products: 1e-10 -- only the summation order and the refined reciprocal
-    differ from the oracle; the Hessian terms cancel more than the force terms.
-  * Mixed 2D products: 1e-4 -- FP32 positions move dx by up to 6e-8, i.e. up to
-    2e-6 relative for the closest pairs (|r| ~ sqrt(eps)), amplified by the
-    1/s^2 term; the vector w is rounded to FP32 as well.
-  * Mixed Ring products: 3e-5 -- half-angle operands (as the force): u = 1 - cos d
-    + eps is formed with an error proportional to |d| and enters as u^{-5/2};
-    measured 2e-7 to 1.3e-6.
+  * Hessian-vector products: tests/tolerances.py (FP64 1e-13; FP32 forms 2e-5
+    for 2D, whose 1/s^2 term doubles the sensitivity to the FP32 positions and
+    whose vector w is rounded to FP32 as well, and 1e-5 for Ring, whose
+    half-angle u = 1 - cos d + eps enters as u^{-5/2}).
   * FP64 reverse sweeps: 1e-9 (10 steps of products and axpys).
   * HMF products: 1e-11 -- the mean-field form (eqs. 6, 7) reorders an O(N) sum of
     O(1) terms against the oracle's pair sum; both are FP64.
@@ -30,10 +26,9 @@ torch = pytest.importorskip("torch")
 md = pytest.importorskip("paper_1212_0262_amd.md")
 from paper_1212_0262_amd import autograd as mdgrad  # noqa: E402
 from gpu_helpers import dev, host, rel_inf  # noqa: E402
+from tolerances import check, hvp_tol  # noqa: E402
 
 HMF, RING, GRAV2D = md.HMF, md.RING, md.GRAV2D
-HVP_TOL = {(GRAV2D, md.FP64): 1e-10, (RING, md.FP64): 1e-10, (GRAV2D, md.MIXED): 1e-4, (RING, md.MIXED): 3e-5,
-           (GRAV2D, md.MIXED_KAHAN): 1e-4, (RING, md.MIXED_KAHAN): 3e-5}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -60,9 +55,7 @@ def test_hvp_matches_oracle(model, eps, prec, n):
     if n == 1:
         assert np.all(hg == 0.0)
         return
-    err = rel_inf(hg, ho)
-    print(f"hvp model={model} prec={prec} n={n} rel_err={err:.3e}")
-    assert err < HVP_TOL[(model, prec)], err
+    check(f"hvp model={model} prec={prec} n={n}", rel_inf(hg, ho), hvp_tol(model, prec))
 
 
 @pytest.mark.parametrize("n", [1, 2, 65, 1001, 5003])

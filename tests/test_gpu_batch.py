@@ -2,9 +2,9 @@
 ensemble against the FP64 oracle run on that realization alone, and against the
 single-system path of the library.
 
-Tolerances are those of the single-system tests (test_gpu_parity.py), since each
-realization is the same computation: FP64 forces 5e-12, mixed 2D 2e-5, mixed
-Ring 1e-5 (relative to max |f| of the realization); energies 1e-12 of K + |V|.
+Force tolerances are those of the single-system tests (tests/tolerances.py), since
+each realization is the same computation, relative to max |f| of the
+realization; energies 1e-12 of K + |V|.
 """
 import os
 
@@ -19,10 +19,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 md = pytest.importorskip("paper_1212_0262_amd.md")
 from gpu_helpers import dev, host, rel_inf  # noqa: E402
+from tolerances import check, force_tol  # noqa: E402
 
 RING, GRAV2D = md.RING, md.GRAV2D
-FORCE_TOL = {md.FP64: 5e-12, md.MIXED: {GRAV2D: 2e-5, RING: 1e-5}, md.MIXED_KAHAN: {GRAV2D: 2e-5, RING: 1e-5},
-             md.MIXED_PAIRF64: {GRAV2D: 2e-5, RING: 1e-5}}
 SIZES = [1, 2, 63, 65, 257, 1000, 3001]
 
 
@@ -30,11 +29,6 @@ SIZES = [1, 2, 63, 65, 257, 1000, 3001]
 def _oracle_threads():
     oracle.set_threads(min(16, os.cpu_count() or 1))
     yield
-
-
-def tol(prec, model):
-    t = FORCE_TOL[prec]
-    return t if isinstance(t, float) else t[model]
 
 
 def ensemble(model, sizes, seed):
@@ -71,7 +65,7 @@ def test_batch_force_matches_oracle_per_realization(model, eps, prec):
         if SIZES[b] == 1:
             assert np.all(fg[b] == 0.0)
             continue
-        assert rel_inf(fg[b], fo) < tol(prec, model), (b, SIZES[b])
+        check(f"ensemble model={model} prec={prec} N_b={SIZES[b]}", rel_inf(fg[b], fo), force_tol(model, prec, SIZES[b]))
 
 
 @pytest.mark.parametrize("model,eps", [(RING, 0.01), (GRAV2D, 1e-3)])
@@ -159,7 +153,8 @@ def test_ensemble_config_full_size():
     order = np.argsort(sizes)
     for b in order[-8:]:
         fo = oracle.force(RING, q[:, off[b]:off[b + 1]], 0.01)
-        assert rel_inf(fg[b], fo) < tol(md.MIXED_KAHAN, RING), b
+        check(f"ensemble workload realization {b} N_b={sizes[b]}", rel_inf(fg[b], fo),
+              force_tol(RING, md.MIXED_KAHAN, int(sizes[b])))
     md.md_step(ctx, qd, pd, f, 0.05, 2)
     qg, pg = split(host(qd), off), split(host(pd), off)
     for b in order[:8]:

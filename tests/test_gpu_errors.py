@@ -27,7 +27,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 md = pytest.importorskip("paper_1212_0262_amd.md")
 from gpu_helpers import dev, host, rel_inf  # noqa: E402
-from test_gpu_parity import force_tol  # noqa: E402
+from tolerances import force_tol  # noqa: E402
 
 GRAV2D, RING, HMF = md.GRAV2D, md.RING, md.HMF
 

@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 md = pytest.importorskip("paper_1212_0262_amd.md")
 from gpu_helpers import dev, host, rel_inf  # noqa: E402
-from test_gpu_parity import FORCE_TOL  # noqa: E402
+from tolerances import check, force_tol  # noqa: E402
 
 HMF, RING, GRAV2D = md.HMF, md.RING, md.GRAV2D
 MAX_HMF_N = 1 << 30
@@ -82,9 +82,7 @@ def test_grav2d_mixed_force_at_the_maximum_size():
     rows = np.sort(np.random.default_rng(93).choice(n, size=16, replace=False))
     fo = oracle.force_rows(GRAV2D, q0, rows, eps)
     fg = host(f)[:, rows]
-    err = rel_inf(fg, fo)
-    print(f"grav2d mixed n=2^23 sampled-row rel_err={err:.3e}")
-    assert err < FORCE_TOL[(GRAV2D, md.MIXED)], err
+    check("grav2d mixed n=2^23 sampled rows", rel_inf(fg, fo), force_tol(GRAV2D, md.MIXED, n))
     ctx.close()
 
 
@@ -101,9 +99,7 @@ def test_ensemble_at_the_maximum_total():
     fg = host(f)
     for b in (0, nb // 2, nb - 1):
         fo = oracle.force(RING, members[b][0], eps)
-        err = rel_inf(fg[:, b * nper:(b + 1) * nper], fo)
-        print(f"ensemble member {b} rel_err={err:.3e}")
-        assert err < FORCE_TOL[(RING, md.MIXED_KAHAN)], err
+        check(f"ensemble member {b}", rel_inf(fg[:, b * nper:(b + 1) * nper], fo), force_tol(RING, md.MIXED_KAHAN, nper))
     with pytest.raises(md.MDError):
         md.md_batch_init(RING, md.MIXED_KAHAN, np.append(offsets, offsets[-1] + 1), eps)
     ctx.close()

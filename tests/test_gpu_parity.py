@@ -1,19 +1,9 @@
 """GPU parity: libmd (through its C ABI) against the FP64 CPU oracle, element by
 element, on the same seeded inputs.
 
-Tolerances (max-norm, relative to the largest oracle value unless stated):
-  * FP64 forces: 5e-12.  Each pair term is formed to a few ulp (the reciprocal
-    and reciprocal square root are Newton-refined to FP64), and only the
-    summation order differs from the oracle: n u kappa with n <= 4096,
-    u = 1.1e-16 and a cancellation factor kappa of a few.
-  * Mixed 2D forces: 2e-5.  Positions are rounded to FP32 (|dr| <= 6e-8 for
-    |r| <= 1); the force changes by the tidal tensor times dr, about
-    log(1/eps) dr relative, plus FP32 rounding of the pair terms and of the
-    j-tile partial sums (128 terms).
-  * Mixed Ring forces: 1e-5.  The FP32 forms use half-angle operands, so
-    1 - cos(ti - tj) is formed from sin((ti - tj)/2) with an error proportional to
-    the pair's own separation (about 6e-8 relative), then raised to the -3/2
-    power; with the FP32 tile sums the measured error is 3e-7 to 6e-7 of max |f|.
+Force tolerances: tests/tolerances.py (about ten times the measured errors:
+FP64 5e-14 sqrt(n / 4096) at n > 4096, FP32 forms 2e-6 for 2D and 5e-6 for Ring).
+Other tolerances (max-norm, relative to the largest oracle value unless stated):
   * Energies (always FP64): 1e-12 of K + |V|.
   * HMF forces: 1e-13 (FP64 magnetization; the force is O(1)).
 """
@@ -31,19 +21,11 @@ torch = pytest.importorskip("torch")
 md = pytest.importorskip("paper_1212_0262_amd.md")
 from gpu_helpers import angle_diff, dev, gpu_energy, gpu_force, gpu_run, host, rel_inf  # noqa: E402
 
+from tolerances import check, force_tol  # noqa: E402
+
 HMF, RING, GRAV2D = md.HMF, md.RING, md.GRAV2D
 MIXED_PRECS = [md.MIXED, md.MIXED_KAHAN, md.MIXED_PAIRF64]
-FORCE_TOL = {
-    (GRAV2D, md.FP64): 5e-12, (RING, md.FP64): 5e-12,
-    (GRAV2D, md.MIXED): 2e-5, (GRAV2D, md.MIXED_KAHAN): 2e-5, (GRAV2D, md.MIXED_PAIRF64): 2e-5,
-    (RING, md.MIXED): 1e-5, (RING, md.MIXED_KAHAN): 1e-5, (RING, md.MIXED_PAIRF64): 1e-5,
-}
 SIZES = [1, 2, 63, 64, 65, 255, 257, 1000, 2048, 3001]
-
-
-def force_tol(model, prec, n=None):
-    """Force tolerance of (model, precision) at n particles."""
-    return FORCE_TOL[(model, prec)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -73,9 +55,7 @@ def test_pair_force_matches_oracle(model, eps, prec, n):
     if n == 1:
         assert np.all(fg == 0.0)
         return
-    err = rel_inf(fg, fo)
-    print(f"model={model} prec={prec} n={n} rel_err={err:.3e}")
-    assert err < FORCE_TOL[(model, prec)], err
+    check(f"model={model} prec={prec} n={n}", rel_inf(fg, fo), force_tol(model, prec, n))
 
 
 @pytest.mark.parametrize("n", [1, 2, 255, 257, 100_000])
@@ -101,9 +81,9 @@ def test_force_is_tile_independent(model, eps, tiles):
     q, _ = _state(model, 1537, seed=3)
     ref = gpu_force(model, md.FP64, q, eps)
     got = gpu_force(model, md.FP64, q, eps, tiles=tiles)
-    assert rel_inf(got, ref) < 1e-13
-    fo = oracle.force(model, q, eps)
-    assert rel_inf(got, fo) < FORCE_TOL[(model, md.FP64)]
+    tol = force_tol(model, md.FP64, q.shape[-1])
+    check(f"tiles {tiles} model={model} against built-in tiles", rel_inf(got, ref), tol)
+    check(f"tiles {tiles} model={model} against the oracle", rel_inf(got, oracle.force(model, q, eps)), tol)
 
 
 def test_bad_tiles_rejected():
@@ -278,8 +258,7 @@ def test_grav2d_full_size_sampled_rows(prec):
     rows = np.random.default_rng(5).choice(n, size=64, replace=False)
     rows = np.concatenate([rows, [0, n - 1]])
     fo = oracle.force_rows(GRAV2D, q, rows, 1e-3)
-    tol = FORCE_TOL[(GRAV2D, prec)] * (10 if prec == md.FP64 else 1)  # n u kappa at n = 262,144
-    assert rel_inf(fg[:, rows], fo) < tol
+    check(f"2D n={n} prec={prec} sampled rows", rel_inf(fg[:, rows], fo), force_tol(GRAV2D, prec, n))
 
 
 @pytest.fixture(scope="module")
@@ -324,7 +303,7 @@ def test_ring_mixed_both_staged_kernels(n):
     fo = oracle.force_rows(RING, q, rows, 0.01)
     for prec in (md.MIXED, md.MIXED_KAHAN):
         fg = gpu_force(RING, prec, q, 0.01)
-        assert rel_inf(fg[:, rows], fo) < FORCE_TOL[(RING, prec)], prec
+        check(f"Ring n={n} prec={prec} sampled rows", rel_inf(fg[:, rows], fo), force_tol(RING, prec, n))
 
 
 @pytest.mark.parametrize("n", [2_097_152, 2_097_153])

@@ -20,7 +20,7 @@ hypothesis = pytest.importorskip("hypothesis")
 from hypothesis import given, settings, strategies as st  # noqa: E402
 
 from gpu_helpers import dev, host, rel_inf  # noqa: E402
-from test_gpu_parity import FORCE_TOL  # noqa: E402
+from tolerances import check, force_tol  # noqa: E402
 
 HMF, RING, GRAV2D = md.HMF, md.RING, md.GRAV2D
 
@@ -122,7 +122,8 @@ def test_random_small_systems_match_oracle(model, prec, n, ipl, waves, split, jt
     if n == 1:
         assert np.all(fg == 0.0)
     else:
-        assert rel_inf(fg, fo) < FORCE_TOL[(model, prec)]
+        check(f"random system model={model} prec={prec} n={n} tiles=({ipl}, {waves}, {split}, {jtile})",
+              rel_inf(fg, fo), force_tol(model, prec, n, run=min(jtile, n)))
 
 
 @settings(max_examples=30, deadline=None, derandomize=True)

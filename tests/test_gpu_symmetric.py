@@ -27,11 +27,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 md = pytest.importorskip("paper_1212_0262_amd.md")
 from gpu_helpers import dev, host, rel_inf  # noqa: E402
-from test_gpu_parity import FORCE_TOL  # noqa: E402
+from tolerances import check, force_tol  # noqa: E402
 
 GRAV2D, RING = md.GRAV2D, md.RING
 EPS = 1e-3
-TOL = FORCE_TOL[(GRAV2D, md.MIXED)]
 PRECS = [md.MIXED, md.MIXED_KAHAN, md.MIXED_PAIRF64, md.FP64]
 MODELS = [(GRAV2D, 1e-3), (RING, 0.01)]
 
@@ -66,9 +65,7 @@ def test_symmetric_force_matches_oracle(n, prec, model, eps):
     q, _ = _state(model, n, seed=300 + n)
     fo = oracle.force(model, q, eps)
     fg = _force(q, md.LAUNCH_SYMMETRIC, prec, model, eps)
-    err = rel_inf(fg, fo)
-    print(f"symmetric model={model} prec={prec} n={n} rel_err={err:.3e}")
-    assert err < FORCE_TOL[(model, prec)], err
+    check(f"symmetric model={model} prec={prec} n={n}", rel_inf(fg, fo), force_tol(model, prec, n))
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -81,9 +78,7 @@ def test_symmetric_force_clustered_state(prec):
     q = q[:, rng.permutation(n)]
     fo = oracle.force(GRAV2D, q, EPS)
     fg = _force(q, md.LAUNCH_SYMMETRIC, prec)
-    err = rel_inf(fg, fo)
-    print(f"symmetric clustered prec={prec} n={n} rel_err={err:.3e}")
-    assert err < FORCE_TOL[(GRAV2D, prec)], err
+    check(f"symmetric clustered prec={prec} n={n}", rel_inf(fg, fo), force_tol(GRAV2D, prec, n, clustered=True))
 
 
 @pytest.mark.parametrize("model,eps", MODELS)
@@ -94,14 +89,11 @@ def test_symmetric_against_staged(n, prec, model, eps):
     q, _ = _state(model, n, seed=7)
     fs = _force(q, md.LAUNCH_SYMMETRIC, prec, model, eps)
     ft = _force(q, md.LAUNCH_STAGED, prec, model, eps)
-    # FP64: n u kappa at this n (as the full-size FP64 rows test)
-    tol = FORCE_TOL[(model, prec)] * (10 if prec == md.FP64 else 1)
-    err = rel_inf(fs, ft)
-    print(f"symmetric vs staged model={model} prec={prec} n={n} rel_diff={err:.3e}")
-    assert err < tol, err
+    tol = force_tol(model, prec, n)
+    check(f"symmetric vs staged model={model} prec={prec} n={n}", rel_inf(fs, ft), tol)
     rows = np.concatenate([np.random.default_rng(n).choice(n, size=16, replace=False), [0, n - 1]])
     fo = oracle.force_rows(model, q, rows, eps)
-    assert rel_inf(fs[..., rows], fo) < tol
+    check(f"symmetric rows model={model} prec={prec} n={n}", rel_inf(fs[..., rows], fo), tol)
 
 
 @pytest.mark.parametrize("model,eps", MODELS)
@@ -165,9 +157,8 @@ def test_symmetric_at_the_maximum_size(model, eps):
     md.md_force(ctx, qd, f)
     rows = np.concatenate([np.random.default_rng(41).choice(n, size=16, replace=False), [0, 1023, 1024, n - 1]])
     fo = oracle.force_rows(model, q, rows, eps)
-    err = rel_inf(host(f)[..., rows], fo)
-    print(f"symmetric model={model} n={n} sampled rel_err={err:.3e}")
-    assert err < FORCE_TOL[(model, md.MIXED)], err
+    check(f"symmetric model={model} n={n} sampled rows", rel_inf(host(f)[..., rows], fo),
+          force_tol(model, md.MIXED, n))
     ctx.close()
 
 
@@ -283,15 +274,13 @@ def test_symmetric_ensemble_matches_oracle(model, prec, eps):
     eps_b = np.full(len(BATCH_SIZES), eps)
     eps_b[-2] = 2 * eps
     f = _batch_force(model, prec, q, off, eps_b, md.LAUNCH_SYMMETRIC)
-    tol = 5e-12 if prec == md.FP64 else FORCE_TOL[(model, md.MIXED)]
     for b, n in enumerate(BATCH_SIZES):
         qb, fb = q[:, off[b]:off[b + 1]], f[:, off[b]:off[b + 1]]
         if n == 1:
             assert np.all(fb == 0.0)
             continue
-        err = rel_inf(fb, oracle.force(model, qb, eps_b[b]))
-        print(f"symmetric ensemble model={model} prec={prec} N_b={n} rel_err={err:.3e}")
-        assert err < tol, (b, n, err)
+        check(f"symmetric ensemble model={model} prec={prec} N_b={n}", rel_inf(fb, oracle.force(model, qb, eps_b[b])),
+              force_tol(model, prec, n))
 
 
 def test_symmetric_ensemble_against_staged_and_repeatable():
@@ -302,7 +291,8 @@ def test_symmetric_ensemble_against_staged_and_repeatable():
     ft = _batch_force(RING, md.MIXED_KAHAN, q, off, eps_b, md.LAUNCH_STAGED)
     for b in range(len(sizes)):
         sl = slice(off[b], off[b + 1])
-        assert rel_inf(fs[:, sl], ft[:, sl]) < FORCE_TOL[(RING, md.MIXED)]
+        check(f"symmetric vs staged ensemble N_b={sizes[b]}", rel_inf(fs[:, sl], ft[:, sl]),
+              force_tol(RING, md.MIXED_KAHAN, sizes[b]))
     assert np.array_equal(fs, _batch_force(RING, md.MIXED_KAHAN, q, off, eps_b, md.LAUNCH_SYMMETRIC))
 
 
@@ -393,7 +383,8 @@ def test_random_symmetric_systems_match_oracle(model, prec, n, eps_scale, seed):
     eps = (1e-3 if model == GRAV2D else 0.01) * eps_scale
     q, _ = _state(model, n, seed=seed)
     fg = _force(q, md.LAUNCH_SYMMETRIC, prec, model, eps)
-    assert rel_inf(fg, oracle.force(model, q, eps)) < FORCE_TOL[(model, prec)]
+    check(f"random symmetric model={model} prec={prec} n={n} eps={eps}", rel_inf(fg, oracle.force(model, q, eps)),
+          force_tol(model, prec, n, eps=eps))
 
 
 @settings(max_examples=15, deadline=None, derandomize=True)
@@ -407,13 +398,13 @@ def test_random_symmetric_ensembles_match_oracle(prec, sizes, seed):
     q, _, off = _ensemble(RING, sizes, seed=seed)
     eps_b = np.full(len(sizes), 0.01)
     f = _batch_force(RING, prec, q, off, eps_b, md.LAUNCH_SYMMETRIC)
-    tol = 5e-12 if prec == md.FP64 else FORCE_TOL[(RING, md.MIXED)]
     for b, n in enumerate(sizes):
         sl = slice(off[b], off[b + 1])
         if n == 1:
             assert np.all(f[:, sl] == 0.0)
         else:
-            assert rel_inf(f[:, sl], oracle.force(RING, q[:, sl], 0.01)) < tol, (b, n)
+            check(f"random symmetric ensemble prec={prec} N_b={n}", rel_inf(f[:, sl], oracle.force(RING, q[:, sl], 0.01)),
+                  force_tol(RING, prec, n))
 
 
 # ------------------------------------------------------- coincident angles --
@@ -452,6 +443,4 @@ def test_ring_fp32_symmetric_coincident_angles():
     fo = oracle.force_rows(RING, q, rows, eps)
     for prec in (md.MIXED, md.MIXED_KAHAN):
         fs = _force(q, md.LAUNCH_SYMMETRIC, prec, RING, eps)
-        err = rel_inf(fs[:, rows], fo)
-        print(f"duplicated angles prec={prec}: rel_err={err:.3e}")
-        assert err < FORCE_TOL[(RING, prec)], err
+        check(f"duplicated angles prec={prec}", rel_inf(fs[:, rows], fo), force_tol(RING, prec, n))
