@@ -247,6 +247,29 @@ int md_get_launch(const md_ctx *c);
 int md_force(md_ctx *c, const double *q, double *f);
 
 /*
+ * md_force for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It takes no context and no
+ * workspace, and calls no allocating routine (device or host): its workspace is
+ * the library's own static device array of MD_NOALLOC_SCRATCH_BYTES, one per
+ * GPU, held from the library's load to the end of the process.
+ *   model, prec, n, eps: as md_init (same validation and statuses).
+ *   hip_stream: the stream to enqueue on (NULL = the legacy default stream).
+ *   q, f: device [d][n] FP64 on the current device, as md_force.
+ * Works on the current device.  Computes what md_force computes in the staged
+ * form (MD_LAUNCH_STAGED) with the built-in tiles, except that the j split is
+ * halved until the pair partials fit the array: where it is not halved the
+ * result is bit-identical to md_force on a context with the same tiles and
+ * launch form.  MD_ENOMEM if n needs more than the array even with one j range
+ * (2D gravity above about 2 million particles; Ring above about 3 million;
+ * HMF never).  MD_EDEVICE for a failed launch (no detail: there is no context).
+ * Every call on a GPU shares that GPU's array, which keeps the previous call's
+ * contents: calls that overlap on one GPU (concurrent streams, or threads) race,
+ * so the caller must order them.
+ */
+#define MD_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int md_force_noalloc(int model, int prec, int64_t n, double eps, void *hip_stream, const double *q, double *f);
+
+/*
  * nsteps Yoshida steps of size dt (eq. 4), in place.  On entry f must equal
  * force(q) (from md_force or the previous md_step); on exit q, p hold the state
  * at t + nsteps*dt and f = force(q).  Three force evaluations per step; the

@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -637,6 +638,67 @@ void timed_end(md_ctx *c, int slot)
     if (slot >= 0 && c->timing) (void)hipEventRecord(c->timing->ev[2 * (size_t)slot + 1], c->stream);
 }
 
+// ---- the force without a caller's workspace (md_force_noalloc) ----
+//
+// The workspace lives in `scratch`, a file-scope device array: every GPU the
+// library runs on holds its own copy, at its own address, from module load to
+// process end.  In host code the array's name is only a stand-in for that
+// address, so host code never passes it: the first md_force_noalloc call on a
+// device looks the device's address up (hipGetSymbolAddress, with that device
+// current) and keeps it; every later call on the device uses the kept address.
+static __device__ __align__(256) char scratch[MD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device, once looked up
+
+// The address of the current device's `scratch` (dev = the current device).
+hipError_t scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr || ((uintptr_t)ptr % kAlign) != 0) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// What md_force reads and writes besides q and f, in the staged form with
+// `jsplit` j ranges: the context's carve-up without the symmetric form's slots,
+// the fused stage's operand buffers, the HVP vector and the HMF FP32 state,
+// which md_force does not touch.
+struct ForceLayout {
+    size_t red, scal, macc, ops, part, total;
+};
+
+ForceLayout force_layout(int model, int prec, int64_t n, int jsplit)
+{
+    ForceLayout L{};
+    const size_t npad = (size_t)pad_n(n);
+    size_t off = 0;
+    L.red = off;
+    off = align_up(off + sizeof(double) * kRedSlots);
+    L.scal = off;
+    off = align_up(off + sizeof(double) * 32);
+    L.macc = off;
+    if (model == MD_HMF) off = align_up(off + sizeof(long long) * kMWords);
+    L.ops = off;
+    if (model == MD_RING) off = align_up(off + 2 * npad * (prec == MD_FP64 ? sizeof(double) : sizeof(float)));
+    else if (model == MD_GRAV2D && prec != MD_FP64) off = align_up(off + 2 * npad * sizeof(float));
+    L.part = off;
+    if (model != MD_HMF) off = align_up(off + (size_t)jsplit * dims(model) * npad * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
 }  // namespace md
 
 using namespace md;
@@ -1116,5 +1178,56 @@ const char *md_strerror(int status)
 const char *md_last_error(const md_ctx *c) { return c ? c->err.c_str() : ""; }
 
 const char *md_version(void) { return "libmd 0.1 (gfx950)"; }
+
+int md_force_noalloc(int model, int prec, int64_t n, double eps, void *hip_stream, const double *q, double *f)
+{
+    if (!model_ok(model) || n < 1 || n > (model == MD_HMF ? kMaxHmfN : kMaxPairN)) return MD_EINVAL;
+    if (!prec_ok(model, prec)) return MD_EUNSUPPORTED;
+    if (model != MD_HMF && !(eps > 0.0 && isfinite(eps))) return MD_EINVAL;
+    if (!q || !f || !aligned8(q) || !aligned8(f)) return MD_EINVAL;
+    // the built-in tiles, with the j split halved until its partials fit
+    Tiles t = default_tiles(model, prec, n);
+    while (t.jsplit > 1 && force_layout(model, prec, n, t.jsplit).total > MD_NOALLOC_SCRATCH_BYTES) t.jsplit /= 2;
+    const ForceLayout L = force_layout(model, prec, n, t.jsplit);
+    if (L.total > MD_NOALLOC_SCRATCH_BYTES) return MD_ENOMEM;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MD_EDEVICE;
+    void *base = nullptr;
+    if (scratch_address(dev, &base) != hipSuccess) return MD_EDEVICE;
+
+    // A context on the stack over the scratch (no host allocation either): the
+    // same fields md_init sets for what md_force reads
+    md_ctx c;
+    c.model = model;
+    c.prec = prec;
+    c.n = n;
+    c.npad = pad_n(n);
+    c.eps = model == MD_HMF ? 0.0 : eps;
+    c.stream = static_cast<hipStream_t>(hip_stream);
+    c.dev = dev;
+    c.ws = static_cast<char *>(base);
+    c.ws_bytes = MD_NOALLOC_SCRATCH_BYTES;
+    c.red = reinterpret_cast<double *>(c.ws + L.red);
+    c.scal = reinterpret_cast<double *>(c.ws + L.scal);
+    c.macc = L.ops > L.macc ? reinterpret_cast<long long *>(c.ws + L.macc) : nullptr;
+    c.ops = L.part > L.ops ? static_cast<void *>(c.ws + L.ops) : nullptr;
+    c.part = L.total > L.part ? reinterpret_cast<double *>(c.ws + L.part) : nullptr;
+    c.launch = MD_LAUNCH_STAGED;
+    c.tiles = t;
+    double *qm = const_cast<double *>(q);
+    hipError_t e = hipSuccess;
+    if (model == MD_HMF) {
+        // launch_hmf_begin zeroes the fixed-point sums the previous call left
+        e = launch_hmf_begin(&c);
+        if (e == hipSuccess) e = launch_hmf_pass(&c, 0, HMF_REDUCE, 0.0, 0.0, 0.0, qm, nullptr, nullptr, nullptr, false);
+        if (e == hipSuccess) e = launch_hmf_pass(&c, 1, HMF_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, nullptr, f, false);
+    } else {
+        // every slot the combine reads is written by the pair kernel first
+        e = launch_update(&c, UPD_PREP, 0.0, 0.0, 0.0, qm, nullptr, nullptr);
+        if (e == hipSuccess) e = launch_pair(&c, q);
+        if (e == hipSuccess) e = launch_update(&c, UPD_F_FROM_PART | UPD_STORE_F, 0.0, 0.0, 0.0, qm, nullptr, f);
+    }
+    return e == hipSuccess ? MD_OK : MD_EDEVICE;
+}
 
 }  // extern "C"

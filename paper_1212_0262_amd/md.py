@@ -50,6 +50,7 @@ SIGNATURES = {
     "md_get_launch": (_I, [_V]),
     "md_max_j_split": (_I, [_I64]),
     "md_force": (_I, [_V, _V, _V]),
+    "md_force_noalloc": (_I, [_I, _I, _I64, _D, _V, _V, _V]),
     "md_step": (_I, [_V, _V, _V, _V, _D, _I64]),
     "md_energy": (_I, [_V, _V, _V, _V]),
     "md_magnetization": (_I, [_V, _V, _V]),
@@ -243,6 +244,28 @@ def md_get_launch(ctx: Context) -> int:
 def md_force(ctx: Context, q: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
     ctx._check(load().md_force(ctx.handle, ctx._arr(q, "q"), ctx._arr(f, "f")), "md_force")
     return f
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # MD_NOALLOC_SCRATCH_BYTES
+
+
+def md_force_noalloc(model: int, prec: int, q: torch.Tensor, eps: float, f: torch.Tensor, stream=None) -> None:
+    """f = force(q) with the library's static workspace: no context, and nothing
+    allocated, here or in the library (f is the caller's).  Staged form, built-in
+    tiles (j split halved until its partials fit the static array)."""
+    d, n = dims(model), q.shape[-1]
+    for name, t in (("q", q), ("f", f)):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+            raise TypeError(f"{name}: expected a device float64 tensor")
+        if tuple(t.shape) != (d, n) or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous [{d}, {n}] tensor, got {tuple(t.shape)}")
+    st = load().md_force_noalloc(int(model), int(prec), int(n), float(eps), _stream_handle(stream), q.data_ptr(),
+                                 f.data_ptr())
+    if st == ENOMEM:
+        raise MDError(st, "md_force_noalloc",
+                      f"n = {n} needs more than the {NOALLOC_SCRATCH_BYTES >> 20} MiB static workspace")
+    if st != OK:
+        raise MDError(st, "md_force_noalloc")
 
 
 def md_step(ctx: Context, q: torch.Tensor, p: torch.Tensor, f: torch.Tensor, dt: float, nsteps: int) -> None:
