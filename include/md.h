@@ -260,8 +260,9 @@ int md_force(md_ctx *c, const double *q, double *f);
  * halved until the pair partials fit the array: where it is not halved the
  * result is bit-identical to md_force on a context with the same tiles and
  * launch form.  MD_ENOMEM if n needs more than the array even with one j range
- * (2D gravity above about 2 million particles; Ring above about 3 million;
- * HMF never).  MD_EDEVICE for a failed launch (no detail: there is no context).
+ * (24 bytes a particle for 2D with FP32 operands and for Ring FP64, so above
+ * about 2.7 million particles; 16 for 2D FP64 and Ring with FP32 operands, above
+ * about 4.1 million; HMF never).  MD_EDEVICE for a failed launch (no detail: there is no context).
  * Every call on a GPU shares that GPU's array, which keeps the previous call's
  * contents: calls that overlap on one GPU (concurrent streams, or threads) race,
  * so the caller must order them.

@@ -25,12 +25,11 @@ namespace {
 
 using namespace pairs;
 
-// 2D: adds (u - 2 r (r.u)/s)/s, u = w_i - w_j, r = r_i - r_j, to (ax, ay).
+// 2D: adds (u - 2 r (r.u)/s)/s, u = w_i - w_j, r = r_i - r_j, to (ax, ay), given
+// r and inv = 1/s.
 template <typename T, typename A>
-__device__ __forceinline__ void hvp_2d(T xi, T yi, T wxi, T wyi, T xj, T yj, T wxj, T wyj, T eps, A &ax, A &ay)
+__device__ __forceinline__ void hvp_2d_add(T dx, T dy, T inv, T wxi, T wyi, T wxj, T wyj, A &ax, A &ay)
 {
-    const T dx = xi - xj, dy = yi - yj;
-    const T inv = rcp_(fma_(dx, dx, fma_(dy, dy, eps)));
     const T ux = wxi - wxj, uy = wyi - wyj;
     const T t = fma_(dx, ux, dy * uy) * inv;
     const T c = (t + t) * inv;
@@ -38,6 +37,30 @@ __device__ __forceinline__ void hvp_2d(T xi, T yi, T wxi, T wyi, T xj, T yj, T w
     ax.add(-c, dx);
     ay.add(inv, uy);
     ay.add(-c, dy);
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ void hvp_2d(T xi, T yi, T wxi, T wyi, T xj, T yj, T wxj, T wyj, T eps, A &ax, A &ay)
+{
+    const T dx = xi - xj, dy = yi - yj;
+    hvp_2d_add(dx, dy, rcp_(fma_(dx, dx, fma_(dy, dy, eps))), wxi, wyi, wxj, wyj, ax, ay);
+}
+
+// The terms of two j (a, then b) with one reciprocal: 1/s_a = s_b / (s_a s_b) and
+// 1/s_b = s_a / (s_a s_b), three multiplies in place of a reciprocal (FP64: the
+// refined reciprocal is a quarter-rate seed and three FMAs).  Each 1/s carries
+// about 2 ulp instead of 1; s_a s_b stays finite and nonzero for particles closer
+// than about 1e77 and eps above 1e-154.
+template <typename T, typename A>
+__device__ __forceinline__ void hvp_2d_two(T xi, T yi, T wxi, T wyi, T xa, T ya, T wxa, T wya, T xb, T yb, T wxb,
+                                           T wyb, T eps, A &ax, A &ay)
+{
+    const T dxa = xi - xa, dya = yi - ya, dxb = xi - xb, dyb = yi - yb;
+    const T sa = fma_(dxa, dxa, fma_(dya, dya, eps));
+    const T sb = fma_(dxb, dxb, fma_(dyb, dyb, eps));
+    const T r = rcp_(sa * sb);
+    hvp_2d_add(dxa, dya, r * sb, wxi, wyi, wxa, wya, ax, ay);
+    hvp_2d_add(dxb, dyb, r * sa, wxi, wyi, wxb, wyb, ax, ay);
 }
 
 // Ring: adds phi''(d) (w_i - w_j) / pref, d = ti - tj.
@@ -97,12 +120,25 @@ __global__ __launch_bounds__(256) void k_hvp_2d(const T *__restrict__ xs, const 
         const int je = min(j1, jt + jtile);
         int j = jt;
         for (; j + 4 <= je; j += 4) {
+            if constexpr (sizeof(T) == 8) {
+                // FP64: one reciprocal for two j (measured FP32: the shared form does
+                // not pay, its multiplies costing what the FP32 reciprocal does)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const T xj = xs[j + u], yj = ys[j + u], wxj = wxs[j + u], wyj = wys[j + u];
+                for (int u = 0; u < 4; u += 2) {
+                    const T xa = xs[j + u], ya = ys[j + u], wxa = wxs[j + u], wya = wys[j + u];
+                    const T xb = xs[j + u + 1], yb = ys[j + u + 1], wxb = wxs[j + u + 1], wyb = wys[j + u + 1];
 #pragma unroll
-                for (int k = 0; k < IPL; ++k)
-                    hvp_2d(xi[k], yi[k], wxi[k], wyi[k], xj, yj, wxj, wyj, eps, ax[k], ay[k]);
+                    for (int k = 0; k < IPL; ++k)
+                        hvp_2d_two(xi[k], yi[k], wxi[k], wyi[k], xa, ya, wxa, wya, xb, yb, wxb, wyb, eps, ax[k], ay[k]);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const T xj = xs[j + u], yj = ys[j + u], wxj = wxs[j + u], wyj = wys[j + u];
+#pragma unroll
+                    for (int k = 0; k < IPL; ++k)
+                        hvp_2d(xi[k], yi[k], wxi[k], wyi[k], xj, yj, wxj, wyj, eps, ax[k], ay[k]);
+                }
             }
         }
         for (; j < je; ++j) {

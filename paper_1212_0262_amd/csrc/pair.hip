@@ -266,7 +266,7 @@ using sym_slot_t = std::conditional_t<std::is_same_v<A, AccTile>, float, double>
 // r0, r1: the operand rows ([2][npad], padded); part: slots [ntile][D][npad] of
 // sym_slot_t<A>.
 template <int MODEL, typename T, typename A, bool SYM>
-__global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1,
+__global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1, int n,
                                                            int npad, int ntile, T e, sym_slot_t<A> *__restrict__ part)
 {
     // JW32 (MD_MIXED): the wavefronts' FP32 j-side sums of the whole tile, added at
@@ -289,31 +289,38 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
         u1[k] = r1[i0 + k * kWave];
     }
     const int jl = b * kSymTile + lane;
-    sym_tile<MODEL, T, A, SYM>(
-        u0, u1, e, lane, kSymTile / kWave,
-        [&](int blk, T &v0, T &v1) {
-            v0 = r0[jl + blk * kWave];
-            v1 = r1[jl + blk * kWave];
-        },
-        [&](int blk, int m, A (&sj)[D]) {
-            if constexpr (JW32) {
+    auto load = [&](int blk, T &v0, T &v1) {
+        v0 = r0[jl + blk * kWave];
+        v1 = r1[jl + blk * kWave];
+    };
+    auto jsum = [&](int blk, int m, A (&sj)[D]) {
+        if constexpr (JW32) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) jw32[wave][d][blk * kWave + m] = (float)sj[d].get();
-            } else {
+            for (int d = 0; d < D; ++d) jw32[wave][d][blk * kWave + m] = (float)sj[d].get();
+        } else {
 #pragma unroll
-                for (int d = 0; d < D; ++d) jw64[wave][d][m] = sj[d].get();
-                __syncthreads();
-                if (threadIdx.x < D * kWave) {
-                    const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
-                    double t = 0.0;
+            for (int d = 0; d < D; ++d) jw64[wave][d][m] = sj[d].get();
+            __syncthreads();
+            if (threadIdx.x < D * kWave) {
+                const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
+                double t = 0.0;
 #pragma unroll
-                    for (int w = 0; w < kSymWaves; ++w) t += jw64[w][d][mm];
-                    part[(size_t)(D * a + d) * npad + b * kSymTile + blk * kWave + mm] = (sym_slot_t<A>)t;
-                }
-                __syncthreads();
+                for (int w = 0; w < kSymWaves; ++w) t += jw64[w][d][mm];
+                part[(size_t)(D * a + d) * npad + b * kSymTile + blk * kWave + mm] = (sym_slot_t<A>)t;
             }
-        },
-        acc);
+            __syncthreads();
+        }
+    };
+    // 2D FP64: one reciprocal for two pairs (SHARE), except in the last tile, which
+    // holds the pads (b is never below a).  Measured at N = 262,144: 16.36 -> 14.76
+    // ms per force evaluation.  The FP32 forms keep one reciprocal a pair: there
+    // the shared form measured 1.5% slower (7.35 -> 7.45 ms), its three multiplies
+    // costing about what the FP32 reciprocal does
+    constexpr bool kShare = MODEL == MD_GRAV2D && sizeof(T) == 8;
+    if (!kShare || (b == ntile - 1 && n < npad))
+        sym_tile<MODEL, T, A, SYM, false>(u0, u1, e, lane, kSymTile / kWave, load, jsum, acc);
+    else
+        sym_tile<MODEL, T, A, SYM, kShare>(u0, u1, e, lane, kSymTile / kWave, load, jsum, acc);
 #pragma unroll
     for (int k = 0; k < kSymIpl; ++k)
 #pragma unroll
@@ -347,13 +354,13 @@ hipError_t sym_launch(md_ctx *c)
     if (noff > 0) {
         const int ts = timed_begin(c, MODEL == MD_GRAV2D ? "k_sym (2D, tile pairs)" : "k_sym (Ring, tile pairs)");
         hipLaunchKernelGGL((k_sym<MODEL, T, A, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad,
-                           npad, ntile, e, slots);
+                           (int)c->n, npad, ntile, e, slots);
         const hipError_t err = hipGetLastError();
         timed_end(c, ts);
         if (err != hipSuccess) return err;
     }
-    hipLaunchKernelGGL((k_sym<MODEL, T, A, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad, npad,
-                       ntile, e, slots);
+    hipLaunchKernelGGL((k_sym<MODEL, T, A, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad,
+                       (int)c->n, npad, ntile, e, slots);
     return hipGetLastError();
 }
 
@@ -463,6 +470,86 @@ __global__ __launch_bounds__(256) void k_update(const SlotT *__restrict__ part, 
             fd = f[(size_t)d * n + i];
         }
         stage_elem<PREP>(d, i, n, npad, fd, flags, f, p, q, ops, kick1, kick2, drift, snap);
+    }
+}
+
+// k_update for VW consecutive particles per thread (the symmetric form's slots,
+// large n): each slot row is read with one 16-byte load per lane (float4 of FP32
+// slots, double2 of FP64 ones) instead of VW 4- or 8-byte ones, the slots of each
+// particle still added in slot order, so the sums are those of k_update bit for
+// bit.  Measured on the 2D slot sum at N = 262,144 (256 FP32 slots a coordinate):
+// 102 -> 93 us.  The grid covers (UPD_PREP ? npad : n) / VW threads; npad is a
+// multiple of 1024, so every load of a thread's VW particles is in the slots.
+template <typename SlotT, int VW>
+struct SlotVec;
+template <>
+struct SlotVec<float, 4> {
+    using T = float4;
+};
+template <>
+struct SlotVec<double, 2> {
+    using T = double2;
+};
+
+template <int D, int PREP, typename SlotT, int VW>
+__global__ __launch_bounds__(64) void k_update_vec(const SlotT *__restrict__ part, int S, int n, int npad,
+                                                   double pref, double *__restrict__ f, double *__restrict__ p,
+                                                   double *__restrict__ q, void *__restrict__ ops, double kick1,
+                                                   double kick2, double drift, int flags, double *__restrict__ snap)
+{
+    using V = typename SlotVec<SlotT, VW>::T;
+    constexpr int U = 8;
+    const int i0 = VW * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (i0 >= npad) return;
+    double fs[VW][D];
+#pragma unroll
+    for (int k = 0; k < VW; ++k)
+#pragma unroll
+        for (int d = 0; d < D; ++d) fs[k][d] = 0.0;
+    if (flags & UPD_F_FROM_PART) {
+        int b = 0;
+        for (; b + U <= S; b += U) {
+            V v[D][U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    v[d][u] = *reinterpret_cast<const V *>(part + (size_t)((b + u) * D + d) * npad + i0);
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const SlotT *e = reinterpret_cast<const SlotT *>(&v[d][u]);
+#pragma unroll
+                    for (int k = 0; k < VW; ++k) fs[k][d] += (double)e[k];
+                }
+        }
+        for (; b < S; ++b)
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const V v = *reinterpret_cast<const V *>(part + (size_t)(b * D + d) * npad + i0);
+                const SlotT *e = reinterpret_cast<const SlotT *>(&v);
+#pragma unroll
+                for (int k = 0; k < VW; ++k) fs[k][d] += (double)e[k];
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        const int i = i0 + k;
+        if (i >= n) {  // with UPD_PREP the grid covers the pads too
+            if (flags & UPD_PREP) stage_pad<PREP>(i, npad, ops);
+            continue;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            double fd = 0.0;
+            if (flags & UPD_F_FROM_PART) {
+                fd = pref * fs[k][d];
+            } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
+                fd = f[(size_t)d * n + i];
+            }
+            stage_elem<PREP>(d, i, n, npad, fd, flags, f, p, q, ops, kick1, kick2, drift, snap);
+        }
     }
 }
 
@@ -633,9 +720,21 @@ hipError_t update(md_ctx *c, int flags, double kick1, double kick2, double drift
     if (pk == PREP_NONE) flags &= ~UPD_PREP;
     const int nthreads = (flags & UPD_PREP) ? npad : n;  // an operand refresh also writes the pads
     const dim3 block(256), grid((unsigned)((nthreads + 255) / 256));
+    // the symmetric form's slot sums with 16-byte loads where VW particles a thread
+    // still leave at least 1024 blocks of one wavefront
+    const int vw = slots32 ? 4 : 2;
+    const bool vec = sym && (flags & UPD_F_FROM_PART) && npad / vw / kWave >= 1024;
+    const dim3 vblock(kWave), vgrid((unsigned)((nthreads + vw * kWave - 1) / (vw * kWave)));
 #define MD_UPD(D_, P_)                                                                                              \
     do {                                                                                                            \
-        if (slots32)                                                                                                \
+        if (vec && slots32)                                                                                         \
+            hipLaunchKernelGGL((k_update_vec<D_, P_, float, 4>), vgrid, vblock, 0, c->stream,                       \
+                               reinterpret_cast<const float *>(c->part), S, n, npad, pref, f, p, q, ops, kick1, kick2, \
+                               drift, flags, snap);                                                                 \
+        else if (vec)                                                                                               \
+            hipLaunchKernelGGL((k_update_vec<D_, P_, double, 2>), vgrid, vblock, 0, c->stream, c->part, S, n, npad, \
+                               pref, f, p, q, ops, kick1, kick2, drift, flags, snap);                               \
+        else if (slots32)                                                                                           \
             hipLaunchKernelGGL((k_update<D_, P_, float>), grid, block, 0, c->stream,                                \
                                reinterpret_cast<const float *>(c->part), S, n, npad, pref, f, p, q, ops, kick1, kick2, \
                                drift, flags, snap);                                                                 \

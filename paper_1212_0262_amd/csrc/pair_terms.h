@@ -235,7 +235,14 @@ __host__ __device__ constexpr T sym_pad()
 
 // nblk (1 .. kSymTile / kWave, uniform across the block): the 64-j blocks of the j
 // tile to stream; a ragged tile stops after its last block that holds a particle.
-template <int MODEL, typename T, typename A, bool SYM, typename Load, typename JSum>
+// SHARE (2D): the lane's i come in twos against the same j, and each two take one
+// reciprocal: with s0, s1 their |r_i - r_j|^2 + eps and R = 1/(s0 s1), the weights
+// are 1/s0 = R s1 and 1/s1 = R s0 (three multiplies in place of a reciprocal; each
+// weight carries about 2 ulp instead of 1).  Needs s0 s1 finite and nonzero (in
+// FP64: particles closer than about 1e77 to each other, eps above 1e-154) and no
+// pad particle among the pair's operands (the pads' s would overflow the
+// product), so blocks that hold pads take SHARE = false.
+template <int MODEL, typename T, typename A, bool SYM, bool SHARE = false, typename Load, typename JSum>
 __device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[kSymIpl], T e, int lane, int nblk,
                                          Load &&load, JSum &&jsum, A (&acc)[MODEL == MD_GRAV2D ? 2 : 1][kSymIpl])
 {
@@ -256,6 +263,33 @@ __device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[k
 #pragma unroll
                     for (int d = 0; d < D; ++d) sj[d].rotate(next);
                 }
+            }
+            if constexpr (MODEL == MD_GRAV2D && SHARE) {
+                static_assert(kSymIpl % 2 == 0, "the i of a lane pair up");
+                T dx[kSymIpl], dy[kSymIpl], w[kSymIpl];
+#pragma unroll
+                for (int k = 0; k < kSymIpl; ++k) {
+                    dx[k] = v0 - u0[k];
+                    dy[k] = v1 - u1[k];
+                    w[k] = fma_(dx[k], dx[k], fma_(dy[k], dy[k], e));
+                }
+#pragma unroll
+                for (int k = 0; k < kSymIpl; k += 2) {
+                    const T r = rcp_(w[k] * w[k + 1]);
+                    const T s0 = w[k];
+                    w[k] = r * w[k + 1];
+                    w[k + 1] = r * s0;
+                }
+#pragma unroll
+                for (int k = 0; k < kSymIpl; ++k) {
+                    acc[0][k].add(-dx[k], w[k]);
+                    acc[1][k].add(-dy[k], w[k]);
+                    if (SYM) {
+                        sj[0].add(dx[k], w[k]);
+                        sj[1].add(dy[k], w[k]);
+                    }
+                }
+                continue;
             }
 #pragma unroll
             for (int k = 0; k < kSymIpl; ++k) {
