@@ -50,30 +50,7 @@ __global__ __launch_bounds__(256) void k_batch_pair_2d(const PairItem *__restric
         xi[k] = xs[i];
         yi[k] = ys[i];
     }
-    for (int jt = it.j0; jt < it.j1; jt += jtile) {
-        const int je = min(it.j1, jt + jtile);
-        int j = jt;
-        for (; j + 8 <= je; j += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const T xj = xs[j + u];
-                const T yj = ys[j + u];
-#pragma unroll
-                for (int k = 0; k < IPL; ++k) pair_2d(xi[k], yi[k], xj, yj, eps, ax[k], ay[k]);
-            }
-        }
-        for (; j < je; ++j) {
-            const T xj = xs[j];
-            const T yj = ys[j];
-#pragma unroll
-            for (int k = 0; k < IPL; ++k) pair_2d(xi[k], yi[k], xj, yj, eps, ax[k], ay[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < IPL; ++k) {
-            ax[k].fold();
-            ay[k].fold();
-        }
-    }
+    grav_j_range<T, A, IPL>(xs, ys, it.j0, it.j1, jtile, eps, xi, yi, ax, ay);
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int i = ibase + kWave * k;

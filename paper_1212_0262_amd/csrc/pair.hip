@@ -34,40 +34,6 @@ using namespace pairs;
 
 // ---------------------------------------------------------------- pair kernels --
 
-// Adds the 2D pair terms of j in [j0, j1) to each lane's IPL accumulators, j
-// ascending, the FP32 partials folded every jtile j (the order every 2D kernel
-// shares, so they agree bit for bit).  xs, ys: the j operands (wave-uniform).
-template <typename T, typename A, int IPL>
-__device__ __forceinline__ void grav_range(const T *__restrict__ xs, const T *__restrict__ ys, int j0, int j1,
-                                           int jtile, T eps, const T (&xi)[IPL], const T (&yi)[IPL], A (&ax)[IPL],
-                                           A (&ay)[IPL])
-{
-    for (int jt = j0; jt < j1; jt += jtile) {
-        const int je = min(j1, jt + jtile);
-        int j = jt;
-        for (; j + 8 <= je; j += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const T xj = xs[j + u];
-                const T yj = ys[j + u];
-#pragma unroll
-                for (int k = 0; k < IPL; ++k) pair_2d(xi[k], yi[k], xj, yj, eps, ax[k], ay[k]);
-            }
-        }
-        for (; j < je; ++j) {
-            const T xj = xs[j];
-            const T yj = ys[j];
-#pragma unroll
-            for (int k = 0; k < IPL; ++k) pair_2d(xi[k], yi[k], xj, yj, eps, ax[k], ay[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < IPL; ++k) {
-            ax[k].fold();
-            ay[k].fold();
-        }
-    }
-}
-
 // part[(s*2 + c)*npad + i] = sum over j in the s-th j range of the 2D pair term.
 template <typename T, typename A, int IPL>
 __global__ __launch_bounds__(256) void k_pair_2d(const T *__restrict__ xs, const T *__restrict__ ys,
@@ -89,7 +55,7 @@ __global__ __launch_bounds__(256) void k_pair_2d(const T *__restrict__ xs, const
         xi[k] = xs[i];
         yi[k] = ys[i];
     }
-    grav_range<T, A, IPL>(xs, ys, j0, j1, jtile, eps, xi, yi, ax, ay);
+    grav_j_range<T, A, IPL>(xs, ys, j0, j1, jtile, eps, xi, yi, ax, ay);
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int i = ibase + kWave * k;
@@ -630,6 +596,12 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
             else ring_term(a0[k], a1[k], x, y, e, acc0[k]);
         }
     };
+    // 2D FP64: the j in twos from the range start, as the staged kernel (grav_j_range)
+    constexpr bool TWO = MODEL == MD_GRAV2D && kPairTwo<T>;
+    auto term2 = [&](T xa, T ya, T xb, T yb) {
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) pair_2d_two(a0[k], a1[k], xa, ya, xb, yb, e, acc0[k], acc1[k]);
+    };
     for (int t = 0; t < wlen; t += 16) {
         const int off = t % CHL;
         if (off == 0) {
@@ -648,10 +620,18 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
         const T *w0 = win + g * WS + off;
         const T *w1 = win + (L + g) * WS + off;
         if (t + 16 <= len) {
+            if constexpr (TWO) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) term(w0[u], w1[u]);
+                for (int u = 0; u < 16; u += 2) term2(w0[u], w1[u], w0[u + 1], w1[u + 1]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) term(w0[u], w1[u]);
+            }
         } else {
-            for (int u = 0; u < len - t; ++u) term(w0[u], w1[u]);
+            int u = 0;
+            if constexpr (TWO)
+                for (; u + 2 <= len - t; u += 2) term2(w0[u], w1[u], w0[u + 1], w1[u + 1]);
+            for (; u < len - t; ++u) term(w0[u], w1[u]);
         }
         if (t < len && ((t + 16) % jtile == 0 || t + 16 >= len)) {
 #pragma unroll

@@ -94,6 +94,82 @@ __device__ __forceinline__ void pair_2d(T xi, T yi, T xj, T yj, T eps, A &ax, A 
     ay.add(dy, w);
 }
 
+// 2D, two j (a, then b) against the same i with one reciprocal: with s_a, s_b the
+// two |r_i - r_j|^2 + eps and R = 1/(s_a s_b), the weights are 1/s_a = R s_b and
+// 1/s_b = R s_a (three multiplies in place of a reciprocal; each weight carries
+// about 2 ulp instead of 1).  s_a s_b must be finite and nonzero.  The FP64 forms
+// take it (the refined FP64 reciprocal is a quarter-rate seed and three FMAs); in
+// FP32 the three multiplies cost about what the reciprocal does.
+template <typename T, typename A>
+__device__ __forceinline__ void pair_2d_two(T xi, T yi, T xa, T ya, T xb, T yb, T eps, A &ax, A &ay)
+{
+    const T dxa = xi - xa, dya = yi - ya, dxb = xi - xb, dyb = yi - yb;
+    const T sa = fma_(dxa, dxa, fma_(dya, dya, eps));
+    const T sb = fma_(dxb, dxb, fma_(dyb, dyb, eps));
+    const T r = rcp_(sa * sb);
+    const T wa = r * sb, wb = r * sa;
+    ax.add(dxa, wa);
+    ay.add(dya, wa);
+    ax.add(dxb, wb);
+    ay.add(dyb, wb);
+}
+
+// Whether the 2D terms of operand type T go in twos (pair_2d_two).
+template <typename T>
+constexpr bool kPairTwo = sizeof(T) == 8;
+
+// The 2D terms of j in [j0, j1) for each lane's IPL i, j ascending, the
+// accumulators folded every jtile j from j0 (jtile a multiple of 16).  The j
+// operands are wave-uniform (scalar loads).  With kPairTwo<T> the j go in twos
+// (j0 + 2m, j0 + 2m + 1) and an odd last one alone: the pairing every 2D staged,
+// fused and batched kernel shares, so that they agree bit for bit.
+template <typename T, typename A, int IPL>
+__device__ __forceinline__ void grav_j_range(const T *__restrict__ xs, const T *__restrict__ ys, int j0, int j1,
+                                             int jtile, T eps, const T (&xi)[IPL], const T (&yi)[IPL],
+                                             A (&ax)[IPL], A (&ay)[IPL])
+{
+    for (int jt = j0; jt < j1; jt += jtile) {
+        const int je = min(j1, jt + jtile);
+        int j = jt;
+        for (; j + 8 <= je; j += 8) {
+            if constexpr (kPairTwo<T>) {
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    const T xa = xs[j + u], ya = ys[j + u], xb = xs[j + u + 1], yb = ys[j + u + 1];
+#pragma unroll
+                    for (int k = 0; k < IPL; ++k) pair_2d_two(xi[k], yi[k], xa, ya, xb, yb, eps, ax[k], ay[k]);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const T xj = xs[j + u];
+                    const T yj = ys[j + u];
+#pragma unroll
+                    for (int k = 0; k < IPL; ++k) pair_2d(xi[k], yi[k], xj, yj, eps, ax[k], ay[k]);
+                }
+            }
+        }
+        if constexpr (kPairTwo<T>) {
+            for (; j + 2 <= je; j += 2) {
+                const T xa = xs[j], ya = ys[j], xb = xs[j + 1], yb = ys[j + 1];
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) pair_2d_two(xi[k], yi[k], xa, ya, xb, yb, eps, ax[k], ay[k]);
+            }
+        }
+        for (; j < je; ++j) {
+            const T xj = xs[j];
+            const T yj = ys[j];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) pair_2d(xi[k], yi[k], xj, yj, eps, ax[k], ay[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            ax[k].fold();
+            ay[k].fold();
+        }
+    }
+}
+
 // Ring (eq. 9): the term sin(ti - tj) / (1 - cos(ti - tj) + eps)^{3/2} as the
 // factors p q, from the cosines and sines of both angles.  one_eps = 1 + eps.
 // q is symmetric in i, j.  With EXACT the numerator p is two rounded products and
