@@ -867,15 +867,18 @@ def grav2d_workload(md, torch, args):
     # The dominant kernel's own launches, timed live by the library (HIP events on its stream).
     kernel_s = mixed["kernel_ms_avg"] * 1e-3
     if mixed["launch"] == "symmetric":
-        # the tile-pair kernel evaluates each pair of two different tiles once for both particles:
-        # it covers every interaction but those within a tile (the diagonal-tile kernel's)
+        # one launch per evaluation: each pair of two different tiles evaluated once for both
+        # particles (14 flops), every ordered pair of a diagonal tile for its i side (10 flops,
+        # the pads' included); it covers all N^2 interactions
         nt = -(-N // SYM_TILE)
-        last = N - (nt - 1) * SYM_TILE
-        units = N * N - (nt - 1) * SYM_TILE ** 2 - last * last
-        evals = nt * (nt - 1) // 2 * SYM_TILE ** 2
-        executed = SYM_FLOPS_PER_EVAL * evals
-        kernel = "k_sym<2, float, AccTile, true> (tile pairs)"
-        instr = {"valu_fp32": 8, "trans": 1, "per": "pair evaluated (both particles)"}
+        units = N * N
+        evals_pairs = nt * (nt - 1) // 2 * SYM_TILE ** 2
+        evals_diag = nt * SYM_TILE ** 2
+        evals = evals_pairs + evals_diag
+        executed = SYM_FLOPS_PER_EVAL * evals_pairs + FLOPS_PER_PAIR * evals_diag
+        kernel = "k_sym<2, float, AccTile> (tile pairs and diagonal tiles)"
+        instr = {"valu_fp32": 8, "trans": 1, "per": "pair of a tile pair evaluated (both particles); "
+                 "diagonal tiles 6 + 1 per ordered pair"}
     else:
         units = N * N
         evals = N * N
@@ -906,7 +909,7 @@ def grav2d_workload(md, torch, args):
             "kernel": kernel, "kernel_timed_as": mixed["kernel_name"],
             "kernel_ms_avg": round(mixed["kernel_ms_avg"], 4), "kernel_launches": mixed["kernel_launches"],
             "executed_flops_per_launch": executed, "pair_evaluations_per_launch": evals,
-            "flops_per_evaluation": executed // max(evals, 1),
+            "flops_per_evaluation": round(executed / max(evals, 1), 3),
             # the metric's convention: 10 flops per interaction (ordered pair) the launch covers
             "interaction_flops": FLOPS_PER_PAIR, "interactions_per_launch": units,
             "interaction_equivalent_tflops": round(interaction_tf, 3),
@@ -914,7 +917,7 @@ def grav2d_workload(md, torch, args):
             "instr_per_evaluation": instr,
             # SIMD cycles per interaction (pair of the N^2 count) and wavefront lane
             "cycles_per_pair_wave": round(SIMD_CYCLES_PER_S * 64 * kernel_s / units, 2),
-            # one whole force evaluation (this kernel, the diagonal tiles, the update) from the timed region
+            # one whole force evaluation (this kernel and the update) from the timed region
             "evaluation_ms": round(mixed["pair_ms_avg"], 4), "evaluation_tflops": round(evaluation_tf, 3),
             "evaluation_frac": round(evaluation_tf / PEAK_FP32_TFLOPS, 4),
         },

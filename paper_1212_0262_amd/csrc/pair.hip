@@ -191,9 +191,9 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 
 // ------------------------------------------------------- symmetric kernels --
 
-// One launch of k_sym<MODEL, T, A, true> takes every tile pair (a, b), a < b, of
-// a single system (the scheme of sym_tile in pair_terms.h); k_sym<..., false>
-// takes the diagonal tiles (a, a): every ordered pair of the tile, i side only.
+// One launch of k_sym<MODEL, T, A> per force evaluation takes the diagonal tiles
+// (a, a): every ordered pair of the tile, i side only; and every tile pair (a, b),
+// a < b, of a single system (the scheme of sym_tile in pair_terms.h):
 //   i side: the tile's sum goes to slot b of the i particles (MD_MIXED: partials
 //     over 128 j folded into FP64);
 //   j side: the sum over the 256 i of a wavefront, the 4 wavefronts added in
@@ -229,22 +229,32 @@ __device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
 template <typename A>
 using sym_slot_t = std::conditional_t<std::is_same_v<A, AccTile>, float, double>;
 
-// r0, r1: the operand rows ([2][npad], padded); part: slots [ntile][D][npad] of
-// sym_slot_t<A>.
+// JW32 (MD_MIXED): the wavefronts' FP32 j-side sums of the whole tile, added at
+// its end; otherwise (Kahan, per-pair FP64, FP64) their FP64 values after every
+// 64-j block (a Kahan sum's value carries its compensation: FP32 would drop it).
+template <typename A>
+constexpr bool kJW32 = std::is_same_v<A, AccTile>;
+// The block's LDS for the j-side sums of a tile pair (one of the two arrays is in
+// use: a union, so the unused one adds no bytes to the block's LDS, which sets how
+// many blocks a CU holds).
+template <int D, typename A>
+union SymLds {
+    float jw32[kJW32<A> ? kSymWaves : 1][D][kJW32<A> ? kSymTile : 1];
+    double jw64[kJW32<A> ? 1 : kSymWaves][D][kJW32<A> ? 1 : kWave];
+};
+
+// One block's share of a symmetric force evaluation: the tile pair (a, b), a < b
+// (SYM), or the diagonal tile a = b.  r0, r1: the operand rows ([2][npad],
+// padded); part: slots [ntile][D][npad] of sym_slot_t<A>.
 template <int MODEL, typename T, typename A, bool SYM>
-__global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1, int n,
-                                                           int npad, int ntile, T e, sym_slot_t<A> *__restrict__ part)
+__device__ __forceinline__ void sym_block(const T *__restrict__ r0, const T *__restrict__ r1, int n, int npad,
+                                          int ntile, T e, sym_slot_t<A> *__restrict__ part, int a, int b,
+                                          SymLds<MODEL == MD_GRAV2D ? 2 : 1, A> &lds)
 {
-    // JW32 (MD_MIXED): the wavefronts' FP32 j-side sums of the whole tile, added at
-    // its end; otherwise (Kahan, per-pair FP64, FP64) their FP64 values after every
-    // 64-j block (a Kahan sum's value carries its compensation: FP32 would drop it)
-    constexpr bool JW32 = std::is_same_v<A, AccTile>;
+    constexpr bool JW32 = kJW32<A>;
     constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
-    __shared__ float jw32[SYM && JW32 ? kSymWaves : 1][D][SYM && JW32 ? kSymTile : 1];
-    __shared__ double jw64[SYM && !JW32 ? kSymWaves : 1][D][SYM && !JW32 ? kWave : 1];
-    int a, b;
-    if (SYM) sym_tile_pair(blockIdx.x, ntile, a, b);
-    else a = b = blockIdx.x;
+    auto &jw32 = lds.jw32;
+    auto &jw64 = lds.jw64;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int i0 = a * kSymTile + wave * kWave * kSymIpl + lane;
     T u0[kSymIpl], u1[kSymIpl];
@@ -305,6 +315,27 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
     }
 }
 
+// One launch per force evaluation: blocks 0 .. ntile - 1 take the diagonal tiles
+// (the cheaper blocks first, so that the grid ends on uniform tile pairs), the
+// others the tile pairs a < b in row-major order.  Measured against two launches
+// (tile pairs, then diagonal tiles), 2D mixed at N = 262,144: the diagonal tiles'
+// 0.09 ms (one round of 256 blocks at one wavefront per SIMD) overlap the tile
+// pairs instead of following them.
+template <int MODEL, typename T, typename A>
+__global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1, int n,
+                                                           int npad, int ntile, T e, sym_slot_t<A> *__restrict__ part)
+{
+    __shared__ SymLds<MODEL == MD_GRAV2D ? 2 : 1, A> lds;
+    const int t = (int)blockIdx.x;
+    if (t < ntile) {
+        sym_block<MODEL, T, A, false>(r0, r1, n, npad, ntile, e, part, t, t, lds);
+    } else {
+        int a, b;
+        sym_tile_pair(t - ntile, ntile, a, b);
+        sym_block<MODEL, T, A, true>(r0, r1, n, npad, ntile, e, part, a, b, lds);
+    }
+}
+
 // The pads (particles n .. npad - 1) hold sym_pad's operands: every operand refresh
 // (UPD_PREP in k_update) writes them, so they are in place before any pair launch
 // of the same call, also inside a captured graph.
@@ -315,19 +346,14 @@ hipError_t sym_launch(md_ctx *c)
     const T *ops = static_cast<const T *>(c->ops);
     const T e = MODEL == MD_GRAV2D ? (T)c->eps : sizeof(T) == 4 ? (T)(2.0 * c->eps) : (T)(1.0 + c->eps);
     const dim3 block(kSymWaves * kWave);
-    const int noff = ntile * (ntile - 1) / 2;
+    const int nblk = ntile + ntile * (ntile - 1) / 2;  // diagonal tiles, then tile pairs
     sym_slot_t<A> *slots = reinterpret_cast<sym_slot_t<A> *>(c->part);
-    if (noff > 0) {
-        const int ts = timed_begin(c, MODEL == MD_GRAV2D ? "k_sym (2D, tile pairs)" : "k_sym (Ring, tile pairs)");
-        hipLaunchKernelGGL((k_sym<MODEL, T, A, true>), dim3((unsigned)noff), block, 0, c->stream, ops, ops + npad,
-                           (int)c->n, npad, ntile, e, slots);
-        const hipError_t err = hipGetLastError();
-        timed_end(c, ts);
-        if (err != hipSuccess) return err;
-    }
-    hipLaunchKernelGGL((k_sym<MODEL, T, A, false>), dim3((unsigned)ntile), block, 0, c->stream, ops, ops + npad,
-                       (int)c->n, npad, ntile, e, slots);
-    return hipGetLastError();
+    const int ts = timed_begin(c, MODEL == MD_GRAV2D ? "k_sym (2D)" : "k_sym (Ring)");
+    hipLaunchKernelGGL((k_sym<MODEL, T, A>), dim3((unsigned)nblk), block, 0, c->stream, ops, ops + npad, (int)c->n,
+                       npad, ntile, e, slots);
+    const hipError_t err = hipGetLastError();
+    timed_end(c, ts);
+    return err;
 }
 
 // --------------------------------------------------------------- update kernel --

@@ -79,9 +79,16 @@ def test_fused_tile_shapes(model, eps, dt, ipl, split, jtile):
     """Tile shapes over 1, 2, 4 and 8 lane groups, ragged n: still bit for bit the
     staged result."""
     n = 3001
-    if not _fused_fits(model, ipl, split):
-        pytest.skip("outside the fused LDS budget")
     tiles = (ipl, 4, split, jtile)
+    if not _fused_fits(model, ipl, split):  # the library refuses the fused form for these tiles
+        ctx = md.md_init(model, md.FP64, n, eps)
+        md.md_set_tiles(ctx, *tiles)
+        with pytest.raises(md.MDError) as ei:
+            md.md_set_launch(ctx, md.LAUNCH_FUSED)
+        assert ei.value.status == md.EUNSUPPORTED
+        assert md.md_get_launch(ctx) == md.LAUNCH_STAGED
+        ctx.close()
+        return
     for prec in (md.FP64, md.MIXED):
         a = _run(model, prec, n, eps, dt, 2, tiles, md.LAUNCH_STAGED, seed=81)
         b = _run(model, prec, n, eps, dt, 2, tiles, md.LAUNCH_FUSED, seed=81)

@@ -23,8 +23,8 @@ from gpu_helpers import dev, host  # noqa: E402
 
 # model, precision, n, eps, launch form (None: HMF), timed kernel, timed launches of md_step(2)
 CASES = [
-    (md.GRAV2D, md.MIXED, 65536, 1e-3, md.LAUNCH_SYMMETRIC, "k_sym (2D, tile pairs)", 6),
-    (md.RING, md.FP64, 4096, 0.01, md.LAUNCH_SYMMETRIC, "k_sym (Ring, tile pairs)", 6),
+    (md.GRAV2D, md.MIXED, 65536, 1e-3, md.LAUNCH_SYMMETRIC, "k_sym (2D)", 6),
+    (md.RING, md.FP64, 4096, 0.01, md.LAUNCH_SYMMETRIC, "k_sym (Ring)", 6),
     (md.GRAV2D, md.MIXED, 5000, 1e-3, md.LAUNCH_STAGED, "k_pair_2d", 6),
     (md.RING, md.MIXED, 5000, 0.01, md.LAUNCH_STAGED, "k_pair_win", 6),
     (md.RING, md.FP64, 5000, 0.01, md.LAUNCH_STAGED, "k_pair_ring", 6),
