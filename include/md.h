@@ -233,9 +233,9 @@ int md_max_j_split(int64_t n);
  * STAGED or SYMMETRIC.
  */
 enum md_launch { MD_LAUNCH_AUTO = 0, MD_LAUNCH_STAGED = 1, MD_LAUNCH_FUSED = 2, MD_LAUNCH_SYMMETRIC = 3 };
-#define MD_SYMMETRIC_AUTO_N 43008
-#define MD_SYMMETRIC_AUTO_N_RING 36864
-#define MD_SYMMETRIC_AUTO_N_RING64 32768
+#define MD_SYMMETRIC_AUTO_N 28672
+#define MD_SYMMETRIC_AUTO_N_RING 28672
+#define MD_SYMMETRIC_AUTO_N_RING64 20480
 int md_set_launch(md_ctx *c, int mode);
 int md_get_launch(const md_ctx *c);
 

@@ -100,8 +100,8 @@ def test_auto_launch_form_and_validation():
     small = md.md_init(RING, md.FP64, 2048, 0.01)
     assert md.md_get_launch(small) == md.LAUNCH_FUSED          # n <= 4096 and the built-in tiles fit
     assert md.md_get_tiles(small) == (1, 4, 64, 128)
-    big = md.md_init(GRAV2D, md.FP64, 32768, 1e-3)
-    assert md.md_get_launch(big) == md.LAUNCH_STAGED           # above the automatic size
+    big = md.md_init(GRAV2D, md.FP64, 16384, 1e-3)
+    assert md.md_get_launch(big) == md.LAUNCH_STAGED           # above the fused form's automatic size
     md.md_set_launch(big, md.LAUNCH_FUSED)
     assert md.md_get_launch(big) == md.LAUNCH_FUSED
     with pytest.raises(md.MDError):                             # 17 wavefronts (odd split: one lane group)
