@@ -530,23 +530,29 @@ def ensemble_workload(md, torch, args):
         cpu = {"value": npairs / dt / 1e9, "unit": "Gpair-interactions/s", "cores": oracle.get_threads(),
                "kind": "oracle", "sample": "force + 2 FP64 Yoshida steps of the 8 smallest realizations"}
     ctx.close()
-    # roofline of the tile-pair kernel (symmetric form, Kahan): the pairs of particles in
-    # different tiles of a realization, each evaluated once for both: 11 flops + 1 rsqrt
-    # for the half-angle term, 5 for each of the two compensated adds
-    tile_pairs = 0.0
+    # roofline of the symmetric kernel (Kahan; one launch per force evaluation): the pairs
+    # of particles in different tiles of a realization, each evaluated once for both (11
+    # flops + 1 rsqrt for the half-angle term, 5 for each of the two compensated adds),
+    # and the ordered pairs within each tile, i side only (11 + 5)
+    tile_pairs = diag_pairs = 0.0
     for nb_ in sizes.astype(np.int64):
         t = np.full(-(-int(nb_) // SYM_TILE), SYM_TILE, dtype=np.float64)
         t[-1] = nb_ - SYM_TILE * (len(t) - 1)
         tile_pairs += (float(nb_) ** 2 - float((t * t).sum())) / 2
+        diag_pairs += float((t * t).sum())
     k_s = k_ms / max(k_n, 1) * 1e-3
     sym = launch == "symmetric"
-    flops = (ENS_SYM_KAHAN_FLOPS * tile_pairs) if sym else (ENS_STAGED_KAHAN_FLOPS * pairs_per_eval)
+    flops = (ENS_SYM_KAHAN_FLOPS * tile_pairs + ENS_STAGED_KAHAN_FLOPS * diag_pairs) if sym \
+        else (ENS_STAGED_KAHAN_FLOPS * pairs_per_eval)
     tf = flops / k_s / 1e12
     roof = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tf / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel_timed_as": k_name,
             "kernel_ms_avg": round(k_ms / max(k_n, 1), 4), "kernel_launches": k_n,
-            "flops_per_evaluation": ENS_SYM_KAHAN_FLOPS if sym else ENS_STAGED_KAHAN_FLOPS,
-            "evaluations_per_launch": tile_pairs if sym else pairs_per_eval}
+            "flops_per_launch": flops,
+            "evaluations_per_launch": (tile_pairs + diag_pairs) if sym else pairs_per_eval,
+            "flops_per_evaluation": {"tile pairs (both particles)": ENS_SYM_KAHAN_FLOPS,
+                                     "diagonal tiles (i side)": ENS_STAGED_KAHAN_FLOPS} if sym
+            else ENS_STAGED_KAHAN_FLOPS}
     return {
         "metric": "Gpair-interactions/s (Ring ensemble, 256 realizations, graph-replayed)",
         "value": round(pairs / (graph_ms * 1e-3) / 1e9, 3), "unit": "Gpair-interactions/s",

@@ -300,14 +300,12 @@ __global__ __launch_bounds__(256) void k_batch_pair_ring_win(const PairItem *__r
 // particles, the j side (the wavefronts' sums added in FP64, fixed order, after
 // every 64-j block) to slot it.slot_j of the j particles.
 template <int MODEL, typename T, typename A, bool SYM>
-__global__ __launch_bounds__(kSymWaves * kWave) void k_batch_sym(const PairItem *__restrict__ items,
-                                                                 const T *__restrict__ r0, const T *__restrict__ r1,
-                                                                 const double *__restrict__ beps, int npad,
-                                                                 double *__restrict__ part)
+__device__ __forceinline__ void batch_sym_item(const PairItem &it, const T *__restrict__ r0,
+                                               const T *__restrict__ r1, const double *__restrict__ beps, int npad,
+                                               double *__restrict__ part,
+                                               double (&jw)[kSymWaves][MODEL == MD_GRAV2D ? 2 : 1][kWave])
 {
     constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
-    __shared__ double jw[SYM ? kSymWaves : 1][D][SYM ? kWave : 1];
-    const PairItem it = items[blockIdx.x];
     const double eb = beps[it.b];
     const T e = MODEL == MD_GRAV2D ? (T)eb : sizeof(T) == 4 ? (T)(2.0 * eb) : (T)(1.0 + eb);
     const T pad = sym_pad<MODEL, T>();
@@ -363,6 +361,22 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_batch_sym(const PairItem 
     }
 }
 
+// One launch per force evaluation: the n_soff tile pairs of the work list (a
+// block each), then its diagonal tiles, cheaper, at the end of the grid.
+template <int MODEL, typename T, typename A>
+__global__ __launch_bounds__(kSymWaves * kWave) void k_batch_sym(const PairItem *__restrict__ items, int n_soff,
+                                                                 const T *__restrict__ r0, const T *__restrict__ r1,
+                                                                 const double *__restrict__ beps, int npad,
+                                                                 double *__restrict__ part)
+{
+    __shared__ double jw[kSymWaves][MODEL == MD_GRAV2D ? 2 : 1][kWave];
+    const PairItem it = items[blockIdx.x];
+    if ((int)blockIdx.x < n_soff)
+        batch_sym_item<MODEL, T, A, true>(it, r0, r1, beps, npad, part, jw);
+    else
+        batch_sym_item<MODEL, T, A, false>(it, r0, r1, beps, npad, part, jw);
+}
+
 template <int MODEL, typename T, typename A>
 hipError_t sym_launch(md_ctx *c)
 {
@@ -371,17 +385,12 @@ hipError_t sym_launch(md_ctx *c)
     const int npad = (int)c->npad;
     const PairItem *items = reinterpret_cast<const PairItem *>(B.d_sitems);
     const dim3 block(kSymWaves * kWave);
-    if (B.n_soff > 0) {
-        const int ts = timed_begin(c, "k_batch_sym (tile pairs)");
-        hipLaunchKernelGGL((k_batch_sym<MODEL, T, A, true>), dim3((unsigned)B.n_soff), block, 0, c->stream, items, r0,
-                           r0 + npad, B.d_eps, npad, c->part);
-        const hipError_t err = hipGetLastError();
-        timed_end(c, ts);
-        if (err != hipSuccess) return err;
-    }
-    hipLaunchKernelGGL((k_batch_sym<MODEL, T, A, false>), dim3((unsigned)B.n_sdiag), block, 0, c->stream,
-                       items + B.n_soff, r0, r0 + npad, B.d_eps, npad, c->part);
-    return hipGetLastError();
+    const int ts = timed_begin(c, "k_batch_sym");
+    hipLaunchKernelGGL((k_batch_sym<MODEL, T, A>), dim3((unsigned)(B.n_soff + B.n_sdiag)), block, 0, c->stream, items,
+                       B.n_soff, r0, r0 + npad, B.d_eps, npad, c->part);
+    const hipError_t err = hipGetLastError();
+    timed_end(c, ts);
+    return err;
 }
 
 int prep_kind(const md_ctx *c)

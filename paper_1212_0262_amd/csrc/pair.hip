@@ -315,24 +315,23 @@ __device__ __forceinline__ void sym_block(const T *__restrict__ r0, const T *__r
     }
 }
 
-// One launch per force evaluation: blocks 0 .. ntile - 1 take the diagonal tiles
-// (the cheaper blocks first, so that the grid ends on uniform tile pairs), the
-// others the tile pairs a < b in row-major order.  Measured against two launches
-// (tile pairs, then diagonal tiles), 2D mixed at N = 262,144: the diagonal tiles'
-// 0.09 ms (one round of 256 blocks at one wavefront per SIMD) overlap the tile
-// pairs instead of following them.
+// One launch per force evaluation: the tile pairs a < b in row-major order, then
+// the diagonal tiles, the cheaper blocks at the end of the grid, where they fill
+// the last round.  Measured against two launches (tile pairs, then diagonal
+// tiles), 2D mixed: 7.28 -> 7.24 ms at N = 262,144 and 0.652 -> 0.613 ms at 65,536
+// (the diagonal tiles' separate launch was one latency-bound round of T blocks).
 template <int MODEL, typename T, typename A>
 __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1, int n,
                                                            int npad, int ntile, T e, sym_slot_t<A> *__restrict__ part)
 {
     __shared__ SymLds<MODEL == MD_GRAV2D ? 2 : 1, A> lds;
-    const int t = (int)blockIdx.x;
-    if (t < ntile) {
-        sym_block<MODEL, T, A, false>(r0, r1, n, npad, ntile, e, part, t, t, lds);
-    } else {
+    const int t = (int)blockIdx.x, noff = ntile * (ntile - 1) / 2;
+    if (t < noff) {
         int a, b;
-        sym_tile_pair(t - ntile, ntile, a, b);
+        sym_tile_pair(t, ntile, a, b);
         sym_block<MODEL, T, A, true>(r0, r1, n, npad, ntile, e, part, a, b, lds);
+    } else {
+        sym_block<MODEL, T, A, false>(r0, r1, n, npad, ntile, e, part, t - noff, t - noff, lds);
     }
 }
 
@@ -346,7 +345,7 @@ hipError_t sym_launch(md_ctx *c)
     const T *ops = static_cast<const T *>(c->ops);
     const T e = MODEL == MD_GRAV2D ? (T)c->eps : sizeof(T) == 4 ? (T)(2.0 * c->eps) : (T)(1.0 + c->eps);
     const dim3 block(kSymWaves * kWave);
-    const int nblk = ntile + ntile * (ntile - 1) / 2;  // diagonal tiles, then tile pairs
+    const int nblk = ntile * (ntile - 1) / 2 + ntile;  // tile pairs, then diagonal tiles
     sym_slot_t<A> *slots = reinterpret_cast<sym_slot_t<A> *>(c->part);
     const int ts = timed_begin(c, MODEL == MD_GRAV2D ? "k_sym (2D)" : "k_sym (Ring)");
     hipLaunchKernelGGL((k_sym<MODEL, T, A>), dim3((unsigned)nblk), block, 0, c->stream, ops, ops + npad, (int)c->n,
