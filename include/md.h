@@ -219,8 +219,9 @@ int md_max_j_split(int64_t n);
  *                     kept on both sides) or MD_FP64, 2D with MD_MIXED or
  *                     MD_MIXED_KAHAN, every N_b <= 1048576.  MD_EUNSUPPORTED for
  *                     other models, precisions or n;
- *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 4096 (the
- *                     built-in tiles there are the fused form's), symmetric
+ *   MD_LAUNCH_AUTO    (default) fused when it applies and n <= 4096 (Ring)
+ *                     or 6144 (2D gravity) (the built-in tiles there are the
+ *                     fused form's), symmetric
  *                     when it applies and n reaches the model's threshold
  *                     (MD_SYMMETRIC_AUTO_N for 2D gravity; for the Ring
  *                     MD_SYMMETRIC_AUTO_N_RING with the FP32 forms and

@@ -177,6 +177,14 @@ bool sym_ok(const md_ctx *c) { return c->batch ? c->batch->sym : sym_capable(c->
 // pairs outnumber their diagonal tiles (small realizations gain nothing from it).
 bool batch_sym_auto(const Batch &B) { return B.sym && B.n_soff >= B.n_sdiag; }
 
+// MD_LAUNCH_AUTO takes the fused form up to this n.  Measured on MI355X, md_step
+// staged (its built-in tiles) against fused (8 lane groups x 8 wavefronts), us per
+// step: Ring FP64 46.8 / 46.7 at N = 4096, 72.2 / 79.3 at 5120; Ring mixed 34.8 /
+// 29.6 and 48.2 / 48.9; 2D FP64 73.0 / 69.4 at 6144, 103.6 / 113.8 at 8192; 2D
+// mixed 49.2 / 45.9 and 68.6 / 67.0 (the 2D forms' j terms are cheaper, so the
+// fused stage's one block per 8 particles stays ahead longer).
+int64_t fused_auto_n(int model) { return model == MD_GRAV2D ? kFusedAutoN2D : kFusedAutoN; }
+
 // md_step's launch form for this context.
 int form_of(const md_ctx *c)
 {
@@ -188,7 +196,7 @@ int form_of(const md_ctx *c)
         if (sym_ok(c)) return MD_LAUNCH_SYMMETRIC;
     if (c->launch == MD_LAUNCH_STAGED || c->launch == MD_LAUNCH_SYMMETRIC || !fused_ok(c, c->tiles))
         return MD_LAUNCH_STAGED;
-    if (c->launch == MD_LAUNCH_FUSED || c->n <= kFusedAutoN) return MD_LAUNCH_FUSED;
+    if (c->launch == MD_LAUNCH_FUSED || c->n <= fused_auto_n(c->model)) return MD_LAUNCH_FUSED;
     return MD_LAUNCH_STAGED;
 }
 
@@ -579,15 +587,14 @@ int max_j_split(int64_t n)
 // its i loads and its output; below that, fixed choices found by the autotuner.
 Tiles default_tiles(int model, int prec, int64_t n)
 {
-    (void)model;
     (void)prec;
     Tiles t;
     t.waves = 4;
     t.jtile = 128;
-    if (n <= kFusedAutoN) {
+    if (n <= fused_auto_n(model)) {
         // the automatic fused launch: the most j ranges (8 lane groups x 8 wavefronts
-        // per block) measured fastest from N = 512 to 4096 (above that the staged form
-        // with the tiles below is faster: its update adds the slots 16 loads at a time)
+        // per block) measured fastest from N = 512 to 4096 (above fused_auto_n the
+        // staged form with the tiles below is faster)
         t.ipl = 1;
         t.jsplit = max_j_split(n) < 64 ? max_j_split(n) : 64;
         return t;

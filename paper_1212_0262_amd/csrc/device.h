@@ -135,47 +135,85 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return t;
 }
 
-// The sum over b = 0 .. S-1 of part[(b D + d) npad + i], added in order of b.  The
-// loads go out 16 at a time: one load, wait and add per slot leaves the update
-// kernels bound by the memory latency (the symmetric 2D form at N = 262,144 adds
-// 256 slots per coordinate).
+// The fixed order in which every launch form adds the S partials (slots) of a
+// particle, b = 0 .. S-1: blocks of kSlotBlock = 8 consecutive slots, each added as
+// a balanced tree, ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7)); the block
+// sums added in order of the block, starting from 0; then the S mod 8 slots past
+// the last block one by one.  All in FP64 (FP32 slots widened first).  The trees
+// keep the dependent adds per particle to S / 8 + 3 + S mod 8: the fused stage
+// sums up to 128 partials per particle inside one block, where a chain of S
+// dependent adds was the longest phase after the pair loop.
+constexpr int kSlotBlock = 8;
+
+template <typename V>
+__device__ __forceinline__ double tree8(const V (&v)[kSlotBlock])
+{
+    return (((double)v[0] + (double)v[1]) + ((double)v[2] + (double)v[3])) +
+           (((double)v[4] + (double)v[5]) + ((double)v[6] + (double)v[7]));
+}
+
+// The sum of part[(b D + d) npad + i] over b in the order above.  The loads go out
+// 16 at a time: one load, wait and add per slot leaves the update kernels bound by
+// the memory latency (the symmetric 2D form at N = 262,144 adds 256 slots per
+// coordinate).
 template <int D>
 __device__ __forceinline__ double slot_sum(const double *__restrict__ part, int S, int d, int npad, int i)
 {
-    constexpr int U = 16;
     double s = 0.0;
     int b = 0;
-    for (; b + U <= S; b += U) {
-        double v[U];
+    for (; b + 2 * kSlotBlock <= S; b += 2 * kSlotBlock) {
+        double v[2][kSlotBlock];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = part[(size_t)((b + u) * D + d) * npad + i];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int u = 0; u < U; ++u) s += v[u];
+            for (int u = 0; u < kSlotBlock; ++u) v[h][u] = part[(size_t)((b + h * kSlotBlock + u) * D + d) * npad + i];
+        s += tree8(v[0]);
+        s += tree8(v[1]);
+    }
+    if (b + kSlotBlock <= S) {
+        double v[kSlotBlock];
+#pragma unroll
+        for (int u = 0; u < kSlotBlock; ++u) v[u] = part[(size_t)((b + u) * D + d) * npad + i];
+        s += tree8(v);
+        b += kSlotBlock;
     }
     for (; b < S; ++b) s += part[(size_t)(b * D + d) * npad + i];
     return s;
 }
 
 // slot_sum for every coordinate d < D at once: the loads of all coordinates go
-// out together (16 D in flight), each coordinate still added in FP64 in order of b.
-// Slots of FP32 (the symmetric form's MD_MIXED slots) or FP64.
+// out together (16 D in flight).  Slots of FP32 (the symmetric form's MD_MIXED
+// slots) or FP64.
 template <int D, typename SlotT = double>
 __device__ __forceinline__ void slot_sums(const SlotT *__restrict__ part, int S, int npad, int i, double (&s)[D])
 {
-    constexpr int U = 16;
 #pragma unroll
     for (int d = 0; d < D; ++d) s[d] = 0.0;
     int b = 0;
-    for (; b + U <= S; b += U) {
-        SlotT v[D][U];
+    for (; b + 2 * kSlotBlock <= S; b += 2 * kSlotBlock) {
+        SlotT v[D][2][kSlotBlock];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u = 0; u < kSlotBlock; ++u)
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    v[d][h][u] = part[(size_t)((b + h * kSlotBlock + u) * D + d) * npad + i];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            s[d] += tree8(v[d][0]);
+            s[d] += tree8(v[d][1]);
+        }
+    }
+    if (b + kSlotBlock <= S) {
+        SlotT v[D][kSlotBlock];
+#pragma unroll
+        for (int u = 0; u < kSlotBlock; ++u)
 #pragma unroll
             for (int d = 0; d < D; ++d) v[d][u] = part[(size_t)((b + u) * D + d) * npad + i];
 #pragma unroll
-        for (int d = 0; d < D; ++d)
-#pragma unroll
-            for (int u = 0; u < U; ++u) s[d] += (double)v[d][u];
+        for (int d = 0; d < D; ++d) s[d] += tree8(v[d]);
+        b += kSlotBlock;
     }
     for (; b < S; ++b)
 #pragma unroll

@@ -51,7 +51,8 @@ constexpr int kEnergyBlock = 256;
 constexpr int64_t kFusedMaxN = 65536;   // contexts up to this n carry the fused stage's operand buffers
 constexpr int kFusedMaxWaves = 16;      // wavefronts per fused block
 constexpr int kFusedLdsBytes = 49152;   // LDS per fused block (split evenly between its wavefronts)
-constexpr int64_t kFusedAutoN = 4096;   // MD_LAUNCH_AUTO takes the fused form up to this n
+constexpr int64_t kFusedAutoN = 4096;   // MD_LAUNCH_AUTO takes the fused form up to this n (Ring)
+constexpr int64_t kFusedAutoN2D = 6144; // ... and up to this n for 2D gravity
 constexpr int kSymTile = 1024;          // particles per tile of the symmetric 2D form (4 waves x 64 x 4 i)
 constexpr int64_t kSymMinN = 2048;      // the symmetric form needs two tiles at least
 constexpr int64_t kSymMaxN = 1 << 20;   // and at most 1024 tiles (its partial slots: 8 d n^2 / 1024 bytes)

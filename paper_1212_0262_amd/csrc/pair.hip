@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 //     sums) or after every 64-j block through a small LDS buffer (the other
 //     accumulations), into slot a of the j particles.
 // Each particle thus receives one slot per tile and the update kernel adds them
-// in FP64 in slot order: a fixed order, no atomics.  The slots of MD_MIXED are
+// in FP64 in the fixed order of slot_sums (device.h): no atomics.  The slots of MD_MIXED are
 // FP32 (the tile's sum rounded once: half the bytes the update reads back, for
 // a rounding below that of the FP32 partials themselves); the others are FP64.
 // Pad particles (n .. npad - 1) contribute nothing:
@@ -467,8 +467,8 @@ __global__ __launch_bounds__(256) void k_update(const SlotT *__restrict__ part, 
 // k_update for VW consecutive particles per thread (the symmetric form's slots,
 // large n): each slot row is read with one 16-byte load per lane (float4 of FP32
 // slots, double2 of FP64 ones) instead of VW 4- or 8-byte ones, the slots of each
-// particle still added in slot order, so the sums are those of k_update bit for
-// bit.  Measured on the 2D slot sum at N = 262,144 (256 FP32 slots a coordinate):
+// particle still added in the order of slot_sums (device.h), so the sums are
+// those of k_update bit for bit.  Measured on the 2D slot sum at N = 262,144 (256 FP32 slots a coordinate):
 // 102 -> 93 us.  The grid covers (UPD_PREP ? npad : n) / VW threads; npad is a
 // multiple of 1024, so every load of a thread's VW particles is in the slots.
 template <typename SlotT, int VW>
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(64) void k_update_vec(const SlotT *__restrict__ par
                                                    double kick2, double drift, int flags, double *__restrict__ snap)
 {
     using V = typename SlotVec<SlotT, VW>::T;
-    constexpr int U = 8;
+    constexpr int U = kSlotBlock;
     const int i0 = VW * (blockIdx.x * blockDim.x + threadIdx.x);
     if (i0 >= npad) return;
     double fs[VW][D];
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(64) void k_update_vec(const SlotT *__restrict__ par
     for (int k = 0; k < VW; ++k)
 #pragma unroll
         for (int d = 0; d < D; ++d) fs[k][d] = 0.0;
-    if (flags & UPD_F_FROM_PART) {
+    if (flags & UPD_F_FROM_PART) {  // the slot order of slot_sums (device.h)
         int b = 0;
         for (; b + U <= S; b += U) {
             V v[D][U];
@@ -509,10 +509,11 @@ __global__ __launch_bounds__(64) void k_update_vec(const SlotT *__restrict__ par
 #pragma unroll
             for (int d = 0; d < D; ++d)
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const SlotT *e = reinterpret_cast<const SlotT *>(&v[d][u]);
+                for (int k = 0; k < VW; ++k) {
+                    SlotT e[U];
 #pragma unroll
-                    for (int k = 0; k < VW; ++k) fs[k][d] += (double)e[k];
+                    for (int u = 0; u < U; ++u) e[u] = reinterpret_cast<const SlotT *>(&v[d][u])[k];
+                    fs[k][d] += tree8(e);
                 }
         }
         for (; b < S; ++b)
@@ -631,14 +632,39 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
         const int off = t % CHL;
         if (off == 0) {
             wave_sync();  // the previous window's reads are done
-            for (int idx = lane; idx < L * CHL; idx += kWave) {
-                const int gg = idx / CHL, ee = idx % CHL;
-                const int jb = (w * L + gg) * jlen;
-                const int j = jb + t + ee;
-                if (t + ee < jlen && j < n) {
-                    win[gg * WS + ee] = r0[j];
-                    win[(L + gg) * WS + ee] = r1[j];
-                }
+            // The window's cnt j per group (none past the wavefront's longest range):
+            // FB 64-j columns of every group are loaded (addresses clamped in
+            // bounds) before the first LDS write, so a window of up to FB * 64 j per
+            // group costs one memory round trip.  Measured at N = 2048 (Ring), from
+            // the kernel's start to the first window in LDS, against one load and
+            // its LDS write per loop trip: 2.2 -> 1.9 us (FP64), 3.3 -> 1.6 us (FP32,
+            // whose windows are twice as long); a step 23.7 -> 22.7 us (FP64) and
+            // 24.1 -> 17.7 us (mixed).
+            constexpr int FB = 8 / L;
+            const int cnt = min(CHL, wlen - t);
+            for (int e0 = 0; e0 < cnt; e0 += FB * kWave) {
+                T x0[FB][L], x1[FB][L];
+#pragma unroll
+                for (int m = 0; m < FB; ++m)
+#pragma unroll
+                    for (int gg = 0; gg < L; ++gg) {
+                        const int ee = e0 + m * kWave + lane;
+                        const int j = (w * L + gg) * jlen + t + ee;
+                        const int jc = ee < cnt && j < n ? j : 0;
+                        x0[m][gg] = r0[jc];
+                        x1[m][gg] = r1[jc];
+                    }
+#pragma unroll
+                for (int m = 0; m < FB; ++m)
+#pragma unroll
+                    for (int gg = 0; gg < L; ++gg) {
+                        const int ee = e0 + m * kWave + lane;
+                        const int j = (w * L + gg) * jlen + t + ee;
+                        if (ee < cnt && j < n) {
+                            win[gg * WS + ee] = x0[m][gg];
+                            win[(L + gg) * WS + ee] = x1[m][gg];
+                        }
+                    }
             }
             wave_sync();
         }
@@ -674,19 +700,42 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
         if constexpr (MODEL == MD_GRAV2D) part[(g * IPL * D + k * D + 1) * IL + il] = acc1[k].get();
     }
     __syncthreads();
+    // The partials of range bb (of S L) for coordinate kd of i slot s2 (the order of
+    // slot_sums in device.h, range 0 first).  First the blocks of kSlotBlock ranges,
+    // a thread per block: its tree sum replaces the block's first partial (each
+    // partial is read by one thread only); then a thread per particle adds them.
+    auto fpart = [&](int bb, int kd, int s2) {
+        return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + (size_t)(bb / L) * slice_bytes) +
+               ((bb % L) * IPL * D + kd) * IL + s2;
+    };
+    const int nblk = S * L / kSlotBlock;
+    if (flags & UPD_F_FROM_PART) {
+        for (int x = threadIdx.x; x < nblk * IPL * D * IL; x += blockDim.x) {
+            const int it = x % (IPL * D * IL), bb = x / (IPL * D * IL) * kSlotBlock;
+            const int s2 = it % IL, kd = it / IL;
+            double v[kSlotBlock];
+#pragma unroll
+            for (int u = 0; u < kSlotBlock; ++u) v[u] = *fpart(bb + u, kd, s2);
+            *fpart(bb, kd, s2) = tree8(v);
+        }
+        __syncthreads();
+    }
     for (int it = threadIdx.x; it < IPL * D * IL; it += blockDim.x) {
         const int s2 = it % IL, kd = it / IL;
         const int k = kd / D, d = kd % D;
         const int i = i0 + IL * k + s2;
         if (i < n) {
             double fd = 0.0;
-            if (flags & UPD_F_FROM_PART) {
+            if (flags & UPD_F_FROM_PART) {  // the block sums above, then the rest
+                constexpr int kMaxBlk = kFusedMaxWaves * 8 / kSlotBlock;  // S <= 16 wavefronts, L <= 8
+                double bs[kMaxBlk];
+#pragma unroll
+                for (int k = 0; k < kMaxBlk; ++k) bs[k] = k < nblk ? *fpart(k * kSlotBlock, kd, s2) : 0.0;
                 double sum = 0.0;
-                for (int bb = 0; bb < S * L; ++bb) {
-                    const double *pb =
-                        reinterpret_cast<const double *>(reinterpret_cast<const char *>(lds) + (size_t)(bb / L) * slice_bytes);
-                    sum += pb[((bb % L) * IPL * D + kd) * IL + s2];
-                }
+#pragma unroll
+                for (int k = 0; k < kMaxBlk; ++k)
+                    if (k < nblk) sum += bs[k];
+                for (int bb = nblk * kSlotBlock; bb < S * L; ++bb) sum += *fpart(bb, kd, s2);
                 fd = pref * sum;
             } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
                 fd = f[(size_t)d * n + i];

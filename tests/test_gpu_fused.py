@@ -100,6 +100,11 @@ def test_auto_launch_form_and_validation():
     small = md.md_init(RING, md.FP64, 2048, 0.01)
     assert md.md_get_launch(small) == md.LAUNCH_FUSED          # n <= 4096 and the built-in tiles fit
     assert md.md_get_tiles(small) == (1, 4, 64, 128)
+    for model, n_fused in ((RING, 4096), (GRAV2D, 6144)):     # the automatic sizes, per model
+        for n, form in ((n_fused, md.LAUNCH_FUSED), (n_fused + 1, md.LAUNCH_STAGED)):
+            ctx = md.md_init(model, md.MIXED, n, 1e-3)
+            assert md.md_get_launch(ctx) == form, (model, n)
+            md.md_destroy(ctx)
     big = md.md_init(GRAV2D, md.FP64, 16384, 1e-3)
     assert md.md_get_launch(big) == md.LAUNCH_STAGED           # above the fused form's automatic size
     md.md_set_launch(big, md.LAUNCH_FUSED)
