@@ -162,6 +162,31 @@ def test_symmetric_at_the_maximum_size(model, eps):
     ctx.close()
 
 
+@pytest.mark.parametrize("model,prec,n", [
+    (GRAV2D, md.MIXED, 267_044),        # 261 tiles: FP32 slots, 4 particles a thread, 5 slots past the trees
+    (GRAV2D, md.FP64, 134_127),         # 131 tiles: FP64 slots, 2 particles a thread, 3 past the trees
+    (RING, md.MIXED_KAHAN, 135_000),    # 132 tiles: 4 past the trees
+])
+def test_symmetric_vector_update_ragged_slot_count(model, prec, n):
+    """Sizes where the update reads the slots with 16-byte loads (several particles a
+    thread) and the slot count is not a multiple of the 8-slot trees, so the last
+    slots take the one-by-one path: sampled rows (first and last tile, the last
+    particles before the pads) against the oracle."""
+    eps = EPS if model == GRAV2D else 0.01
+    q, _ = _state(model, n, seed=43)
+    ctx = md.md_init(model, prec, n, eps)
+    assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
+    qd = dev(q)
+    f = torch.empty_like(qd)
+    md.md_force(ctx, qd, f)
+    rng = np.random.default_rng(43)
+    rows = np.concatenate([rng.choice(n, size=12, replace=False), [0, 1023, n - 1025, n - 2, n - 1]])
+    fo = oracle.force_rows(model, q, rows, eps)
+    check(f"symmetric vector update model={model} prec={prec} n={n} sampled rows", rel_inf(host(f)[..., rows], fo),
+          force_tol(model, prec, n))
+    ctx.close()
+
+
 def test_launch_form_and_refusals():
     big = md.md_init(GRAV2D, md.MIXED, md.SYMMETRIC_AUTO_N, EPS)
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
