@@ -323,6 +323,9 @@ int md_magnetization(md_ctx *c, const double *q, double *out_dev2);
  * its Jacobian is -H).  q, w, out: device [d][n] FP64.  HMF uses the mean-field
  * form of eqs. 6 and 7: (H w)_i = w_i (cos q_i Mx + sin q_i My) - cos q_i Cw
  * - sin q_i Sw with Cw, Sw the averages of cos q_j w_j and sin q_j w_j, O(N).
+ * 2D MD_FP64 contexts whose force takes the symmetric launch form (md_get_launch)
+ * take it for the product too: each pair evaluated once for both particles,
+ * the per-tile sums added in a fixed order (reproducible bit for bit).
  *
  * md_step_vjp: reverse-mode derivative of nsteps Yoshida steps started from the
  * state (q0, p0) (e.g. a checkpoint kept during the forward run).  On entry

@@ -211,19 +211,182 @@ __global__ __launch_bounds__(256) void k_hvp_ring(const T *__restrict__ cs, cons
     }
 }
 
-enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_HALF32 = 2, PREP_SINCOS64 = 3 };
+// ------------------------------------------------------ symmetric product --
+
+// The 2D term t(i, j) = phi''(r_i - r_j) (w_i - w_j) is odd under i <-> j (phi'' is
+// even in r, w_i - w_j odd), so, as for the force (k_sym, pair.hip), one evaluation
+// serves both particles: i adds t, j adds -t.  FP64, the force's tiles: a block
+// takes a tile pair (a, b), a < b (SYM), or a diagonal tile (a, a), every ordered
+// pair, i side only.  A wavefront holds 4 i per lane; tile b streams through in 16
+// blocks of 64 j, and at step s lane l meets j = (l + s) mod 64: the j operands
+// (x, y, wx, wy) and the j-side sums move one lane per step through ds_bpermute.
+// The i of a lane come in twos with one reciprocal (hvp_2d_two's scheme: SHARE),
+// except where the tile holds pads, whose s would overflow the product.
+//   x, y, wx, wy: this lane's 4 i;  e: eps;
+//   load(blk, xj, yj, wxj, wyj): this lane's j of 64-j block blk (lane l: j = l);
+//   jsum(blk, m, sj): the j-side sums of the block (sj belongs to j = m of it);
+//   acc: the i-side sums, [component][i].
+template <bool SYM, bool SHARE, typename Load, typename JSum>
+__device__ __forceinline__ void sym_tile_hvp(const double (&x)[kSymIpl], const double (&y)[kSymIpl],
+                                             const double (&wx)[kSymIpl], const double (&wy)[kSymIpl], double e,
+                                             int lane, Load &&load, JSum &&jsum, AccF64 (&acc)[2][kSymIpl])
+{
+    constexpr int nblk = kSymTile / kWave;
+    const int next = ((lane + 1) & (kWave - 1)) * 4;  // ds_bpermute byte address of lane l + 1
+    double n0, n1, n2, n3;
+    load(0, n0, n1, n2, n3);
+    for (int blk = 0; blk < nblk; ++blk) {
+        double xj = n0, yj = n1, wxj = n2, wyj = n3;
+        if (blk + 1 < nblk) load(blk + 1, n0, n1, n2, n3);
+        AccF64 sj[2];
+#pragma unroll 8
+        for (int s = 0; s < kWave; ++s) {
+            if (s) {
+                xj = lane_next(next, xj);
+                yj = lane_next(next, yj);
+                wxj = lane_next(next, wxj);
+                wyj = lane_next(next, wyj);
+                if (SYM) {
+                    sj[0].rotate(next);
+                    sj[1].rotate(next);
+                }
+            }
+            double dx[kSymIpl], dy[kSymIpl], inv[kSymIpl];
+#pragma unroll
+            for (int k = 0; k < kSymIpl; ++k) {
+                dx[k] = x[k] - xj;
+                dy[k] = y[k] - yj;
+                inv[k] = fma_(dx[k], dx[k], fma_(dy[k], dy[k], e));
+            }
+            if constexpr (SHARE) {
+#pragma unroll
+                for (int k = 0; k < kSymIpl; k += 2) {
+                    const double r = rcp_(inv[k] * inv[k + 1]);
+                    const double s0 = inv[k];
+                    inv[k] = r * inv[k + 1];
+                    inv[k + 1] = r * s0;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kSymIpl; ++k) inv[k] = rcp_(inv[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < kSymIpl; ++k) {
+                const double ux = wx[k] - wxj, uy = wy[k] - wyj;
+                const double t = fma_(dx[k], ux, dy[k] * uy) * inv[k];
+                const double c = (t + t) * inv[k];
+                acc[0][k].add(inv[k], ux);
+                acc[0][k].add(-c, dx[k]);
+                acc[1][k].add(inv[k], uy);
+                acc[1][k].add(-c, dy[k]);
+                if (SYM) {
+                    sj[0].add(-inv[k], ux);
+                    sj[0].add(c, dx[k]);
+                    sj[1].add(-inv[k], uy);
+                    sj[1].add(c, dy[k]);
+                }
+            }
+        }
+        if (SYM) jsum(blk, (lane + kWave - 1) & (kWave - 1), sj);  // after step 63 lane l holds j = l - 1
+    }
+}
+
+// One block's share of the symmetric product: tile pair (a, b) (SYM) or the diagonal
+// tile a = b.  q, w: [2][npad] operand rows (padded); part: slots [ntile][2][npad],
+// the i side to slot b of the i particles, the j side (the 4 wavefronts' sums added
+// in FP64 in a fixed order after every 64-j block) to slot a of the j particles.
+template <bool SYM>
+__device__ __forceinline__ void hvp_sym_block(const double *__restrict__ q, const double *__restrict__ w, int n,
+                                              int npad, int ntile, double e, double *__restrict__ part, int a, int b,
+                                              double (&jw)[kSymWaves][2][kWave])
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int i0 = a * kSymTile + wave * kWave * kSymIpl + lane;
+    double x[kSymIpl], y[kSymIpl], wx[kSymIpl], wy[kSymIpl];
+#pragma unroll
+    for (int k = 0; k < kSymIpl; ++k) {
+        const int i = i0 + k * kWave;
+        x[k] = q[i];
+        y[k] = q[npad + i];
+        wx[k] = w[i];
+        wy[k] = w[npad + i];
+    }
+    const int jl = b * kSymTile + lane;
+    auto load = [&](int blk, double &xj, double &yj, double &wxj, double &wyj) {
+        const int j = jl + blk * kWave;
+        xj = q[j];
+        yj = q[npad + j];
+        wxj = w[j];
+        wyj = w[npad + j];
+    };
+    auto jsum = [&](int blk, int m, AccF64 (&sj)[2]) {
+        jw[wave][0][m] = sj[0].get();
+        jw[wave][1][m] = sj[1].get();
+        __syncthreads();
+        if (threadIdx.x < 2 * kWave) {
+            const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
+            double t = 0.0;
+#pragma unroll
+            for (int v = 0; v < kSymWaves; ++v) t += jw[v][d][mm];
+            part[(size_t)(2 * a + d) * npad + b * kSymTile + blk * kWave + mm] = t;
+        }
+        __syncthreads();
+    };
+    AccF64 acc[2][kSymIpl];
+    if (b == ntile - 1 && n < npad)
+        sym_tile_hvp<SYM, false>(x, y, wx, wy, e, lane, load, jsum, acc);
+    else
+        sym_tile_hvp<SYM, true>(x, y, wx, wy, e, lane, load, jsum, acc);
+#pragma unroll
+    for (int k = 0; k < kSymIpl; ++k)
+#pragma unroll
+        for (int d = 0; d < 2; ++d) part[(size_t)(2 * b + d) * npad + i0 + k * kWave] = acc[d][k].get();
+}
+
+// One launch per product: the tile pairs a < b in row-major order, then the diagonal
+// tiles (the force's order, k_sym in pair.hip).
+__global__ __launch_bounds__(kSymWaves * kWave) void k_hvp_sym(const double *__restrict__ q,
+                                                               const double *__restrict__ w, int n, int npad,
+                                                               int ntile, double e, double *__restrict__ part)
+{
+    __shared__ double jw[kSymWaves][2][kWave];
+    const int t = (int)blockIdx.x, noff = ntile * (ntile - 1) / 2;
+    if (t < noff) {
+        int a, b;
+        sym_tile_pair(t, ntile, a, b);
+        hvp_sym_block<true>(q, w, n, npad, ntile, e, part, a, b, jw);
+    } else {
+        hvp_sym_block<false>(q, w, n, npad, ntile, e, part, t - noff, t - noff, jw);
+    }
+}
+
+// PREP_COPY64: the symmetric product's padded FP64 rows (positions to ops, vector to wops).
+enum Prep { PREP_NONE = 0, PREP_CAST32 = 1, PREP_HALF32 = 2, PREP_SINCOS64 = 3, PREP_COPY64 = 4 };
 
 // Elementwise: hw = pref * (sum of the product partials, fixed order); out = hw;
 // lq -= h hw; lp += a lq; operands of the next product (positions pos, vector lp).
+// PREP_COPY64 (the symmetric product): the grid covers npad and writes the pads of
+// the operand rows too, positions at sym_pad (1e150) and the vector at 0.
 template <int D, int PREP>
 __global__ __launch_bounds__(256) void k_adj_update(const double *__restrict__ part, int S, int n, int npad,
                                                     double pref, int flags, double h, double h2, double a,
                                                     double *__restrict__ lq, double *__restrict__ lp,
                                                     double *__restrict__ out, const double *__restrict__ pos,
-                                                    void *__restrict__ ops, float *__restrict__ wops)
+                                                    void *__restrict__ ops, void *__restrict__ wops)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n) {
+        if constexpr (PREP == PREP_COPY64) {
+            if (i < npad) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    if (flags & ADJ_PREPQ) static_cast<double *>(ops)[(size_t)d * npad + i] = sym_pad<MD_GRAV2D, double>();
+                    if (flags & ADJ_PREPW) static_cast<double *>(wops)[(size_t)d * npad + i] = 0.0;
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const size_t k = (size_t)d * n + i;
@@ -237,10 +400,15 @@ __global__ __launch_bounds__(256) void k_adj_update(const double *__restrict__ p
             }
         }
         if (flags & ADJ_DRIFT) lp[k] += a * lq[k];
-        if (flags & ADJ_PREPW) wops[(size_t)d * npad + i] = (float)lp[k];
+        if (flags & ADJ_PREPW) {
+            if (PREP == PREP_COPY64) static_cast<double *>(wops)[(size_t)d * npad + i] = lp[k];
+            else static_cast<float *>(wops)[(size_t)d * npad + i] = (float)lp[k];
+        }
         if ((flags & ADJ_PREPQ) && PREP != PREP_NONE) {
             const double qd = pos[k];
-            if (PREP == PREP_CAST32) {
+            if (PREP == PREP_COPY64) {
+                static_cast<double *>(ops)[(size_t)d * npad + i] = qd;
+            } else if (PREP == PREP_CAST32) {
                 static_cast<float *>(ops)[(size_t)d * npad + i] = (float)qd;
             } else if (PREP == PREP_HALF32) {
                 double sn, cn;
@@ -257,9 +425,15 @@ __global__ __launch_bounds__(256) void k_adj_update(const double *__restrict__ p
     }
 }
 
+// The symmetric product (k_hvp_sym) where the force takes the symmetric form: 2D, FP64.
+bool hvp_sym(const md_ctx *c)
+{
+    return c->model == MD_GRAV2D && c->prec == MD_FP64 && !c->batch && launch_form(c) == MD_LAUNCH_SYMMETRIC;
+}
+
 int prep_kind(const md_ctx *c)
 {
-    if (c->model == MD_GRAV2D) return c->prec == MD_FP64 ? PREP_NONE : PREP_CAST32;
+    if (c->model == MD_GRAV2D) return c->prec != MD_FP64 ? PREP_CAST32 : hvp_sym(c) ? PREP_COPY64 : PREP_NONE;
     return c->prec == MD_FP64 ? PREP_SINCOS64 : PREP_HALF32;
 }
 
@@ -302,6 +476,17 @@ hipError_t hvp_launch(md_ctx *c, const void *qsrc, const void *wsrc, dim3 grid, 
 // ADJ_PREPW), i.e. `pos` and `w` must be the arrays those operands came from.
 hipError_t launch_hvp_pair(md_ctx *c, const double *pos, const double *w)
 {
+    if (hvp_sym(c)) {
+        const int npad = (int)c->npad, ntile = npad / kSymTile;
+        const int nblocks = ntile * (ntile - 1) / 2 + ntile;
+        const int ts = timed_begin(c, "k_hvp_sym");
+        hipLaunchKernelGGL(k_hvp_sym, dim3((unsigned)nblocks), dim3(kSymWaves * kWave), 0, c->stream,
+                           static_cast<const double *>(c->ops), static_cast<const double *>(c->wops), (int)c->n, npad,
+                           ntile, c->eps, c->part);
+        const hipError_t err = hipGetLastError();
+        timed_end(c, ts);
+        return err;
+    }
     const Tiles &t = c->tiles;
     const int n = (int)c->n;
     const int per_block = kWave * t.ipl * t.waves;
@@ -324,20 +509,23 @@ hipError_t launch_adj_update(md_ctx *c, int flags, double h, double h2, double a
                              double *out, const double *pos)
 {
     const int n = (int)c->n;
-    const dim3 block(256), grid((unsigned)((n + 255) / 256));
+    const bool sym = hvp_sym(c);
+    const int nthreads = sym && (flags & (ADJ_PREPQ | ADJ_PREPW)) ? (int)c->npad : n;  // the pads too
+    const dim3 block(256), grid((unsigned)((nthreads + 255) / 256));
     // Hessian prefactors: 2/N (2D); 1/(2 sqrt2 N) (Ring, FP64 terms); 1/N (Ring, half-angle FP32 terms)
     const double pref = c->model == MD_GRAV2D ? 2.0 / (double)n
                         : c->prec == MD_FP64  ? 1.0 / (2.0 * 1.4142135623730951 * (double)n)
                                               : 1.0 / (double)n;
     const int pk = prep_kind(c);
-    if (c->prec == MD_FP64) flags &= ~ADJ_PREPW;
+    if (c->prec == MD_FP64 && !sym) flags &= ~ADJ_PREPW;
     if (pk == PREP_NONE) flags &= ~ADJ_PREPQ;
-    const int S = c->tiles.jsplit, npad = (int)c->npad;
+    const int npad = (int)c->npad, S = sym ? npad / kSymTile : c->tiles.jsplit;
 #define MD_ADJ(D_, P_)                                                                                          \
     hipLaunchKernelGGL((k_adj_update<D_, P_>), grid, block, 0, c->stream, c->part, S, n, npad, pref, flags, h, h2, a, \
                        lq, lp, out, pos, c->ops, c->wops)
     if (c->model == MD_GRAV2D) {
         if (pk == PREP_CAST32) MD_ADJ(2, PREP_CAST32);
+        else if (pk == PREP_COPY64) MD_ADJ(2, PREP_COPY64);
         else MD_ADJ(2, PREP_NONE);
     } else {
         if (pk == PREP_HALF32) MD_ADJ(1, PREP_HALF32);

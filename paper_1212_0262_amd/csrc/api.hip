@@ -76,6 +76,8 @@ Layout layout(int model, int prec, int64_t n)
         off = align_up(off + 2 * npad * sizeof(double));  // 2D FP64: the symmetric form's padded copy
     L.wops = off;
     if (model != MD_HMF && prec != MD_FP64) off = align_up(off + (size_t)dims(model) * npad * sizeof(float));
+    else if (model == MD_GRAV2D && sym_capable(model, prec, n))
+        off = align_up(off + 2 * npad * sizeof(double));  // 2D FP64: the symmetric product's padded vector
     L.part = off;
     if (model != MD_HMF) {
         size_t slots = (size_t)max_j_split(n);
@@ -747,7 +749,7 @@ int md_init(md_ctx **out, int model, int prec, int64_t n, double eps, void *hip_
     c->scal = reinterpret_cast<double *>(c->ws + L.scal);
     c->macc = (L.ops > L.macc) ? reinterpret_cast<long long *>(c->ws + L.macc) : nullptr;
     c->ops = (L.wops > L.ops) ? static_cast<void *>(c->ws + L.ops) : nullptr;
-    c->wops = (L.part > L.wops) ? reinterpret_cast<float *>(c->ws + L.wops) : nullptr;
+    c->wops = (L.part > L.wops) ? static_cast<void *>(c->ws + L.wops) : nullptr;
     c->part = (L.th32 > L.part) ? reinterpret_cast<double *>(c->ws + L.part) : nullptr;
     c->th32 = (L.p32 > L.th32) ? reinterpret_cast<float *>(c->ws + L.th32) : nullptr;
     c->p32 = (L.fops0 > L.p32) ? reinterpret_cast<float *>(c->ws + L.p32) : nullptr;

@@ -129,7 +129,8 @@ struct md_ctx {
     size_t ws_bytes = 0;
     // workspace carve-up
     void *ops = nullptr;      // pair operands: 2D [2][npad] FP32 copy; Ring [2][npad] cos,sin (FP32 or FP64)
-    float *wops = nullptr;    // FP32 copy of the Hessian-vector product's vector (mixed forms)
+    void *wops = nullptr;     // the Hessian-vector product's vector as operands: FP32 [d][npad] (mixed
+                              // forms), FP64 [2][npad] with pads (2D FP64, symmetric form)
     double *part = nullptr;   // pair partials [jsplit][d][npad]; symmetric form: [npad / kSymTile][d][npad]
     double *red = nullptr;    // reduction partials [kRedSlots]
     double *scal = nullptr;   // small device scalars (HMF magnetization, ...)

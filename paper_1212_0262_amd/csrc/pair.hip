@@ -201,9 +201,10 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 //     sums) or after every 64-j block through a small LDS buffer (the other
 //     accumulations), into slot a of the j particles.
 // Each particle thus receives one slot per tile and the update kernel adds them
-// in FP64 in the fixed order of slot_sums (device.h): no atomics.  The slots of MD_MIXED are
-// FP32 (the tile's sum rounded once: half the bytes the update reads back, for
-// a rounding below that of the FP32 partials themselves); the others are FP64.
+// in FP64 in the fixed order of slot_sums (device.h): no atomics.  The slots of
+// MD_MIXED are FP32 (the tile's sum rounded once: half the bytes the update reads
+// back, for a rounding below that of the FP32 partials themselves); the others
+// are FP64.  The tile pairs are numbered by sym_tile_pair (pair_terms.h).
 // Pad particles (n .. npad - 1) contribute nothing:
 //   2D FP32: at (1e30, 1e30): r^2 overflows to +inf for any pair with a pad
 //     particle, the reciprocal is 0 and both terms are exactly zero (a pad-pad
@@ -212,18 +213,6 @@ __global__ __launch_bounds__(256) void k_pair_win(const T *__restrict__ r0, cons
 //     reciprocal of +inf would be NaN), so a term with a pad particle is about
 //     5e-151, below the last bit of any force sum larger than 1e-135;
 //   Ring: operands (0, 0): the numerator p is exactly 0 and q finite.
-// Tile pair (a, b), a < b, of linear index t in row-major order over a.
-__device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
-{
-    auto row0 = [ntile](int r) { return r * (2 * ntile - r - 1) / 2; };  // first index of row r
-    const double m = 2.0 * ntile - 1.0;
-    int r = (int)((m - sqrt(m * m - 8.0 * t)) * 0.5);
-    r = max(0, min(r, ntile - 2));
-    while (r > 0 && row0(r) > t) --r;
-    while (r + 1 <= ntile - 2 && row0(r + 1) <= t) ++r;
-    a = r;
-    b = r + 1 + (t - row0(r));
-}
 
 // Slot type of the symmetric form with accumulator A.
 template <typename A>

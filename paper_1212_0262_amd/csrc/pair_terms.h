@@ -298,6 +298,19 @@ __device__ __forceinline__ void window_stream(const T *__restrict__ r0, const T 
 //   acc:      the i-side accumulators, [component][i].
 constexpr int kSymIpl = 4, kSymWaves = kSymTile / (kWave * kSymIpl);
 
+// Tile pair (a, b), a < b, of linear index t in row-major order over a.
+__device__ __forceinline__ void sym_tile_pair(int t, int ntile, int &a, int &b)
+{
+    auto row0 = [ntile](int r) { return r * (2 * ntile - r - 1) / 2; };  // first index of row r
+    const double m = 2.0 * ntile - 1.0;
+    int r = (int)((m - sqrt(m * m - 8.0 * t)) * 0.5);
+    r = max(0, min(r, ntile - 2));
+    while (r > 0 && row0(r) > t) --r;
+    while (r + 1 <= ntile - 2 && row0(r + 1) <= t) ++r;
+    a = r;
+    b = r + 1 + (t - row0(r));
+}
+
 // Operand value of a pad particle (beyond the system's or realization's end): its
 // pair terms vanish.  2D FP32: r^2 overflows to +inf, the reciprocal is 0 and the
 // terms exactly 0.  2D FP64: r^2 about 2e300 (the refined FP64 reciprocal of +inf

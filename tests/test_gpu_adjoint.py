@@ -58,6 +58,47 @@ def test_hvp_matches_oracle(model, eps, prec, n):
     check(f"hvp model={model} prec={prec} n={n}", rel_inf(hg, ho), hvp_tol(model, prec))
 
 
+@pytest.mark.parametrize("n,launch", [(2048, md.LAUNCH_SYMMETRIC), (3001, md.LAUNCH_SYMMETRIC),
+                                      (5003, md.LAUNCH_SYMMETRIC), (32768, md.LAUNCH_AUTO)])
+def test_hvp_symmetric_matches_oracle(n, launch):
+    """2D FP64 with the force in the symmetric form: the product takes it too (each
+    pair evaluated once for both particles, tile-pair slots added in a fixed order),
+    against the oracle and against the staged product; ragged sizes put pad particles
+    in the last tile.  N = 32768 is the adjoint workload's size, where the automatic
+    form is the symmetric one."""
+    q, _ = _state(GRAV2D, n, seed=90 + n)
+    w = np.random.default_rng(n + 3).normal(size=q.shape)
+    ho = oracle.hvp(GRAV2D, q, w, 1e-3)
+    ctx = md.md_init(GRAV2D, md.FP64, n, 1e-3)
+    md.md_set_launch(ctx, launch)
+    assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
+    hs = host(md.md_hvp(ctx, dev(q), dev(w)))
+    hs2 = host(md.md_hvp(ctx, dev(q), dev(w)))
+    np.testing.assert_array_equal(hs, hs2)                     # fixed order: repeatable bit for bit
+    md.md_set_launch(ctx, md.LAUNCH_STAGED)
+    hst = host(md.md_hvp(ctx, dev(q), dev(w)))
+    tol = hvp_tol(GRAV2D, md.FP64) * max(1.0, np.sqrt(n / 4096))
+    check(f"symmetric hvp n={n} vs oracle", rel_inf(hs, ho), tol)
+    check(f"symmetric hvp n={n} vs staged", rel_inf(hs, hst), tol)
+
+
+def test_step_vjp_symmetric_matches_oracle():
+    """The reverse sweep with the symmetric product (2D FP64, forced symmetric form,
+    a ragged size) against the oracle's."""
+    n, nst, eps, dt = 2500, 6, 1e-3, 0.01
+    q0, p0 = _state(GRAV2D, n, seed=64)
+    rng = np.random.default_rng(10)
+    lq0, lp0 = rng.normal(size=q0.shape), rng.normal(size=p0.shape)
+    oq, op = oracle.step_vjp(GRAV2D, q0, p0, dt, nst, lq0, lp0, eps)
+    ctx = md.md_init(GRAV2D, md.FP64, n, eps)
+    md.md_set_launch(ctx, md.LAUNCH_SYMMETRIC)
+    lq, lp = dev(lq0), dev(lp0)
+    md.md_step_vjp(ctx, dev(q0), dev(p0), dt, nst, lq, lp)
+    eq, ep = rel_inf(host(lq), oq), rel_inf(host(lp), op)
+    print(f"symmetric vjp rel_err q={eq:.3e} p={ep:.3e}")
+    assert eq < 1e-9 and ep < 1e-9
+
+
 @pytest.mark.parametrize("n", [1, 2, 65, 1001, 5003])
 @pytest.mark.parametrize("prec", [md.FP64, md.MIXED_F32STATE])
 def test_hmf_hvp_matches_oracle(prec, n):
