@@ -54,7 +54,15 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (FMA = 2 flops)
 PEAK_FP64_TFLOPS = 78.6
 SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9   # 1024 SIMDs at 2.4 GHz
 LAUNCH_NAMES = {1: "staged", 2: "fused", 3: "symmetric"}
-SYM_TILE = 1024              # particles per tile of the symmetric form
+SYM_TILE = 1024              # particles per tile of the symmetric form of ensembles (single systems:
+                             # md_get_sym_tile, 512 or 1024)
+
+
+def sym_counts(n, tile):
+    """Tile pairs' and diagonal tiles' evaluations of one symmetric launch over n
+    particles in tiles of `tile` (n padded to a multiple of 1024)."""
+    nt = -(-n // 1024) * 1024 // tile
+    return nt * (nt - 1) // 2 * tile ** 2, nt * tile ** 2
 SYM_FLOPS_PER_EVAL = 14      # symmetric form, per pair evaluated: 2 sub, 2 FMA (r^2), 2 FMA (i side), 2 FMA (j side)
 PAIR_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("pair.hip", "pair_terms.h", "device.h")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "grav2d_pair_mixed_n262144_pmc.txt")
@@ -138,7 +146,7 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup, launch=None):
         "E0": e0.tolist(), "E1": e1.tolist(),
         "dE_E": abs(e1[2] - e0[2]) / abs(e0[2]),
         "dE_KV": abs(e1[2] - e0[2]) / (abs(e0[0]) + abs(e0[1])),
-        "tiles": list(tiles), "launch": launch, "final_q": q, "final_p": p,
+        "tiles": list(tiles), "launch": launch, "sym_tile": md.md_get_sym_tile(ctx), "final_q": q, "final_p": p,
     }
 
 
@@ -664,8 +672,7 @@ def adjoint_workload(md, torch, args):
     k_ms, k_n, k_name = md.md_timing_end(ctx)
     k_s = k_ms / max(k_n, 1) * 1e-3
     if k_name == "k_hvp_sym":
-        nt = -(-ADJ_N // SYM_TILE)
-        tile_pair_evals, diag_evals = nt * (nt - 1) // 2 * SYM_TILE ** 2, nt * SYM_TILE ** 2
+        tile_pair_evals, diag_evals = sym_counts(ADJ_N, md.md_get_sym_tile(ctx))
         flops = ADJ_HVP_SYM_FLOPS * tile_pair_evals + ADJ_HVP_FLOPS * diag_evals
         per = {"tile_pair_evaluations_per_launch": tile_pair_evals, "diagonal_evaluations_per_launch": diag_evals,
                "flops_per_tile_pair_evaluation": ADJ_HVP_SYM_FLOPS, "flops_per_diagonal_evaluation": ADJ_HVP_FLOPS}
@@ -889,13 +896,11 @@ def grav2d_workload(md, torch, args):
         # one launch per evaluation: each pair of two different tiles evaluated once for both
         # particles (14 flops), every ordered pair of a diagonal tile for its i side (10 flops,
         # the pads' included); it covers all N^2 interactions
-        nt = -(-N // SYM_TILE)
         units = N * N
-        evals_pairs = nt * (nt - 1) // 2 * SYM_TILE ** 2
-        evals_diag = nt * SYM_TILE ** 2
+        evals_pairs, evals_diag = sym_counts(N, mixed["sym_tile"])
         evals = evals_pairs + evals_diag
         executed = SYM_FLOPS_PER_EVAL * evals_pairs + FLOPS_PER_PAIR * evals_diag
-        kernel = "k_sym<2, float, AccTile> (tile pairs and diagonal tiles)"
+        kernel = f"k_sym<2, float, AccTile, {mixed['sym_tile'] // 256}> (tile pairs and diagonal tiles)"
         instr = {"valu_fp32": 8, "trans": 1, "per": "pair of a tile pair evaluated (both particles); "
                  "diagonal tiles 6 + 1 per ordered pair"}
     else:

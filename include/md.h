@@ -232,13 +232,20 @@ int md_max_j_split(int64_t n);
  * md_get_launch returns the form md_step will take (STAGED, FUSED or
  * SYMMETRIC), or a negative status.  HMF contexts are always STAGED, ensembles
  * STAGED or SYMMETRIC.
+ * md_get_sym_tile returns the particles per tile of the symmetric form when
+ * md_get_launch is SYMMETRIC (1024, or 512 for single systems up to 32768 (2D
+ * MD_MIXED, MD_FP64), 65536 (2D compensated forms) or 131072 (Ring) particles:
+ * more, shorter tile pairs where they are few), else 0; a negative status for a
+ * null context.  The force then evaluates T (T - 1) / 2 tile pairs of T^2 pairs
+ * each and T diagonal tiles of T^2 ordered pairs, T = the padded n over the tile.
  */
 enum md_launch { MD_LAUNCH_AUTO = 0, MD_LAUNCH_STAGED = 1, MD_LAUNCH_FUSED = 2, MD_LAUNCH_SYMMETRIC = 3 };
-#define MD_SYMMETRIC_AUTO_N 28672
-#define MD_SYMMETRIC_AUTO_N_RING 28672
-#define MD_SYMMETRIC_AUTO_N_RING64 20480
+#define MD_SYMMETRIC_AUTO_N 20480
+#define MD_SYMMETRIC_AUTO_N_RING 20480
+#define MD_SYMMETRIC_AUTO_N_RING64 18432
 int md_set_launch(md_ctx *c, int mode);
 int md_get_launch(const md_ctx *c);
+int md_get_sym_tile(const md_ctx *c);
 
 /*
  * f = -dV/dq at positions q (eqs. 6-9 and the 2D gradient of eq. 3).

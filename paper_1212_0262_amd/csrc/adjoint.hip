@@ -226,12 +226,12 @@ __global__ __launch_bounds__(256) void k_hvp_ring(const T *__restrict__ cs, cons
 //   load(blk, xj, yj, wxj, wyj): this lane's j of 64-j block blk (lane l: j = l);
 //   jsum(blk, m, sj): the j-side sums of the block (sj belongs to j = m of it);
 //   acc: the i-side sums, [component][i].
-template <bool SYM, bool SHARE, typename Load, typename JSum>
+template <int TILE, bool SYM, bool SHARE, typename Load, typename JSum>
 __device__ __forceinline__ void sym_tile_hvp(const double (&x)[kSymIpl], const double (&y)[kSymIpl],
                                              const double (&wx)[kSymIpl], const double (&wy)[kSymIpl], double e,
                                              int lane, Load &&load, JSum &&jsum, AccF64 (&acc)[2][kSymIpl])
 {
-    constexpr int nblk = kSymTile / kWave;
+    constexpr int nblk = TILE / kWave;
     const int next = ((lane + 1) & (kWave - 1)) * 4;  // ds_bpermute byte address of lane l + 1
     double n0, n1, n2, n3;
     load(0, n0, n1, n2, n3);
@@ -292,16 +292,18 @@ __device__ __forceinline__ void sym_tile_hvp(const double (&x)[kSymIpl], const d
 }
 
 // One block's share of the symmetric product: tile pair (a, b) (SYM) or the diagonal
-// tile a = b.  q, w: [2][npad] operand rows (padded); part: slots [ntile][2][npad],
-// the i side to slot b of the i particles, the j side (the 4 wavefronts' sums added
-// in FP64 in a fixed order after every 64-j block) to slot a of the j particles.
-template <bool SYM>
+// tile a = b, tiles of W x 64 x 4 particles (the force's, sym_tile_n).  q, w:
+// [2][npad] operand rows (padded); part: slots [ntile][2][npad], the i side to slot
+// b of the i particles, the j side (the W wavefronts' sums added in FP64 in a
+// fixed order after every 64-j block) to slot a of the j particles.
+template <bool SYM, int W>
 __device__ __forceinline__ void hvp_sym_block(const double *__restrict__ q, const double *__restrict__ w, int n,
-                                              int npad, int ntile, double e, double *__restrict__ part, int a, int b,
-                                              double (&jw)[kSymWaves][2][kWave])
+                                              int npad, double e, double *__restrict__ part, int a, int b,
+                                              double (&jw)[W][2][kWave])
 {
+    constexpr int TILE = W * kWave * kSymIpl;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int i0 = a * kSymTile + wave * kWave * kSymIpl + lane;
+    const int i0 = a * TILE + wave * kWave * kSymIpl + lane;
     double x[kSymIpl], y[kSymIpl], wx[kSymIpl], wy[kSymIpl];
 #pragma unroll
     for (int k = 0; k < kSymIpl; ++k) {
@@ -311,7 +313,7 @@ __device__ __forceinline__ void hvp_sym_block(const double *__restrict__ q, cons
         wx[k] = w[i];
         wy[k] = w[npad + i];
     }
-    const int jl = b * kSymTile + lane;
+    const int jl = b * TILE + lane;
     auto load = [&](int blk, double &xj, double &yj, double &wxj, double &wyj) {
         const int j = jl + blk * kWave;
         xj = q[j];
@@ -327,16 +329,16 @@ __device__ __forceinline__ void hvp_sym_block(const double *__restrict__ q, cons
             const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
             double t = 0.0;
 #pragma unroll
-            for (int v = 0; v < kSymWaves; ++v) t += jw[v][d][mm];
-            part[(size_t)(2 * a + d) * npad + b * kSymTile + blk * kWave + mm] = t;
+            for (int v = 0; v < W; ++v) t += jw[v][d][mm];
+            part[(size_t)(2 * a + d) * npad + b * TILE + blk * kWave + mm] = t;
         }
         __syncthreads();
     };
     AccF64 acc[2][kSymIpl];
-    if (b == ntile - 1 && n < npad)
-        sym_tile_hvp<SYM, false>(x, y, wx, wy, e, lane, load, jsum, acc);
+    if ((b + 1) * TILE > n)  // a j tile with pads: one reciprocal a pair
+        sym_tile_hvp<TILE, SYM, false>(x, y, wx, wy, e, lane, load, jsum, acc);
     else
-        sym_tile_hvp<SYM, true>(x, y, wx, wy, e, lane, load, jsum, acc);
+        sym_tile_hvp<TILE, SYM, true>(x, y, wx, wy, e, lane, load, jsum, acc);
 #pragma unroll
     for (int k = 0; k < kSymIpl; ++k)
 #pragma unroll
@@ -345,18 +347,19 @@ __device__ __forceinline__ void hvp_sym_block(const double *__restrict__ q, cons
 
 // One launch per product: the tile pairs a < b in row-major order, then the diagonal
 // tiles (the force's order, k_sym in pair.hip).
-__global__ __launch_bounds__(kSymWaves * kWave) void k_hvp_sym(const double *__restrict__ q,
-                                                               const double *__restrict__ w, int n, int npad,
-                                                               int ntile, double e, double *__restrict__ part)
+template <int W>
+__global__ __launch_bounds__(W * kWave) void k_hvp_sym(const double *__restrict__ q, const double *__restrict__ w,
+                                                       int n, int npad, int ntile, double e,
+                                                       double *__restrict__ part)
 {
-    __shared__ double jw[kSymWaves][2][kWave];
+    __shared__ double jw[W][2][kWave];
     const int t = (int)blockIdx.x, noff = ntile * (ntile - 1) / 2;
     if (t < noff) {
         int a, b;
         sym_tile_pair(t, ntile, a, b);
-        hvp_sym_block<true>(q, w, n, npad, ntile, e, part, a, b, jw);
+        hvp_sym_block<true, W>(q, w, n, npad, e, part, a, b, jw);
     } else {
-        hvp_sym_block<false>(q, w, n, npad, ntile, e, part, t - noff, t - noff, jw);
+        hvp_sym_block<false, W>(q, w, n, npad, e, part, t - noff, t - noff, jw);
     }
 }
 
@@ -477,12 +480,16 @@ hipError_t hvp_launch(md_ctx *c, const void *qsrc, const void *wsrc, dim3 grid, 
 hipError_t launch_hvp_pair(md_ctx *c, const double *pos, const double *w)
 {
     if (hvp_sym(c)) {
-        const int npad = (int)c->npad, ntile = npad / kSymTile;
+        const int npad = (int)c->npad, tile = sym_tile_n(c->model, c->prec, c->n), ntile = npad / tile;
         const int nblocks = ntile * (ntile - 1) / 2 + ntile;
+        const double *q = static_cast<const double *>(c->ops), *w = static_cast<const double *>(c->wops);
         const int ts = timed_begin(c, "k_hvp_sym");
-        hipLaunchKernelGGL(k_hvp_sym, dim3((unsigned)nblocks), dim3(kSymWaves * kWave), 0, c->stream,
-                           static_cast<const double *>(c->ops), static_cast<const double *>(c->wops), (int)c->n, npad,
-                           ntile, c->eps, c->part);
+        if (tile == kSymTile)
+            hipLaunchKernelGGL(k_hvp_sym<4>, dim3((unsigned)nblocks), dim3(4 * kWave), 0, c->stream, q, w, (int)c->n,
+                               npad, ntile, c->eps, c->part);
+        else
+            hipLaunchKernelGGL(k_hvp_sym<2>, dim3((unsigned)nblocks), dim3(2 * kWave), 0, c->stream, q, w, (int)c->n,
+                               npad, ntile, c->eps, c->part);
         const hipError_t err = hipGetLastError();
         timed_end(c, ts);
         return err;
@@ -519,7 +526,7 @@ hipError_t launch_adj_update(md_ctx *c, int flags, double h, double h2, double a
     const int pk = prep_kind(c);
     if (c->prec == MD_FP64 && !sym) flags &= ~ADJ_PREPW;
     if (pk == PREP_NONE) flags &= ~ADJ_PREPQ;
-    const int npad = (int)c->npad, S = sym ? npad / kSymTile : c->tiles.jsplit;
+    const int npad = (int)c->npad, S = sym ? npad / sym_tile_n(c->model, c->prec, c->n) : c->tiles.jsplit;
 #define MD_ADJ(D_, P_)                                                                                          \
     hipLaunchKernelGGL((k_adj_update<D_, P_>), grid, block, 0, c->stream, c->part, S, n, npad, pref, flags, h, h2, a, \
                        lq, lp, out, pos, c->ops, c->wops)

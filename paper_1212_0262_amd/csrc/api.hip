@@ -81,7 +81,7 @@ Layout layout(int model, int prec, int64_t n)
     L.part = off;
     if (model != MD_HMF) {
         size_t slots = (size_t)max_j_split(n);
-        if (sym_capable(model, prec, n)) slots = std::max(slots, npad / kSymTile);
+        if (sym_capable(model, prec, n)) slots = std::max(slots, npad / (size_t)sym_tile_n(model, prec, n));
         off = align_up(off + slots * dims(model) * npad * sizeof(double));
     }
     L.th32 = off;
@@ -570,6 +570,21 @@ hipError_t upload_lists(md_ctx *c)
 
 int64_t pad_n(int64_t n) { return (n + kSymTile - 1) / kSymTile * kSymTile; }
 
+// Tiles of 512 (2 wavefronts a block) in the symmetric form of single systems up to
+// a size per model and precision: a block's tile pair is a serial unit of work (one
+// block holds its tile's i for the whole j tile), so with few tile pairs the
+// launch is as long as a block's round; half-size tiles give four times the tile
+// pairs at half the length each.  Measured md_step against 1024-tiles, us per
+// step (MI355X): 2D mixed 342.7 / 454.9 at N = 24,576, 523 / 562 at 32,768, 1005 /
+// 955 at 49,152; 2D FP64 588 / 729, 842 / 931, 1735 / 1740; 2D Kahan 829 / 944 at
+// 32,768, 2747 / 2800 at 65,536, 6037 / 5954 at 98,304; Ring mixed 1802 / 1919 at
+// 65,536, 6653 / 6710 at 131,072; Ring FP64 3479 / 3646 and 13,304 / 13,403.
+int sym_tile_n(int model, int prec, int64_t n)
+{
+    const int64_t small = model == MD_RING ? 131072 : (prec == MD_MIXED || prec == MD_FP64) ? 32768 : 65536;
+    return n <= small ? kSymTileSmall : kSymTile;
+}
+
 int launch_form(const md_ctx *c) { return form_of(c); }
 
 int dims(int model) { return model == MD_GRAV2D ? 2 : 1; }
@@ -915,6 +930,13 @@ int md_get_launch(const md_ctx *c)
     if (!c) return MD_EINVAL;
     if (c->model == MD_HMF) return MD_LAUNCH_STAGED;
     return form_of(c);
+}
+
+int md_get_sym_tile(const md_ctx *c)
+{
+    if (!c) return MD_EINVAL;
+    if (c->model == MD_HMF || form_of(c) != MD_LAUNCH_SYMMETRIC) return 0;
+    return c->batch ? kSymTile : sym_tile_n(c->model, c->prec, c->n);
 }
 
 int md_get_tiles(const md_ctx *c, int *out4)

@@ -223,29 +223,31 @@ using sym_slot_t = std::conditional_t<std::is_same_v<A, AccTile>, float, double>
 // 64-j block (a Kahan sum's value carries its compensation: FP32 would drop it).
 template <typename A>
 constexpr bool kJW32 = std::is_same_v<A, AccTile>;
-// The block's LDS for the j-side sums of a tile pair (one of the two arrays is in
-// use: a union, so the unused one adds no bytes to the block's LDS, which sets how
-// many blocks a CU holds).
-template <int D, typename A>
+// The block's LDS for the j-side sums of a tile pair of W wavefronts (one of the
+// two arrays is in use: a union, so the unused one adds no bytes to the block's
+// LDS, which sets how many blocks a CU holds).
+template <int D, typename A, int W>
 union SymLds {
-    float jw32[kJW32<A> ? kSymWaves : 1][D][kJW32<A> ? kSymTile : 1];
-    double jw64[kJW32<A> ? 1 : kSymWaves][D][kJW32<A> ? 1 : kWave];
+    float jw32[kJW32<A> ? W : 1][D][kJW32<A> ? W * kWave * kSymIpl : 1];
+    double jw64[kJW32<A> ? 1 : W][D][kJW32<A> ? 1 : kWave];
 };
 
 // One block's share of a symmetric force evaluation: the tile pair (a, b), a < b
-// (SYM), or the diagonal tile a = b.  r0, r1: the operand rows ([2][npad],
+// (SYM), or the diagonal tile a = b, of tiles of W x 64 x 4 particles (W = 4: the
+// 1024 of kSymTile; W = 2: 512 for smaller n, sym_tile_n in api.hip).  r0, r1: the operand rows ([2][npad],
 // padded); part: slots [ntile][D][npad] of sym_slot_t<A>.
-template <int MODEL, typename T, typename A, bool SYM>
+template <int MODEL, typename T, typename A, bool SYM, int W>
 __device__ __forceinline__ void sym_block(const T *__restrict__ r0, const T *__restrict__ r1, int n, int npad,
-                                          int ntile, T e, sym_slot_t<A> *__restrict__ part, int a, int b,
-                                          SymLds<MODEL == MD_GRAV2D ? 2 : 1, A> &lds)
+                                          T e, sym_slot_t<A> *__restrict__ part, int a, int b,
+                                          SymLds<MODEL == MD_GRAV2D ? 2 : 1, A, W> &lds)
 {
     constexpr bool JW32 = kJW32<A>;
     constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
+    constexpr int TILE = W * kWave * kSymIpl;
     auto &jw32 = lds.jw32;
     auto &jw64 = lds.jw64;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int i0 = a * kSymTile + wave * kWave * kSymIpl + lane;
+    const int i0 = a * TILE + wave * kWave * kSymIpl + lane;
     T u0[kSymIpl], u1[kSymIpl];
     A acc[D][kSymIpl];
 #pragma unroll
@@ -253,7 +255,7 @@ __device__ __forceinline__ void sym_block(const T *__restrict__ r0, const T *__r
         u0[k] = r0[i0 + k * kWave];
         u1[k] = r1[i0 + k * kWave];
     }
-    const int jl = b * kSymTile + lane;
+    const int jl = b * TILE + lane;
     auto load = [&](int blk, T &v0, T &v1) {
         v0 = r0[jl + blk * kWave];
         v1 = r1[jl + blk * kWave];
@@ -270,35 +272,35 @@ __device__ __forceinline__ void sym_block(const T *__restrict__ r0, const T *__r
                 const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
                 double t = 0.0;
 #pragma unroll
-                for (int w = 0; w < kSymWaves; ++w) t += jw64[w][d][mm];
-                part[(size_t)(D * a + d) * npad + b * kSymTile + blk * kWave + mm] = (sym_slot_t<A>)t;
+                for (int w = 0; w < W; ++w) t += jw64[w][d][mm];
+                part[(size_t)(D * a + d) * npad + b * TILE + blk * kWave + mm] = (sym_slot_t<A>)t;
             }
             __syncthreads();
         }
     };
-    // 2D FP64: one reciprocal for two pairs (SHARE), except in the last tile, which
-    // holds the pads (b is never below a).  Measured at N = 262,144: 16.36 -> 14.76
-    // ms per force evaluation.  The FP32 forms keep one reciprocal a pair: there
-    // the shared form measured 1.5% slower (7.35 -> 7.45 ms), its three multiplies
-    // costing about what the FP32 reciprocal does
+    // 2D FP64: one reciprocal for two pairs (SHARE), except in a j tile that holds
+    // pads (b is never below a).  Measured at N = 262,144: 16.36 -> 14.76 ms per
+    // force evaluation.  The FP32 forms keep one reciprocal a pair: there the shared
+    // form measured 1.5% slower (7.35 -> 7.45 ms), its three multiplies costing
+    // about what the FP32 reciprocal does
     constexpr bool kShare = MODEL == MD_GRAV2D && sizeof(T) == 8;
-    if (!kShare || (b == ntile - 1 && n < npad))
-        sym_tile<MODEL, T, A, SYM, false>(u0, u1, e, lane, kSymTile / kWave, load, jsum, acc);
+    if (!kShare || (b + 1) * TILE > n)
+        sym_tile<MODEL, T, A, SYM, false>(u0, u1, e, lane, TILE / kWave, load, jsum, acc);
     else
-        sym_tile<MODEL, T, A, SYM, kShare>(u0, u1, e, lane, kSymTile / kWave, load, jsum, acc);
+        sym_tile<MODEL, T, A, SYM, kShare>(u0, u1, e, lane, TILE / kWave, load, jsum, acc);
 #pragma unroll
     for (int k = 0; k < kSymIpl; ++k)
 #pragma unroll
         for (int d = 0; d < D; ++d) part[(size_t)(D * b + d) * npad + i0 + k * kWave] = (sym_slot_t<A>)acc[d][k].get();
     if constexpr (SYM && JW32) {
         __syncthreads();
-        for (int m = threadIdx.x; m < kSymTile; m += kSymWaves * kWave) {
+        for (int m = threadIdx.x; m < TILE; m += W * kWave) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 double t = 0.0;
 #pragma unroll
-                for (int w = 0; w < kSymWaves; ++w) t += (double)jw32[w][d][m];
-                part[(size_t)(D * a + d) * npad + b * kSymTile + m] = (sym_slot_t<A>)t;
+                for (int w = 0; w < W; ++w) t += (double)jw32[w][d][m];
+                part[(size_t)(D * a + d) * npad + b * TILE + m] = (sym_slot_t<A>)t;
             }
         }
     }
@@ -309,18 +311,18 @@ __device__ __forceinline__ void sym_block(const T *__restrict__ r0, const T *__r
 // the last round.  Measured against two launches (tile pairs, then diagonal
 // tiles), 2D mixed: 7.28 -> 7.24 ms at N = 262,144 and 0.652 -> 0.613 ms at 65,536
 // (the diagonal tiles' separate launch was one latency-bound round of T blocks).
-template <int MODEL, typename T, typename A>
-__global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1, int n,
-                                                           int npad, int ntile, T e, sym_slot_t<A> *__restrict__ part)
+template <int MODEL, typename T, typename A, int W>
+__global__ __launch_bounds__(W * kWave) void k_sym(const T *__restrict__ r0, const T *__restrict__ r1, int n, int npad,
+                                                   int ntile, T e, sym_slot_t<A> *__restrict__ part)
 {
-    __shared__ SymLds<MODEL == MD_GRAV2D ? 2 : 1, A> lds;
+    __shared__ SymLds<MODEL == MD_GRAV2D ? 2 : 1, A, W> lds;
     const int t = (int)blockIdx.x, noff = ntile * (ntile - 1) / 2;
     if (t < noff) {
         int a, b;
         sym_tile_pair(t, ntile, a, b);
-        sym_block<MODEL, T, A, true>(r0, r1, n, npad, ntile, e, part, a, b, lds);
+        sym_block<MODEL, T, A, true, W>(r0, r1, n, npad, e, part, a, b, lds);
     } else {
-        sym_block<MODEL, T, A, false>(r0, r1, n, npad, ntile, e, part, t - noff, t - noff, lds);
+        sym_block<MODEL, T, A, false, W>(r0, r1, n, npad, e, part, t - noff, t - noff, lds);
     }
 }
 
@@ -330,15 +332,18 @@ __global__ __launch_bounds__(kSymWaves * kWave) void k_sym(const T *__restrict__
 template <int MODEL, typename T, typename A>
 hipError_t sym_launch(md_ctx *c)
 {
-    const int npad = (int)c->npad, ntile = npad / kSymTile;
+    const int npad = (int)c->npad, tile = sym_tile_n(c->model, c->prec, c->n), ntile = npad / tile;
     const T *ops = static_cast<const T *>(c->ops);
     const T e = MODEL == MD_GRAV2D ? (T)c->eps : sizeof(T) == 4 ? (T)(2.0 * c->eps) : (T)(1.0 + c->eps);
-    const dim3 block(kSymWaves * kWave);
     const int nblk = ntile * (ntile - 1) / 2 + ntile;  // tile pairs, then diagonal tiles
     sym_slot_t<A> *slots = reinterpret_cast<sym_slot_t<A> *>(c->part);
     const int ts = timed_begin(c, MODEL == MD_GRAV2D ? "k_sym (2D)" : "k_sym (Ring)");
-    hipLaunchKernelGGL((k_sym<MODEL, T, A>), dim3((unsigned)nblk), block, 0, c->stream, ops, ops + npad, (int)c->n,
-                       npad, ntile, e, slots);
+    if (tile == kSymTile)
+        hipLaunchKernelGGL((k_sym<MODEL, T, A, 4>), dim3((unsigned)nblk), dim3(4 * kWave), 0, c->stream, ops,
+                           ops + npad, (int)c->n, npad, ntile, e, slots);
+    else
+        hipLaunchKernelGGL((k_sym<MODEL, T, A, 2>), dim3((unsigned)nblk), dim3(2 * kWave), 0, c->stream, ops,
+                           ops + npad, (int)c->n, npad, ntile, e, slots);
     const hipError_t err = hipGetLastError();
     timed_end(c, ts);
     return err;
@@ -756,7 +761,7 @@ hipError_t update(md_ctx *c, int flags, double kick1, double kick2, double drift
     const int n = (int)c->n;
     const double pref = force_prefactor(c->model, c->prec, n);
     const bool sym = !fused && launch_form(c) == MD_LAUNCH_SYMMETRIC;
-    const int S = sym ? (int)(c->npad / kSymTile) : c->tiles.jsplit;
+    const int S = sym ? (int)(c->npad / sym_tile_n(c->model, c->prec, c->n)) : c->tiles.jsplit;
     const bool slots32 = sym && c->prec == MD_MIXED;  // the symmetric form's FP32 slots (sym_slot_t)
     const int npad = (int)c->npad;
     const int pk = prep_kind(c, fused);

@@ -25,9 +25,9 @@ HMF, RING, GRAV2D = 0, 1, 2
 FP64, MIXED, MIXED_KAHAN, MIXED_PAIRF64, MIXED_F32STATE = 0, 1, 2, 3, 4
 OK, EINVAL, EDEVICE, ENOMEM, ESTATE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 LAUNCH_AUTO, LAUNCH_STAGED, LAUNCH_FUSED, LAUNCH_SYMMETRIC = 0, 1, 2, 3
-SYMMETRIC_AUTO_N = 28672  # MD_SYMMETRIC_AUTO_N: LAUNCH_AUTO takes the symmetric 2D form from this n
-SYMMETRIC_AUTO_N_RING = 28672    # MD_SYMMETRIC_AUTO_N_RING: the same for the Ring with the FP32 forms
-SYMMETRIC_AUTO_N_RING64 = 20480  # MD_SYMMETRIC_AUTO_N_RING64: the same for the Ring with FP64
+SYMMETRIC_AUTO_N = 20480  # MD_SYMMETRIC_AUTO_N: LAUNCH_AUTO takes the symmetric 2D form from this n
+SYMMETRIC_AUTO_N_RING = 20480    # MD_SYMMETRIC_AUTO_N_RING: the same for the Ring with the FP32 forms
+SYMMETRIC_AUTO_N_RING64 = 18432  # MD_SYMMETRIC_AUTO_N_RING64: the same for the Ring with FP64
 
 MODEL_NAMES = {HMF: "hmf", RING: "ring", GRAV2D: "grav2d"}
 PREC_NAMES = {FP64: "fp64", MIXED: "mixed", MIXED_KAHAN: "mixed_kahan",
@@ -48,6 +48,7 @@ SIGNATURES = {
     "md_get_tiles": (_I, [_V, ctypes.POINTER(_I)]),
     "md_set_launch": (_I, [_V, _I]),
     "md_get_launch": (_I, [_V]),
+    "md_get_sym_tile": (_I, [_V]),
     "md_max_j_split": (_I, [_I64]),
     "md_force": (_I, [_V, _V, _V]),
     "md_force_noalloc": (_I, [_I, _I, _I64, _D, _V, _V, _V]),
@@ -238,6 +239,13 @@ def md_get_launch(ctx: Context) -> int:
     """The form md_step takes: LAUNCH_STAGED, LAUNCH_FUSED or LAUNCH_SYMMETRIC."""
     r = int(load().md_get_launch(ctx.handle))
     ctx._check(min(r, 0), "md_get_launch")
+    return r
+
+
+def md_get_sym_tile(ctx: Context) -> int:
+    """Particles per tile of the symmetric form (1024 or 512) if md_step takes it, else 0."""
+    r = int(load().md_get_sym_tile(ctx.handle))
+    ctx._check(min(r, 0), "md_get_sym_tile")
     return r
 
 
