@@ -223,26 +223,27 @@ int md_max_j_split(int64_t n);
  *                     or 6144 (2D gravity) (the built-in tiles there are the
  *                     fused form's), symmetric
  *                     when it applies and n reaches the model's threshold
- *                     (MD_SYMMETRIC_AUTO_N for 2D gravity; for the Ring
- *                     MD_SYMMETRIC_AUTO_N_RING with the FP32 forms and
- *                     MD_SYMMETRIC_AUTO_N_RING64 with MD_FP64: measured
- *                     crossovers on MI355X), else staged;
+ *                     (MD_SYMMETRIC_AUTO_N for 2D gravity with MD_MIXED
+ *                     or MD_FP64, MD_SYMMETRIC_AUTO_N_COMP with the
+ *                     compensated forms; for the Ring MD_SYMMETRIC_AUTO_N_RING
+ *                     with the FP32 forms and MD_SYMMETRIC_AUTO_N_RING64 with
+ *                     MD_FP64: measured crossovers on MI355X), else staged;
  *                     for ensembles, symmetric when it applies and their tile
  *                     pairs a < b outnumber their diagonal tiles.
  * md_get_launch returns the form md_step will take (STAGED, FUSED or
  * SYMMETRIC), or a negative status.  HMF contexts are always STAGED, ensembles
  * STAGED or SYMMETRIC.
  * md_get_sym_tile returns the particles per tile of the symmetric form when
- * md_get_launch is SYMMETRIC (1024, or 512 for single systems up to 32768 (2D
- * MD_MIXED, MD_FP64), 65536 (2D compensated forms) or 131072 (Ring) particles:
- * more, shorter tile pairs where they are few), else 0; a negative status for a
- * null context.  The force then evaluates T (T - 1) / 2 tile pairs of T^2 pairs
+ * md_get_launch is SYMMETRIC (1024; for single systems 256 up to 65536
+ * particles and 512 for the Ring up to 131072: more, shorter tile pairs where
+ * they are few), else 0; a negative status for a null context.  The force then evaluates T (T - 1) / 2 tile pairs of T^2 pairs
  * each and T diagonal tiles of T^2 ordered pairs, T = the padded n over the tile.
  */
 enum md_launch { MD_LAUNCH_AUTO = 0, MD_LAUNCH_STAGED = 1, MD_LAUNCH_FUSED = 2, MD_LAUNCH_SYMMETRIC = 3 };
-#define MD_SYMMETRIC_AUTO_N 20480
-#define MD_SYMMETRIC_AUTO_N_RING 20480
-#define MD_SYMMETRIC_AUTO_N_RING64 18432
+#define MD_SYMMETRIC_AUTO_N 13312
+#define MD_SYMMETRIC_AUTO_N_COMP 15360
+#define MD_SYMMETRIC_AUTO_N_RING 13312
+#define MD_SYMMETRIC_AUTO_N_RING64 10240
 int md_set_launch(md_ctx *c, int mode);
 int md_get_launch(const md_ctx *c);
 int md_get_sym_tile(const md_ctx *c);

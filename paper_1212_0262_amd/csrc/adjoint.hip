@@ -325,8 +325,8 @@ __device__ __forceinline__ void hvp_sym_block(const double *__restrict__ q, cons
         jw[wave][0][m] = sj[0].get();
         jw[wave][1][m] = sj[1].get();
         __syncthreads();
-        if (threadIdx.x < 2 * kWave) {
-            const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
+        for (int x = threadIdx.x; x < 2 * kWave; x += W * kWave) {  // W = 1: a thread per (d, j) in turn
+            const int d = x / kWave, mm = x & (kWave - 1);
             double t = 0.0;
 #pragma unroll
             for (int v = 0; v < W; ++v) t += jw[v][d][mm];
@@ -487,8 +487,11 @@ hipError_t launch_hvp_pair(md_ctx *c, const double *pos, const double *w)
         if (tile == kSymTile)
             hipLaunchKernelGGL(k_hvp_sym<4>, dim3((unsigned)nblocks), dim3(4 * kWave), 0, c->stream, q, w, (int)c->n,
                                npad, ntile, c->eps, c->part);
-        else
+        else if (tile == kSymTileSmall)
             hipLaunchKernelGGL(k_hvp_sym<2>, dim3((unsigned)nblocks), dim3(2 * kWave), 0, c->stream, q, w, (int)c->n,
+                               npad, ntile, c->eps, c->part);
+        else
+            hipLaunchKernelGGL(k_hvp_sym<1>, dim3((unsigned)nblocks), dim3(kWave), 0, c->stream, q, w, (int)c->n,
                                npad, ntile, c->eps, c->part);
         const hipError_t err = hipGetLastError();
         timed_end(c, ts);

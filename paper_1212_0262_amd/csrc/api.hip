@@ -570,19 +570,28 @@ hipError_t upload_lists(md_ctx *c)
 
 int64_t pad_n(int64_t n) { return (n + kSymTile - 1) / kSymTile * kSymTile; }
 
-// Tiles of 512 (2 wavefronts a block) in the symmetric form of single systems up to
-// a size per model and precision: a block's tile pair is a serial unit of work (one
-// block holds its tile's i for the whole j tile), so with few tile pairs the
-// launch is as long as a block's round; half-size tiles give four times the tile
-// pairs at half the length each.  Measured md_step against 1024-tiles, us per
-// step (MI355X): 2D mixed 342.7 / 454.9 at N = 24,576, 523 / 562 at 32,768, 1005 /
-// 955 at 49,152; 2D FP64 588 / 729, 842 / 931, 1735 / 1740; 2D Kahan 829 / 944 at
-// 32,768, 2747 / 2800 at 65,536, 6037 / 5954 at 98,304; Ring mixed 1802 / 1919 at
-// 65,536, 6653 / 6710 at 131,072; Ring FP64 3479 / 3646 and 13,304 / 13,403.
+// Smaller tiles in the symmetric form of single systems below a size: a block's
+// tile pair is a serial unit of work (its wavefronts hold their i for the whole j
+// tile), so with few tile pairs the launch is as long as a block's round.  Tiles
+// of 256 (one wavefront a block) give 16 times the tile pairs of 1024-tiles at a
+// sixteenth of the work each, tiles of 512 (two wavefronts) four times.  Measured
+// md_step, us per step (MI355X), 256- / 512- / 1024-tiles where measured:
+//   2D mixed: N = 32,768 419 / 480 / 562; 49,152 842 / 1005 / 933; 65,536 1434 /
+//     1613 / 1509; 98,304 3195 / 3218 / 3174;
+//   2D FP64: 32,768 788 / 821 / 931; 65,536 2930 / 2943 / 2978; 98,304 6639 / 6376 /
+//     6392;
+//   2D Kahan: 49,152 1586 / 1705 / 1780; 65,536 2747 / 2754 / 2800; 98,304 6227 / -
+//     / 6009;
+//   Ring mixed: 49,152 1001 / 1090 / 1154; 131,072 6563 / 6651 / 6710; 196,608
+//     14,736 / - / 14,596;
+//   Ring FP64: 65,536 3464 / 3532 / 3646; 98,304 7677 / 7649 / 7709; 131,072 13,597
+//     / 13,459 / 13,403 (the 1024 figure from another box);
+//   Ring Kahan: 65,536 2262 / 2319 / -; 131,072 8849 / 8741 / -.
 int sym_tile_n(int model, int prec, int64_t n)
 {
-    const int64_t small = model == MD_RING ? 131072 : (prec == MD_MIXED || prec == MD_FP64) ? 32768 : 65536;
-    return n <= small ? kSymTileSmall : kSymTile;
+    (void)prec;
+    if (n <= 65536) return 256;
+    return model == MD_RING && n <= 131072 ? kSymTileSmall : kSymTile;
 }
 
 int launch_form(const md_ctx *c) { return form_of(c); }

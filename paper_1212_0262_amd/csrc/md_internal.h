@@ -54,13 +54,15 @@ constexpr int kFusedLdsBytes = 49152;   // LDS per fused block (split evenly bet
 constexpr int64_t kFusedAutoN = 4096;   // MD_LAUNCH_AUTO takes the fused form up to this n (Ring)
 constexpr int64_t kFusedAutoN2D = 6144; // ... and up to this n for 2D gravity
 constexpr int kSymTile = 1024;          // particles per tile of the symmetric form (4 waves x 64 x 4 i)
-constexpr int kSymTileSmall = 512;      // ... for smaller n (2 waves x 64 x 4 i; sym_tile_n)
+constexpr int kSymTileSmall = 512;      // ... for smaller n (2 waves x 64 x 4 i; sym_tile_n), and 256
+                                        // (1 wave) for smaller n still
 constexpr int64_t kSymMinN = 2048;      // the symmetric form needs two tiles at least
 constexpr int64_t kSymMaxN = 1 << 20;   // and at most 1024 tiles (its partial slots: 8 d n^2 / 1024 bytes)
 // MD_LAUNCH_AUTO takes the symmetric form from this n (measured crossovers)
 inline int64_t sym_auto_n(int model, int prec)
 {
-    if (model != MD_RING) return MD_SYMMETRIC_AUTO_N;
+    if (model != MD_RING)
+        return prec == MD_MIXED_KAHAN || prec == MD_MIXED_PAIRF64 ? MD_SYMMETRIC_AUTO_N_COMP : MD_SYMMETRIC_AUTO_N;
     return prec == MD_FP64 ? MD_SYMMETRIC_AUTO_N_RING64 : MD_SYMMETRIC_AUTO_N_RING;
 }
 
@@ -156,7 +158,7 @@ struct md_ctx {
 namespace md {
 
 int64_t pad_n(int64_t n);  // n rounded up to a multiple of kSymTile
-int sym_tile_n(int model, int prec, int64_t n);  // particles per tile of the symmetric form (512 or 1024)
+int sym_tile_n(int model, int prec, int64_t n);  // particles per tile of the symmetric form (256, 512, 1024)
 int dims(int model);
 // MD_LAUNCH_STAGED, MD_LAUNCH_FUSED or MD_LAUNCH_SYMMETRIC: the form the pair
 // stages of this context take now (launch mode, tiles and n).

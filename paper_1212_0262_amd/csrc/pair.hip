@@ -268,8 +268,8 @@ __device__ __forceinline__ void sym_block(const T *__restrict__ r0, const T *__r
 #pragma unroll
             for (int d = 0; d < D; ++d) jw64[wave][d][m] = sj[d].get();
             __syncthreads();
-            if (threadIdx.x < D * kWave) {
-                const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
+            for (int x = threadIdx.x; x < D * kWave; x += W * kWave) {  // W = 1: a thread per (d, j) in turn
+                const int d = x / kWave, mm = x & (kWave - 1);
                 double t = 0.0;
 #pragma unroll
                 for (int w = 0; w < W; ++w) t += jw64[w][d][mm];
@@ -341,8 +341,11 @@ hipError_t sym_launch(md_ctx *c)
     if (tile == kSymTile)
         hipLaunchKernelGGL((k_sym<MODEL, T, A, 4>), dim3((unsigned)nblk), dim3(4 * kWave), 0, c->stream, ops,
                            ops + npad, (int)c->n, npad, ntile, e, slots);
-    else
+    else if (tile == kSymTileSmall)
         hipLaunchKernelGGL((k_sym<MODEL, T, A, 2>), dim3((unsigned)nblk), dim3(2 * kWave), 0, c->stream, ops,
+                           ops + npad, (int)c->n, npad, ntile, e, slots);
+    else
+        hipLaunchKernelGGL((k_sym<MODEL, T, A, 1>), dim3((unsigned)nblk), dim3(kWave), 0, c->stream, ops,
                            ops + npad, (int)c->n, npad, ntile, e, slots);
     const hipError_t err = hipGetLastError();
     timed_end(c, ts);

@@ -25,9 +25,10 @@ HMF, RING, GRAV2D = 0, 1, 2
 FP64, MIXED, MIXED_KAHAN, MIXED_PAIRF64, MIXED_F32STATE = 0, 1, 2, 3, 4
 OK, EINVAL, EDEVICE, ENOMEM, ESTATE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 LAUNCH_AUTO, LAUNCH_STAGED, LAUNCH_FUSED, LAUNCH_SYMMETRIC = 0, 1, 2, 3
-SYMMETRIC_AUTO_N = 20480  # MD_SYMMETRIC_AUTO_N: LAUNCH_AUTO takes the symmetric 2D form from this n
-SYMMETRIC_AUTO_N_RING = 20480    # MD_SYMMETRIC_AUTO_N_RING: the same for the Ring with the FP32 forms
-SYMMETRIC_AUTO_N_RING64 = 18432  # MD_SYMMETRIC_AUTO_N_RING64: the same for the Ring with FP64
+SYMMETRIC_AUTO_N = 13312  # MD_SYMMETRIC_AUTO_N: LAUNCH_AUTO takes the symmetric 2D form from this n (MIXED, FP64)
+SYMMETRIC_AUTO_N_COMP = 15360    # MD_SYMMETRIC_AUTO_N_COMP: the same for 2D with the compensated forms
+SYMMETRIC_AUTO_N_RING = 13312    # MD_SYMMETRIC_AUTO_N_RING: the same for the Ring with the FP32 forms
+SYMMETRIC_AUTO_N_RING64 = 10240  # MD_SYMMETRIC_AUTO_N_RING64: the same for the Ring with FP64
 
 MODEL_NAMES = {HMF: "hmf", RING: "ring", GRAV2D: "grav2d"}
 PREC_NAMES = {FP64: "fp64", MIXED: "mixed", MIXED_KAHAN: "mixed_kahan",

@@ -105,7 +105,7 @@ def test_auto_launch_form_and_validation():
             ctx = md.md_init(model, md.MIXED, n, 1e-3)
             assert md.md_get_launch(ctx) == form, (model, n)
             md.md_destroy(ctx)
-    big = md.md_init(GRAV2D, md.FP64, 16384, 1e-3)
+    big = md.md_init(GRAV2D, md.FP64, 12288, 1e-3)
     assert md.md_get_launch(big) == md.LAUNCH_STAGED           # above the fused form's automatic size
     md.md_set_launch(big, md.LAUNCH_FUSED)
     assert md.md_get_launch(big) == md.LAUNCH_FUSED

@@ -208,9 +208,10 @@ def test_launch_form_and_refusals():
     assert md.md_get_launch(big) == md.LAUNCH_STAGED
     md.md_set_launch(big, md.LAUNCH_AUTO)
     assert md.md_get_launch(big) == md.LAUNCH_SYMMETRIC
-    # every FP32 accumulation takes the form (the Ring FP32 forms share one threshold)
-    for model, prec, n0 in [(GRAV2D, md.MIXED_KAHAN, md.SYMMETRIC_AUTO_N),
-                            (GRAV2D, md.MIXED_PAIRF64, md.SYMMETRIC_AUTO_N),
+    # every FP32 accumulation takes the form (the 2D compensated forms share one threshold, the Ring FP32
+    # forms another)
+    for model, prec, n0 in [(GRAV2D, md.MIXED_KAHAN, md.SYMMETRIC_AUTO_N_COMP),
+                            (GRAV2D, md.MIXED_PAIRF64, md.SYMMETRIC_AUTO_N_COMP),
                             (RING, md.MIXED_KAHAN, md.SYMMETRIC_AUTO_N_RING),
                             (RING, md.MIXED_PAIRF64, md.SYMMETRIC_AUTO_N_RING)]:
         for n, form in ((n0, md.LAUNCH_SYMMETRIC), (n0 - 1, md.LAUNCH_STAGED)):
