@@ -134,6 +134,7 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup, launch=None):
     e1 = md.md_energy(ctx, q, p).cpu().numpy()
     tiles = md.md_get_tiles(ctx)
     launch = LAUNCH_NAMES[md.md_get_launch(ctx)]
+    sym_tile = md.md_get_sym_tile(ctx)
     ctx.close()
     pairs = 3.0 * N * N * steps
     return {
@@ -146,7 +147,7 @@ def run_variant(md, torch, prec, q0, p0, steps, warmup, launch=None):
         "E0": e0.tolist(), "E1": e1.tolist(),
         "dE_E": abs(e1[2] - e0[2]) / abs(e0[2]),
         "dE_KV": abs(e1[2] - e0[2]) / (abs(e0[0]) + abs(e0[1])),
-        "tiles": list(tiles), "launch": launch, "sym_tile": md.md_get_sym_tile(ctx), "final_q": q, "final_p": p,
+        "tiles": list(tiles), "launch": launch, "sym_tile": sym_tile, "final_q": q, "final_p": p,
     }
 
 
