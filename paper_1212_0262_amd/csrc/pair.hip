@@ -707,13 +707,17 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
     };
     const int nblk = S * L / kSlotBlock;
     if (flags & UPD_F_FROM_PART) {
-        for (int x = threadIdx.x; x < nblk * IPL * D * IL; x += blockDim.x) {
-            const int it = x % (IPL * D * IL), bb = x / (IPL * D * IL) * kSlotBlock;
-            const int s2 = it % IL, kd = it / IL;
-            double v[kSlotBlock];
+        // wavefront k takes block k (and k + S, ...), its lanes the particles: with 8
+        // lane groups the block is one wavefront's slice, and the lanes of each LDS
+        // read take consecutive words
+        for (int k = w; k < nblk; k += S) {
+            for (int it = lane; it < IPL * D * IL; it += kWave) {
+                const int bb = k * kSlotBlock, s2 = it % IL, kd = it / IL;
+                double v[kSlotBlock];
 #pragma unroll
-            for (int u = 0; u < kSlotBlock; ++u) v[u] = *fpart(bb + u, kd, s2);
-            *fpart(bb, kd, s2) = tree8(v);
+                for (int u = 0; u < kSlotBlock; ++u) v[u] = *fpart(bb + u, kd, s2);
+                *fpart(bb, kd, s2) = tree8(v);
+            }
         }
         __syncthreads();
     }
