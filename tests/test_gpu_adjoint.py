@@ -59,13 +59,13 @@ def test_hvp_matches_oracle(model, eps, prec, n):
 
 
 @pytest.mark.parametrize("n,launch", [(2048, md.LAUNCH_SYMMETRIC), (3001, md.LAUNCH_SYMMETRIC),
-                                      (5003, md.LAUNCH_SYMMETRIC), (32768, md.LAUNCH_AUTO)])
+                                      (5003, md.LAUNCH_SYMMETRIC), (32768, md.LAUNCH_AUTO), (70_001, md.LAUNCH_AUTO)])
 def test_hvp_symmetric_matches_oracle(n, launch):
     """2D FP64 with the force in the symmetric form: the product takes it too (each
     pair evaluated once for both particles, tile-pair slots added in a fixed order),
     against the oracle and against the staged product; ragged sizes put pad particles
     in the last tile.  N = 32768 is the adjoint workload's size, where the automatic
-    form is the symmetric one."""
+    form is the symmetric one (tiles of 256, as below it); 70,001 takes tiles of 1024."""
     q, _ = _state(GRAV2D, n, seed=90 + n)
     w = np.random.default_rng(n + 3).normal(size=q.shape)
     ho = oracle.hvp(GRAV2D, q, w, 1e-3)

@@ -83,9 +83,10 @@ def test_symmetric_force_clustered_state(prec):
 
 @pytest.mark.parametrize("model,eps", MODELS)
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n", [40_000, 131_073])
+@pytest.mark.parametrize("n", [40_000, 65_537, 100_000, 131_073])
 def test_symmetric_against_staged(n, prec, model, eps):
-    """Both forms sum the same pair terms in different groupings."""
+    """Both forms sum the same pair terms in different groupings.  The sizes take each
+    tile size: 256 up to 65,536, then 1024 (2D) or 512 (Ring, up to 131,072)."""
     q, _ = _state(model, n, seed=7)
     fs = _force(q, md.LAUNCH_SYMMETRIC, prec, model, eps)
     ft = _force(q, md.LAUNCH_STAGED, prec, model, eps)
@@ -185,6 +186,23 @@ def test_symmetric_vector_update_ragged_slot_count(model, prec, n):
     check(f"symmetric vector update model={model} prec={prec} n={n} sampled rows", rel_inf(host(f)[..., rows], fo),
           force_tol(model, prec, n))
     ctx.close()
+
+
+def test_sym_tile_sizes():
+    """The tile of the symmetric form (md_get_sym_tile): 256 up to 65,536 particles, then
+    512 for the Ring up to 131,072 and 1024 otherwise; 0 when another form runs."""
+    for model, n, tile in [(GRAV2D, 20_000, 256), (GRAV2D, 65_536, 256), (GRAV2D, 65_537, 1024),
+                           (RING, 65_536, 256), (RING, 65_537, 512), (RING, 131_072, 512), (RING, 131_073, 1024)]:
+        ctx = md.md_init(model, md.MIXED, n, EPS)
+        assert md.md_get_launch(ctx) == md.LAUNCH_SYMMETRIC
+        assert md.md_get_sym_tile(ctx) == tile, (model, n)
+        md.md_set_launch(ctx, md.LAUNCH_STAGED)
+        assert md.md_get_sym_tile(ctx) == 0
+        ctx.close()
+    b = md.md_batch_init(RING, md.MIXED_KAHAN, [0, 8000, 16000], [0.01] * 2)
+    md.md_set_launch(b, md.LAUNCH_SYMMETRIC)
+    assert md.md_get_sym_tile(b) == 1024                       # ensembles keep tiles of 1024
+    b.close()
 
 
 def test_launch_form_and_refusals():
