@@ -66,6 +66,8 @@ def sym_counts(n, tile):
 SYM_FLOPS_PER_EVAL = 14      # symmetric form, per pair evaluated: 2 sub, 2 FMA (r^2), 2 FMA (i side), 2 FMA (j side)
 PAIR_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("pair.hip", "pair_terms.h", "device.h")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "grav2d_pair_mixed_n262144_pmc.txt")
+HMF_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hmf_pass_n1e7_pmc.txt")
+HMF_KERNEL_SRCS = [os.path.join(ROOT, "paper_1212_0262_amd", "csrc", f) for f in ("hmf.hip", "device.h")]
 GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 GATE_BAR = {"mixed": 1e-5, "fp64": 1e-6}   # |E - E_oracle| / |E0| at every report time
 
@@ -74,13 +76,27 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def pair_kernel_hash() -> str:
-    """Hash of the sources the pair kernel is compiled from."""
+def source_hash(srcs) -> str:
+    """Hash of the sources a kernel is compiled from (the counter summaries record it)."""
     h = hashlib.sha256()
-    for fn in PAIR_KERNEL_SRCS:
+    for fn in srcs:
         with open(fn, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def hmf_traffic_from_profile():
+    """HBM bytes of one FP64 stage pass (the median dispatch) from the committed counter
+    summary, if it was taken on the current source of the pass kernel; else None."""
+    try:
+        txt = open(HMF_TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (m and b) or m.group(1) != source_hash(HMF_KERNEL_SRCS):
+        return None
+    return float(b.group(1))
 
 
 def traffic_from_profile(launch, tiles):
@@ -95,7 +111,7 @@ def traffic_from_profile(launch, tiles):
     f = re.search(r"launch:\s*(\w+)", txt)
     t = re.search(r"tiles_ipl_waves_jsplit_jtile:\s*([0-9, ]+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not (m and f and t and b) or m.group(1) != pair_kernel_hash() or f.group(1) != launch:
+    if not (m and f and t and b) or m.group(1) != source_hash(PAIR_KERNEL_SRCS) or f.group(1) != launch:
         return None
     if launch == "staged" and [int(x) for x in t.group(1).replace(" ", "").split(",") if x] != list(tiles):
         return None
@@ -420,7 +436,8 @@ def hmf_workload(md, torch, args):
                    "precision": "fp64"},
         # the stage pass's own launches (timed by the library), 32 bytes per particle each
         "roofline": {"bound": "hbm", "achieved": round(fp["pass_algorithmic_GBs"], 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(fp["pass_algorithmic_GBs"] / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(fp["pass_algorithmic_GBs"] / PEAK_HBM_GBS, 4),
+                     "traffic": hmf_traffic_from_profile(),
                      "kernel": "k_hmf_pass<double, 2, false>", "kernel_timed_as": fp["pass_timed_as"],
                      "kernel_ms_avg": round(fp["pass_ms_avg"], 5), "bytes_per_launch": HMF_N * HMF_BYTES["fp64"] // 3,
                      "step_GBs": round(fp["algorithmic_GBs"], 1),
