@@ -113,6 +113,7 @@ def test_null_context_calls():
     assert lib.md_get_tiles(None, None) == md.EINVAL
     assert lib.md_set_launch(None, md.LAUNCH_FUSED) == md.EINVAL
     assert lib.md_get_launch(None) == md.EINVAL
+    assert lib.md_get_sym_tile(None) == md.EINVAL
     assert lib.md_set_stream(None, None) == md.EINVAL
     assert lib.md_destroy(None) == md.OK
     assert lib.md_last_error(None) == b""
