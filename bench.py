@@ -54,8 +54,7 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (FMA = 2 flops)
 PEAK_FP64_TFLOPS = 78.6
 SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9   # 1024 SIMDs at 2.4 GHz
 LAUNCH_NAMES = {1: "staged", 2: "fused", 3: "symmetric"}
-SYM_TILE = 1024              # particles per tile of the symmetric form of ensembles (single systems:
-                             # md_get_sym_tile, 512 or 1024)
+ENS_SYM_TILE = 512           # particles per tile of the ensembles' symmetric form (md_get_sym_tile)
 
 
 def sym_counts(n, tile):
@@ -555,6 +554,7 @@ def ensemble_workload(md, torch, args):
         dt = time.perf_counter() - t0
         cpu = {"value": npairs / dt / 1e9, "unit": "Gpair-interactions/s", "cores": oracle.get_threads(),
                "kind": "oracle", "sample": "force + 2 FP64 Yoshida steps of the 8 smallest realizations"}
+    tile = md.md_get_sym_tile(ctx) or ENS_SYM_TILE
     ctx.close()
     # roofline of the symmetric kernel (Kahan; one launch per force evaluation): the pairs
     # of particles in different tiles of a realization, each evaluated once for both (11
@@ -562,8 +562,8 @@ def ensemble_workload(md, torch, args):
     # and the ordered pairs within each tile, i side only (11 + 5)
     tile_pairs = diag_pairs = 0.0
     for nb_ in sizes.astype(np.int64):
-        t = np.full(-(-int(nb_) // SYM_TILE), SYM_TILE, dtype=np.float64)
-        t[-1] = nb_ - SYM_TILE * (len(t) - 1)
+        t = np.full(-(-int(nb_) // tile), tile, dtype=np.float64)
+        t[-1] = nb_ - tile * (len(t) - 1)
         tile_pairs += (float(nb_) ** 2 - float((t * t).sum())) / 2
         diag_pairs += float((t * t).sum())
     k_s = k_ms / max(k_n, 1) * 1e-3

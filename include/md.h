@@ -234,9 +234,10 @@ int md_max_j_split(int64_t n);
  * SYMMETRIC), or a negative status.  HMF contexts are always STAGED, ensembles
  * STAGED or SYMMETRIC.
  * md_get_sym_tile returns the particles per tile of the symmetric form when
- * md_get_launch is SYMMETRIC (1024; for single systems 256 up to 65536
- * particles and 512 for the Ring up to 131072: more, shorter tile pairs where
- * they are few), else 0; a negative status for a null context.  The force then evaluates T (T - 1) / 2 tile pairs of T^2 pairs
+ * md_get_launch is SYMMETRIC (single systems: 256 up to 65536 particles, 512
+ * for the Ring up to 131072, 1024 above -- more, shorter tile pairs where they
+ * are few; ensembles: 512 within each realization), else 0; a negative status
+ * for a null context.  The force then evaluates T (T - 1) / 2 tile pairs of T^2 pairs
  * each and T diagonal tiles of T^2 ordered pairs, T = the padded n over the tile.
  */
 enum md_launch { MD_LAUNCH_AUTO = 0, MD_LAUNCH_STAGED = 1, MD_LAUNCH_FUSED = 2, MD_LAUNCH_SYMMETRIC = 3 };

@@ -434,7 +434,7 @@ int make_batch(int model, int prec, int nb, const int64_t *off, const double *ep
     // symmetric form: every realization within the single-system limits, slots within 4 GiB
     const bool sym_prec = model == MD_RING ? (prec == MD_MIXED || prec == MD_MIXED_KAHAN || prec == MD_FP64)
                                            : (prec == MD_MIXED || prec == MD_MIXED_KAHAN);
-    B.tmax = (int)div_up(B.nmax, kSymTile);
+    B.tmax = (int)div_up(B.nmax, kBatchSymTile);
     const size_t sym_slot_bytes = (size_t)B.tmax * dims(model) * (size_t)pad_n(off[nb]) * sizeof(double);
     B.sym = sym_prec && B.nmax <= kSymMaxN && sym_slot_bytes <= (size_t(1) << 32);
     B.sitems.clear();
@@ -444,11 +444,11 @@ int make_batch(int model, int prec, int nb, const int64_t *off, const double *ep
         std::vector<int> diag;
         for (int b = 0; b < nb; ++b) {
             const int64_t o = off[b], n = off[b + 1] - off[b];
-            const int T = (int)div_up(n, kSymTile);
+            const int T = (int)div_up(n, kBatchSymTile);
             for (int ta = 0; ta < T; ++ta) {
-                const int ia = (int)(o + (int64_t)ta * kSymTile);
+                const int ia = (int)(o + (int64_t)ta * kBatchSymTile);
                 for (int tb = ta + 1; tb < T; ++tb) {
-                    const int it[8] = {b, ia, (int)(o + n), tb, (int)(o + (int64_t)tb * kSymTile), (int)(o + n), ta, 0};
+                    const int it[8] = {b, ia, (int)(o + n), tb, (int)(o + (int64_t)tb * kBatchSymTile), (int)(o + n), ta, 0};
                     B.sitems.insert(B.sitems.end(), it, it + 8);
                 }
                 const int dg[8] = {b, ia, (int)(o + n), ta, ia, (int)(o + n), ta, 0};
@@ -945,7 +945,7 @@ int md_get_sym_tile(const md_ctx *c)
 {
     if (!c) return MD_EINVAL;
     if (c->model == MD_HMF || form_of(c) != MD_LAUNCH_SYMMETRIC) return 0;
-    return c->batch ? kSymTile : sym_tile_n(c->model, c->prec, c->n);
+    return c->batch ? kBatchSymTile : sym_tile_n(c->model, c->prec, c->n);
 }
 
 int md_get_tiles(const md_ctx *c, int *out4)

@@ -299,13 +299,14 @@ __global__ __launch_bounds__(256) void k_batch_pair_ring_win(const PairItem *__r
 // the pad value, whose terms vanish.  The i side goes to slot it.slot of the i
 // particles, the j side (the wavefronts' sums added in FP64, fixed order, after
 // every 64-j block) to slot it.slot_j of the j particles.
-template <int MODEL, typename T, typename A, bool SYM>
+template <int MODEL, typename T, typename A, bool SYM, int W>
 __device__ __forceinline__ void batch_sym_item(const PairItem &it, const T *__restrict__ r0,
                                                const T *__restrict__ r1, const double *__restrict__ beps, int npad,
                                                double *__restrict__ part,
-                                               double (&jw)[kSymWaves][MODEL == MD_GRAV2D ? 2 : 1][kWave])
+                                               double (&jw)[W][MODEL == MD_GRAV2D ? 2 : 1][kWave])
 {
     constexpr int D = MODEL == MD_GRAV2D ? 2 : 1;
+    constexpr int TILE = W * kWave * kSymIpl;
     const double eb = beps[it.b];
     const T e = MODEL == MD_GRAV2D ? (T)eb : sizeof(T) == 4 ? (T)(2.0 * eb) : (T)(1.0 + eb);
     const T pad = sym_pad<MODEL, T>();
@@ -315,8 +316,8 @@ __device__ __forceinline__ void batch_sym_item(const PairItem &it, const T *__re
     // work (no barriers without SYM).  The j tile stops after its last 64-j block
     // that holds a particle: the pads' terms are zero.
     if (!SYM && it.i0 + wave * kWave * kSymIpl >= it.i1) return;
-    // (j1 is the realization's end: only its last tile is shorter than kSymTile)
-    const int nblk = min(kSymTile / kWave, (it.j1 - it.j0 + kWave - 1) / kWave);
+    // (j1 is the realization's end: only its last tile is shorter than TILE)
+    const int nblk = min(TILE / kWave, (it.j1 - it.j0 + kWave - 1) / kWave);
     T u0[kSymIpl], u1[kSymIpl];
     A acc[D][kSymIpl];
 #pragma unroll
@@ -338,13 +339,13 @@ __device__ __forceinline__ void batch_sym_item(const PairItem &it, const T *__re
 #pragma unroll
             for (int d = 0; d < D; ++d) jw[wave][d][m] = sj[d].get();
             __syncthreads();
-            if (threadIdx.x < D * kWave) {
-                const int d = threadIdx.x / kWave, mm = threadIdx.x & (kWave - 1);
+            for (int x = threadIdx.x; x < D * kWave; x += W * kWave) {  // W = 1: a thread per (d, j) in turn
+                const int d = x / kWave, mm = x & (kWave - 1);
                 const int j = it.j0 + blk * kWave + mm;
                 if (j < it.j1) {
                     double t = 0.0;
 #pragma unroll
-                    for (int w = 0; w < kSymWaves; ++w) t += jw[w][d][mm];
+                    for (int w = 0; w < W; ++w) t += jw[w][d][mm];
                     part[(size_t)(D * it.slot_j + d) * npad + j] = t;
                 }
             }
@@ -363,18 +364,18 @@ __device__ __forceinline__ void batch_sym_item(const PairItem &it, const T *__re
 
 // One launch per force evaluation: the n_soff tile pairs of the work list (a
 // block each), then its diagonal tiles, cheaper, at the end of the grid.
-template <int MODEL, typename T, typename A>
-__global__ __launch_bounds__(kSymWaves * kWave) void k_batch_sym(const PairItem *__restrict__ items, int n_soff,
-                                                                 const T *__restrict__ r0, const T *__restrict__ r1,
-                                                                 const double *__restrict__ beps, int npad,
-                                                                 double *__restrict__ part)
+template <int MODEL, typename T, typename A, int W>
+__global__ __launch_bounds__(W * kWave) void k_batch_sym(const PairItem *__restrict__ items, int n_soff,
+                                                         const T *__restrict__ r0, const T *__restrict__ r1,
+                                                         const double *__restrict__ beps, int npad,
+                                                         double *__restrict__ part)
 {
-    __shared__ double jw[kSymWaves][MODEL == MD_GRAV2D ? 2 : 1][kWave];
+    __shared__ double jw[W][MODEL == MD_GRAV2D ? 2 : 1][kWave];
     const PairItem it = items[blockIdx.x];
     if ((int)blockIdx.x < n_soff)
-        batch_sym_item<MODEL, T, A, true>(it, r0, r1, beps, npad, part, jw);
+        batch_sym_item<MODEL, T, A, true, W>(it, r0, r1, beps, npad, part, jw);
     else
-        batch_sym_item<MODEL, T, A, false>(it, r0, r1, beps, npad, part, jw);
+        batch_sym_item<MODEL, T, A, false, W>(it, r0, r1, beps, npad, part, jw);
 }
 
 template <int MODEL, typename T, typename A>
@@ -384,10 +385,10 @@ hipError_t sym_launch(md_ctx *c)
     const T *r0 = static_cast<const T *>(c->ops);
     const int npad = (int)c->npad;
     const PairItem *items = reinterpret_cast<const PairItem *>(B.d_sitems);
-    const dim3 block(kSymWaves * kWave);
+    constexpr int W = kBatchSymTile / (kWave * kSymIpl);
     const int ts = timed_begin(c, "k_batch_sym");
-    hipLaunchKernelGGL((k_batch_sym<MODEL, T, A>), dim3((unsigned)(B.n_soff + B.n_sdiag)), block, 0, c->stream, items,
-                       B.n_soff, r0, r0 + npad, B.d_eps, npad, c->part);
+    hipLaunchKernelGGL((k_batch_sym<MODEL, T, A, W>), dim3((unsigned)(B.n_soff + B.n_sdiag)), dim3(W * kWave), 0,
+                       c->stream, items, B.n_soff, r0, r0 + npad, B.d_eps, npad, c->part);
     const hipError_t err = hipGetLastError();
     timed_end(c, ts);
     return err;

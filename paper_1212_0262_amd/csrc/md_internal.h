@@ -54,6 +54,7 @@ constexpr int kFusedLdsBytes = 49152;   // LDS per fused block (split evenly bet
 constexpr int64_t kFusedAutoN = 4096;   // MD_LAUNCH_AUTO takes the fused form up to this n (Ring)
 constexpr int64_t kFusedAutoN2D = 6144; // ... and up to this n for 2D gravity
 constexpr int kSymTile = 1024;          // particles per tile of the symmetric form (4 waves x 64 x 4 i)
+constexpr int kBatchSymTile = 512;     // tiles of the ensembles' symmetric form (2 waves x 64 x 4 i)
 constexpr int kSymTileSmall = 512;      // ... for smaller n (2 waves x 64 x 4 i; sym_tile_n), and 256
                                         // (1 wave) for smaller n still
 constexpr int64_t kSymMinN = 2048;      // the symmetric form needs two tiles at least

@@ -201,7 +201,7 @@ def test_sym_tile_sizes():
         ctx.close()
     b = md.md_batch_init(RING, md.MIXED_KAHAN, [0, 8000, 16000], [0.01] * 2)
     md.md_set_launch(b, md.LAUNCH_SYMMETRIC)
-    assert md.md_get_sym_tile(b) == 1024                       # ensembles keep tiles of 1024
+    assert md.md_get_sym_tile(b) == 512                        # ensembles: tiles of 512
     b.close()
 
 
