@@ -43,12 +43,11 @@ __device__ __forceinline__ double rsq64(double x)
 // |x| < 2^30.  On |r| <= pi/4 the Taylor series of sin to r^17 and of cos to r^16
 // are exact to 1e-19.  The quadrant k mod 4 permutes and negates the pair.
 // Larger |x| (never reached by the dynamics here) falls back to the library.
-__device__ __forceinline__ void sincos64(double x, double *sp, double *cp)
+constexpr double kSincosMaxArg = 1073741824.0;  // 2^30: the reduction's range
+
+// sincos64 without the fallback: valid for |x| < kSincosMaxArg, no branch.
+__device__ __forceinline__ void sincos64_reduced(double x, double *sp, double *cp)
 {
-    if (!(fabs(x) < 1073741824.0)) {
-        sincos(x, sp, cp);
-        return;
-    }
     const double P1 = 1.5707963267948966;      // pi/2 rounded to double
     const double P2 = 6.123233995736766e-17;   // pi/2 - P1
     const double k = __builtin_rint(x * 0.6366197723675814);
@@ -78,6 +77,15 @@ __device__ __forceinline__ void sincos64(double x, double *sp, double *cp)
     const double b = (q & 1) ? sr : cr;
     *sp = (q & 2) ? -a : a;
     *cp = ((q + 1) & 2) ? -b : b;
+}
+
+__device__ __forceinline__ void sincos64(double x, double *sp, double *cp)
+{
+    if (!(fabs(x) < kSincosMaxArg)) {
+        sincos(x, sp, cp);
+        return;
+    }
+    sincos64_reduced(x, sp, cp);
 }
 
 // FP32 counterpart (the FP32-state HMF path keeps |x| <= pi): Taylor to r^11 / r^12.

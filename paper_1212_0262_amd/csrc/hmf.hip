@@ -39,8 +39,30 @@ namespace {
 
 constexpr int kUnroll = 2;  // vectors per thread per grid-stride iteration
 
-__device__ __forceinline__ void sincos_(double x, double *s, double *c) { sincos64(x, s, c); }
-__device__ __forceinline__ void sincos_(float x, float *s, float *c) { sincos32(x, s, c); }
+// sincos of E angles, each step over all of them before the next, so that their
+// chains interleave.  FP64: the branch-free reduced form for all, then the library
+// for any angle beyond its range (never, for the dynamics here).
+template <int E>
+__device__ __forceinline__ void sincos_n(const double (&x)[E], double (&s)[E], double (&c)[E])
+{
+    bool big = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        sincos64_reduced(x[e], &s[e], &c[e]);
+        big |= !(fabs(x[e]) < kSincosMaxArg);
+    }
+    if (big) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (!(fabs(x[e]) < kSincosMaxArg)) sincos(x[e], &s[e], &c[e]);
+    }
+}
+template <int E>
+__device__ __forceinline__ void sincos_n(const float (&x)[E], float (&s)[E], float (&c)[E])
+{
+#pragma unroll
+    for (int e = 0; e < E; ++e) sincos32(x[e], &s[e], &c[e]);
+}
 
 // Map an FP32 angle into [-pi, pi).
 __device__ __forceinline__ float wrap_pi(float t)
@@ -64,33 +86,53 @@ struct PassArgs {
     int flags;
 };
 
-// The work of one particle: kick (with f from f_in or from M), drift, and the
-// sincos of the new angle into the partial sums.
-template <typename T>
-__device__ __forceinline__ void particle(T &t, T &p, double fin, double *fout, T mx, T my, T k1, T k2, T dr,
-                                         int flags, double &sc, double &ss)
+// The work of one stage on E particles: kick (with f from f_in or from M), drift,
+// and the sincos of the new angle into the partial sums (of the particles with
+// ok[e]; in the order of e).  Each step runs over all E particles before the next,
+// with no branch between them.
+template <typename T, int E>
+__device__ __forceinline__ void stage_n(T (&t)[E], T (&p)[E], const double (&fin)[E], double (&fout)[E],
+                                        const bool (&ok)[E], T mx, T my, T k1, T k2, T dr, int flags, double &sc,
+                                        double &ss)
 {
     if (flags & (HMF_KICK_M | HMF_STORE_F)) {
-        T s, c;
-        sincos_(t, &s, &c);
-        const T f = c * my - s * mx;
-        if (flags & HMF_STORE_F) *fout = (double)f;
+        T s[E], c[E], f[E];
+        sincos_n(t, s, c);
+#pragma unroll
+        for (int e = 0; e < E; ++e) f[e] = c[e] * my - s[e] * mx;
+        if (flags & HMF_STORE_F) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) fout[e] = (double)f[e];
+        }
         if (flags & HMF_KICK_M) {
-            p += k1 * f;
-            if (flags & HMF_KICK2) p += k2 * f;
+#pragma unroll
+            for (int e = 0; e < E; ++e) p[e] += k1 * f[e];
+            if (flags & HMF_KICK2) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) p[e] += k2 * f[e];
+            }
         }
     } else if (flags & HMF_KICK_F) {
-        p += k1 * (T)fin;
+#pragma unroll
+        for (int e = 0; e < E; ++e) p[e] += k1 * (T)fin[e];
     }
     if (flags & HMF_DRIFT) {
-        t += dr * p;
-        if constexpr (sizeof(T) == 4) t = wrap_pi(t);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            t[e] += dr * p[e];
+            if constexpr (sizeof(T) == 4) t[e] = wrap_pi(t[e]);
+        }
     }
     if (flags & HMF_REDUCE) {
-        T s, c;
-        sincos_(t, &s, &c);
-        sc += (double)c;
-        ss += (double)s;
+        T s[E], c[E];
+        sincos_n(t, s, c);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (ok[e]) {
+                sc += (double)c[e];
+                ss += (double)s[e];
+            }
+        }
     }
 }
 
@@ -182,54 +224,73 @@ __global__ __launch_bounds__(256) void k_hmf_pass(T *__restrict__ th, T *__restr
     const int stride = gridDim.x * blockDim.x;
     using VT = Vec<T, W>;
     using VD = Vec<double, W>;
+    constexpr int E = kUnroll * W;  // particles per thread and iteration: e = u W + w
     for (int base = blockIdx.x * blockDim.x + threadIdx.x; base < nvec; base += stride * kUnroll) {
         VT t[kUnroll], q[kUnroll];
         VD fi[kUnroll];
+        bool ok[E];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int v = base + u * stride;
+            t[u] = VT{};
+            q[u] = VT{};
+            fi[u] = VD{};
             if (v < nvec) {
                 t[u] = reinterpret_cast<const VT *>(th)[v];
                 if (need_p) q[u] = reinterpret_cast<const VT *>(p)[v];
                 if (flags & HMF_KICK_F) fi[u] = reinterpret_cast<const VD *>(f_in)[v];
             }
+#pragma unroll
+            for (int w = 0; w < W; ++w) ok[u * W + w] = v < nvec;
         }
+        T te[E], pe[E];
+        double fe[E], fo[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            te[e] = t[e / W].x[e % W];
+            pe[e] = q[e / W].x[e % W];
+            fe[e] = fi[e / W].x[e % W];
+            fo[e] = 0.0;
+        }
+        stage_n(te, pe, fe, fo, ok, mx, my, k1, k2, dr, flags, sc, ss);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int v = base + u * stride;
             if (v >= nvec) continue;
-            VD fo;
+            VT to, po;
+            VD ff;
 #pragma unroll
             for (int w = 0; w < W; ++w) {
-                T pw = need_p ? q[u].x[w] : T(0);
-                particle(t[u].x[w], pw, (flags & HMF_KICK_F) ? fi[u].x[w] : 0.0, &fo.x[w], mx, my, k1, k2, dr,
-                         flags, sc, ss);
-                q[u].x[w] = pw;
+                to.x[w] = te[u * W + w];
+                po.x[w] = pe[u * W + w];
+                ff.x[w] = fo[u * W + w];
             }
-            if (flags & HMF_STORE_F) reinterpret_cast<VD *>(f_out)[v] = fo;
+            if (flags & HMF_STORE_F) reinterpret_cast<VD *>(f_out)[v] = ff;
             if (write) {
-                reinterpret_cast<VT *>(th)[v] = t[u];
-                if (need_p) reinterpret_cast<VT *>(p)[v] = q[u];
+                reinterpret_cast<VT *>(th)[v] = to;
+                if (need_p) reinterpret_cast<VT *>(p)[v] = po;
             }
             if (snap && (flags & HMF_DRIFT)) {
 #pragma unroll
-                for (int w = 0; w < W; ++w) snap[v * W + w] = t[u].x[w];
+                for (int w = 0; w < W; ++w) snap[v * W + w] = to.x[w];
             }
         }
     }
     // the n mod W particles past the last full vector: block 0
     if (W > 1 && blockIdx.x == 0 && (int)threadIdx.x < n - nvec * W) {
         const int i = nvec * W + threadIdx.x;
-        T t = th[i];
-        T pw = need_p ? p[i] : T(0);
-        double fo = 0.0;
-        particle(t, pw, (flags & HMF_KICK_F) ? f_in[i] : 0.0, &fo, mx, my, k1, k2, dr, flags, sc, ss);
-        if (flags & HMF_STORE_F) f_out[i] = fo;
+        T t1[1] = {th[i]};
+        T p1[1] = {need_p ? p[i] : T(0)};
+        const double f1[1] = {(flags & HMF_KICK_F) ? f_in[i] : 0.0};
+        double fo1[1] = {0.0};
+        const bool ok1[1] = {true};
+        stage_n(t1, p1, f1, fo1, ok1, mx, my, k1, k2, dr, flags, sc, ss);
+        if (flags & HMF_STORE_F) f_out[i] = fo1[0];
         if (write) {
-            th[i] = t;
-            if (need_p) p[i] = pw;
+            th[i] = t1[0];
+            if (need_p) p[i] = p1[0];
         }
-        if (snap && (flags & HMF_DRIFT)) snap[i] = t;
+        if (snap && (flags & HMF_DRIFT)) snap[i] = t1[0];
     }
     if (flags & HMF_REDUCE) {
         const double bc = block_sum(sc, lds[0]);
