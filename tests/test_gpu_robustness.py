@@ -57,6 +57,35 @@ def test_hmf_unaligned_arrays_take_the_scalar_path(n):
     assert np.abs(host(f) - fo).max() < 1e-12
 
 
+@pytest.mark.parametrize("n,unaligned", [(20_003, False), (1001, True)])
+def test_hmf_angles_beyond_the_reduction_range(n, unaligned):
+    """The FP64 pass reduces every angle of a thread by pi/2 in two FMA steps, exact
+    for |theta| < 2^30; any angle beyond (the dynamics never reach one) is redone by
+    the device library's sincos afterwards.  Such angles in vector lanes, at the
+    range's edge and in the scalar tail, against the oracle's sin and cos: the
+    force and the magnetization, and the force md_step leaves equal to md_force at
+    the positions it leaves, bit for bit."""
+    q, p = inputs.hmf_waterbag(n, seed=92)
+    idx = [0, 1, 2, 3, 500, n - 2, n - 1]
+    vals = [3.0e9, -2.0 ** 30, 2.0 ** 30 - 0.5, -1.1e12, 4.5e15, 2.0 ** 30, -6.0e9]
+    q[0, idx] = vals
+    fo = oracle.force(HMF, q)
+    mo = np.array([np.cos(q[0]).sum(), np.sin(q[0]).sum()]) / n
+    ctx = md.md_init(HMF, md.FP64, n, 0.0)
+    put = _offset_view if unaligned else dev
+    qd, pd = put(q), put(p)
+    f = put(np.zeros_like(q))
+    md.md_force(ctx, qd, f)
+    assert np.abs(host(f) - fo).max() < 1e-13
+    assert np.abs(host(md.md_magnetization(ctx, qd)) - mo).max() < 1e-13
+    md.md_step(ctx, qd, pd, f, 0.1, 3)
+    assert np.isfinite(host(qd)).all() and np.isfinite(host(pd)).all()
+    f2 = put(np.zeros_like(q))
+    md.md_force(ctx, qd, f2)
+    np.testing.assert_array_equal(host(f2), host(f))
+    ctx.close()
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 4097, 20_003])
 def test_hmf_f32state_ragged_tails(n):
     """FP32 state moves 4 particles per vector access; the n mod 4 others take the
