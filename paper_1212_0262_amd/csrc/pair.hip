@@ -494,6 +494,18 @@ __global__ __launch_bounds__(64) void k_update_vec(const SlotT *__restrict__ par
     for (int k = 0; k < VW; ++k)
 #pragma unroll
         for (int d = 0; d < D; ++d) fs[k][d] = 0.0;
+    // q and p of the thread's particles go out before the slot loads: their
+    // latency then hides under the slot sum instead of following it
+    double qv[VW][D], pv[VW][D];
+#pragma unroll
+    for (int k = 0; k < VW; ++k)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int i = i0 + k;
+            const size_t e = (size_t)d * n + i;
+            qv[k][d] = (i < n && stage_reads_q(flags)) ? q[e] : 0.0;
+            pv[k][d] = (i < n && stage_reads_p(flags)) ? p[e] : 0.0;
+        }
     if (flags & UPD_F_FROM_PART) {  // the slot order of slot_sums (device.h)
         int b = 0;
         for (; b + U <= S; b += U) {
@@ -537,7 +549,8 @@ __global__ __launch_bounds__(64) void k_update_vec(const SlotT *__restrict__ par
             } else if (flags & (UPD_KICK1 | UPD_KICK2 | UPD_STORE_F)) {
                 fd = f[(size_t)d * n + i];
             }
-            stage_elem<PREP>(d, i, n, npad, fd, flags, f, p, q, ops, kick1, kick2, drift, snap);
+            stage_elem_v<PREP>(d, i, n, npad, fd, qv[k][d], pv[k][d], flags, f, p, q, ops, kick1, kick2, drift,
+                               snap);
         }
     }
 }
