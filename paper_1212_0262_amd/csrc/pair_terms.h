@@ -78,6 +78,23 @@ __device__ __forceinline__ float rcp_(float x) { return rcp32(x); }
 __device__ __forceinline__ double rcp_(double x) { return rcp64(x); }
 __device__ __forceinline__ float rsq_(float x) { return rsq32(x); }
 __device__ __forceinline__ double rsq_(double x) { return rsq64(x); }
+// u^{-3/2}.  FP32: the hardware inverse square root, cubed.  FP64: with y the
+// hardware seed of u^{-1/2} (relative error below 2^-23) and e = 1 - u y^2,
+// u^{-3/2} = y^3 (1 - e)^{-3/2} = y^3 (1 + 3e/2 + 15e^2/8) + O(e^3): refined once
+// in the cube, one FP64 operation fewer than refining u^{-1/2} and cubing it.
+__device__ __forceinline__ float rsq3_(float u)
+{
+    const float r = rsq32(u);
+    return r * r * r;
+}
+__device__ __forceinline__ double rsq3_(double u)
+{
+    const double y = __builtin_amdgcn_rsq(u);
+    const double y2 = y * y;
+    const double e = __builtin_fma(-u, y2, 1.0);
+    const double y3 = y2 * y;
+    return __builtin_fma(y3, e * __builtin_fma(e, 1.875, 1.5), y3);
+}
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -188,9 +205,8 @@ __device__ __forceinline__ void ring_factors_eq9(T ci, T si, T cj, T sj, T one_e
         num = fma_(si, cj, -(ci * sj));
     }
     const T u = fma_(-ci, cj, fma_(-si, sj, one_eps));
-    const T r = rsq_(u);
     p = num;
-    q = r * r * r;
+    q = rsq3_(u);
 }
 
 // Ring, half-angle operands (the FP32 forms): A = sqrt2 sin(t/2), B = sqrt2 cos(t/2)
