@@ -106,8 +106,26 @@ enum md_status {
 size_t md_workspace_bytes(int model, int prec, int64_t n);
 
 /*
+ * The softening eps (eqs. 1 and 3) each pair model and precision accepts
+ * (MD_EINVAL outside; MD_HMF ignores eps): within them no pair term overflows,
+ * loses its normal range or takes the square root of a negative number, for any
+ * positions.  2D in FP64 adds two pair terms with one reciprocal of the product
+ * of their |r_i - r_j|^2 + eps, which must stay a normal FP64 number; the FP32
+ * forms round eps to FP32 (the Ring's half-angle form raises 2 eps to the -3/2);
+ * the Ring in FP64 (eq. 9) forms 1 + eps - cos(ti - tj), which has to stay
+ * positive for two particles at the same angle.  No upper bound for the Ring in
+ * FP64.
+ */
+#define MD_EPS_MIN_2D_FP64 1e-150
+#define MD_EPS_MAX_2D_FP64 1e150
+#define MD_EPS_MIN_2D_FP32 1e-30
+#define MD_EPS_MIN_RING_FP64 1e-12
+#define MD_EPS_MIN_RING_FP32 1e-25
+#define MD_EPS_MAX_FP32 1e30
+
+/*
  * Create a context for n particles of `model` (eqs. 1-3) with softening eps
- * (eqs. 1 and 3; ignored for MD_HMF, must be > 0 otherwise), computing in
+ * (eqs. 1 and 3, in the range above; ignored for MD_HMF), computing in
  * `prec`.  hip_stream: a hipStream_t, or NULL for the default stream.
  * workspace: device memory of at least md_workspace_bytes(model, prec, n)
  * bytes, 256-byte aligned.  On success *out holds the new context.
@@ -121,8 +139,8 @@ int md_init(md_ctx **out, int model, int prec, int64_t n, double eps,
  * MD_GRAV2D; MD_HMF is MD_EUNSUPPORTED) advanced together, e.g. for ensemble
  * averages over initial conditions of quasi-stationary states (Sec. 1).  Each
  * realization b is the system of eqs. 1 or 3 with its own N_b = offsets[b+1] -
- * offsets[b] >= 1 particles, its own 1/N_b coupling and its own eps[b] > 0;
- * realizations do not interact.
+ * offsets[b] >= 1 particles, its own 1/N_b coupling and its own eps[b] (in
+ * the range md_init takes); realizations do not interact.
  *   offsets: host int64 [nb + 1], offsets[0] = 0, strictly increasing,
  *            offsets[nb] <= 2^24 (total particles).
  *   eps:     host FP64 [nb].

@@ -46,6 +46,23 @@ bool prec_ok(int model, int prec)
 
 bool model_ok(int model) { return model == MD_HMF || model == MD_RING || model == MD_GRAV2D; }
 
+// The softening each pair form takes without an overflow, a non-normal number or a
+// negative square-root argument in its terms, for any positions: 2D FP64 adds two
+// terms with one reciprocal of s_a s_b (each s >= eps), which has to stay a normal
+// FP64 number; the FP32 forms round eps to FP32 and divide by it (2D) or raise
+// 2 eps to the -3/2 (the Ring's half-angle form); eq. 9 in FP64 forms
+// u = 1 + eps - cos d, which must stay positive for two particles at the same
+// angle (1 + eps is rounded to 2^-53).  MD_HMF has no softening.
+bool eps_ok(int model, int prec, double eps)
+{
+    if (model == MD_HMF) return true;
+    if (!(eps > 0.0 && isfinite(eps))) return false;
+    if (model == MD_GRAV2D)
+        return prec == MD_FP64 ? (eps >= MD_EPS_MIN_2D_FP64 && eps <= MD_EPS_MAX_2D_FP64)
+                               : (eps >= MD_EPS_MIN_2D_FP32 && eps <= MD_EPS_MAX_FP32);
+    return prec == MD_FP64 ? eps >= MD_EPS_MIN_RING_FP64 : (eps >= MD_EPS_MIN_RING_FP32 && eps <= MD_EPS_MAX_FP32);
+}
+
 // Contexts that can take the symmetric form (and carry its partial slots): Ring
 // and 2D in every precision form they accept.
 bool sym_capable(int model, int prec, int64_t n)
@@ -402,7 +419,7 @@ int make_batch(int model, int prec, int nb, const int64_t *off, const double *ep
     for (int b = 0; b < nb; ++b) {
         const int64_t n = off[b + 1] - off[b];
         if (n < 1 || off[b + 1] > kMaxBatchTotal) return MD_EINVAL;
-        if (!(eps[b] > 0.0 && isfinite(eps[b]))) return MD_EINVAL;
+        if (!eps_ok(model, prec, eps[b])) return MD_EINVAL;
         if (n > B.nmax) B.nmax = n;
         B.pref[b] = force_prefactor(model, prec, n);
     }
@@ -754,7 +771,7 @@ int md_init(md_ctx **out, int model, int prec, int64_t n, double eps, void *hip_
     *out = nullptr;
     if (!model_ok(model) || n < 1 || n > (model == MD_HMF ? kMaxHmfN : kMaxPairN)) return MD_EINVAL;
     if (!prec_ok(model, prec)) return MD_EUNSUPPORTED;
-    if (model != MD_HMF && !(eps > 0.0 && isfinite(eps))) return MD_EINVAL;
+    if (!eps_ok(model, prec, eps)) return MD_EINVAL;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return MD_EINVAL;
     const Layout L = layout(model, prec, n);
     if (workspace_bytes < L.total) return MD_ENOMEM;
@@ -1223,7 +1240,7 @@ int md_force_noalloc(int model, int prec, int64_t n, double eps, void *hip_strea
 {
     if (!model_ok(model) || n < 1 || n > (model == MD_HMF ? kMaxHmfN : kMaxPairN)) return MD_EINVAL;
     if (!prec_ok(model, prec)) return MD_EUNSUPPORTED;
-    if (model != MD_HMF && !(eps > 0.0 && isfinite(eps))) return MD_EINVAL;
+    if (!eps_ok(model, prec, eps)) return MD_EINVAL;
     if (!q || !f || !aligned8(q) || !aligned8(f)) return MD_EINVAL;
     // the built-in tiles, with the j split halved until its partials fit
     Tiles t = default_tiles(model, prec, n);

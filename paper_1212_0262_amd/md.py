@@ -29,6 +29,12 @@ SYMMETRIC_AUTO_N = 13312  # MD_SYMMETRIC_AUTO_N: LAUNCH_AUTO takes the symmetric
 SYMMETRIC_AUTO_N_COMP = 15360    # MD_SYMMETRIC_AUTO_N_COMP: the same for 2D with the compensated forms
 SYMMETRIC_AUTO_N_RING = 13312    # MD_SYMMETRIC_AUTO_N_RING: the same for the Ring with the FP32 forms
 SYMMETRIC_AUTO_N_RING64 = 10240  # MD_SYMMETRIC_AUTO_N_RING64: the same for the Ring with FP64
+# MD_EPS_*: the softening each pair model and precision accepts (md_init)
+EPS_MIN_2D_FP64, EPS_MAX_2D_FP64 = 1e-150, 1e150
+EPS_MIN_2D_FP32 = 1e-30
+EPS_MIN_RING_FP64 = 1e-12
+EPS_MIN_RING_FP32 = 1e-25
+EPS_MAX_FP32 = 1e30
 
 MODEL_NAMES = {HMF: "hmf", RING: "ring", GRAV2D: "grav2d"}
 PREC_NAMES = {FP64: "fp64", MIXED: "mixed", MIXED_KAHAN: "mixed_kahan",

@@ -94,6 +94,51 @@ def test_init_rejects_bad_arguments(args, expect):
     assert st == expect and h is None
 
 
+def test_eps_ranges_match_the_header():
+    txt = open(os.path.join(ROOT, "include", "md.h")).read()
+    macros = dict(re.findall(r"#define MD_(EPS_[A-Z0-9_]+)\s+(\S+)", txt))
+    assert len(macros) == 6, macros
+    for name, value in macros.items():
+        assert getattr(md, name) == float(value), name
+
+
+# (model, prec, eps): each side of every bound of the accepted softening
+EPS_CASES = [
+    (md.GRAV2D, md.FP64, md.EPS_MIN_2D_FP64, md.EPS_MAX_2D_FP64),
+    (md.GRAV2D, md.MIXED, md.EPS_MIN_2D_FP32, md.EPS_MAX_FP32),
+    (md.GRAV2D, md.MIXED_KAHAN, md.EPS_MIN_2D_FP32, md.EPS_MAX_FP32),
+    (md.GRAV2D, md.MIXED_PAIRF64, md.EPS_MIN_2D_FP32, md.EPS_MAX_FP32),
+    (md.RING, md.FP64, md.EPS_MIN_RING_FP64, None),
+    (md.RING, md.MIXED, md.EPS_MIN_RING_FP32, md.EPS_MAX_FP32),
+    (md.RING, md.MIXED_KAHAN, md.EPS_MIN_RING_FP32, md.EPS_MAX_FP32),
+]
+
+
+@pytest.mark.parametrize("model,prec,lo,hi", EPS_CASES)
+def test_eps_range_is_enforced(model, prec, lo, hi):
+    """Softening below (or above) the range of a pair form is MD_EINVAL from md_init,
+    md_batch_init and md_force_noalloc, before any device work; the bounds
+    themselves pass validation (on a machine without a GPU the call then stops at
+    the device, not at the argument)."""
+    import numpy as np
+    lib = _lib()
+    bad = [lo * 0.5] + ([hi * 2.0] if hi else [])
+    good = [lo] + ([hi] if hi else [1e200])
+    off = np.array([0, 10, 20], dtype=np.int64)
+    h = ctypes.c_void_p()
+    for eps in bad:
+        assert _init(lib, model, prec, 100, eps)[0] == md.EINVAL, eps
+        e2 = np.array([0.01 if model == md.RING else 1e-3, eps])
+        assert lib.md_batch_init(ctypes.byref(h), model, prec, 2, off.ctypes.data, e2.ctypes.data, None, 256,
+                                 1 << 40) == md.EINVAL, eps
+        assert lib.md_force_noalloc(model, prec, 100, eps, None, 256, 256) == md.EINVAL, eps
+    for eps in good:
+        st, hh = _init(lib, model, prec, 100, eps)
+        assert st != md.EINVAL, eps
+        if st == md.OK:
+            lib.md_destroy(hh)
+
+
 def test_init_rejects_bad_workspace():
     lib = _lib()
     need = md.md_workspace_bytes(md.GRAV2D, md.MIXED, 1000)

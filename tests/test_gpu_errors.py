@@ -12,6 +12,9 @@ operands under graph capture.
     are written by every operand refresh: a context whose first symmetric call is
     captured into a graph, never replayed, and then run eagerly gives the
     oracle's forces from a workspace that starts as NaN bytes.
+  * The softening range (MD_EPS_*): at either end of it, with particles at the
+    same position or angle, every launch form gives finite forces, steps and
+    energies.
 """
 import ctypes
 import os
@@ -175,3 +178,38 @@ def test_symmetric_pads_when_first_call_is_captured(model, prec, eps):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(host(fg), fh)
     ctx.close()
+
+
+# (model, prec, lo, hi) of the accepted softening; hi None: no upper bound
+EPS_BOUNDS = [
+    (GRAV2D, md.FP64, md.EPS_MIN_2D_FP64, md.EPS_MAX_2D_FP64),
+    (GRAV2D, md.MIXED, md.EPS_MIN_2D_FP32, md.EPS_MAX_FP32),
+    (GRAV2D, md.MIXED_KAHAN, md.EPS_MIN_2D_FP32, md.EPS_MAX_FP32),
+    (RING, md.FP64, md.EPS_MIN_RING_FP64, None),
+    (RING, md.MIXED, md.EPS_MIN_RING_FP32, md.EPS_MAX_FP32),
+]
+
+
+@pytest.mark.parametrize("model,prec,lo,hi", EPS_BOUNDS)
+@pytest.mark.parametrize("launch", [md.LAUNCH_STAGED, md.LAUNCH_FUSED, md.LAUNCH_SYMMETRIC])
+def test_eps_bounds_keep_every_form_finite(model, prec, lo, hi, launch):
+    """At the smallest and largest softening a form accepts, a state whose first 512
+    particles reappear at 1024 (other tiles of the symmetric form) and at 513
+    (the same tile, the same j pairs of the 2D FP64 reciprocal) gives finite
+    forces, positions, momenta and energies in every launch form."""
+    n = 4096
+    q, p = inputs.uniform_state(model, n, seed=77)
+    q[:, 1024:1536] = q[:, :512]
+    q[:, 513:1025] = q[:, :512]
+    for eps in (lo, hi if hi else 1e200):
+        ctx = md.md_init(model, prec, n, eps)
+        md.md_set_launch(ctx, launch)
+        qd, pd = dev(q), dev(p)
+        f = torch.empty_like(qd)
+        md.md_force(ctx, qd, f)
+        assert torch.isfinite(f).all(), (eps, "force")
+        md.md_step(ctx, qd, pd, f, 1e-3, 2)
+        e = md.md_energy(ctx, qd, pd)
+        for name, t in (("q", qd), ("p", pd), ("f", f), ("energy", e)):
+            assert torch.isfinite(t).all(), (eps, name)
+        ctx.close()
