@@ -453,6 +453,27 @@ def test_random_symmetric_ensembles_match_oracle(prec, sizes, seed):
 
 # ------------------------------------------------------- coincident angles --
 
+def test_ring_fp64_symmetric_coincident_angles():
+    """Ring FP64, symmetric launch: a tile pair forms eq. 9's numerator
+    sin ti cos tj - cos ti sin tj as one product and one FMA, so for two particles
+    at exactly the same angle in different tiles it is the rounding error of
+    cos t sin t, at most 2^-53 |cos t sin t|, instead of 0; u = 1 + eps - cos 0 is
+    eps to within a few ulp of 1.  Each such pair adds + on the lower tile's
+    particle and - on the higher one's, with the prefactor 1/(2 sqrt2 N), so in an
+    all-equal state (whose forces vanish) no force exceeds
+    (N - 1)/(2 sqrt2 N) 2^-53 |cos t sin t| eps^{-3/2}.  The staged form gives
+    exactly 0."""
+    n, eps, th = 12_288, 0.01, 0.7
+    bound = (n - 1) / (2 * np.sqrt(2) * n) * 2.0 ** -53 * abs(np.cos(th) * np.sin(th)) * (eps * (1 - 1e-12)) ** -1.5
+    q = np.full((1, n), th)
+    fs = _force(q, md.LAUNCH_SYMMETRIC, md.FP64, RING, eps)
+    ft = _force(q, md.LAUNCH_STAGED, md.FP64, RING, eps)
+    print(f"all-equal state FP64: max |f| symmetric {np.abs(fs).max():.3e} (bound {bound:.3e}), "
+          f"staged {np.abs(ft).max():.1e}")
+    assert np.all(ft == 0.0)
+    assert np.abs(fs).max() <= 1.01 * bound
+
+
 def test_ring_fp32_symmetric_coincident_angles():
     """Ring FP32 forms, symmetric launch: a tile pair forms the half-angle
     numerator a = 2 sin(d/2) as one product and one FMA (one rounding fewer than
