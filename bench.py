@@ -249,7 +249,7 @@ RING_N = 2048
 RING_EPS = 0.01
 RING_DT = 0.05
 RING_FLOPS_PER_PAIR = 11          # eq. 9 in FP64, plus one rsqrt
-RING_FP64_CYCLES_PER_PAIR = 13 * 4.6 + 16.0
+RING_FP64_CYCLES_PER_PAIR = 12 * 4.6 + 16.0
 LAUNCH_FLOOR_US = 1.55
 kWAVE = 64
 PEAK_HBM_GBS = 8000.0
@@ -344,7 +344,7 @@ def ring_workload(md, torch, args):
     # roofline of the FP64 pair (fused) kernel: 11 flops + 1 rsqrt per ordered pair (eq. 9:
     # 3 for the numerator, 4 for 1 + eps - cos d, 2 for the cube, 2 to accumulate); at
     # this N it is bound by latency, so the kernel time is set beside two floors: the
-    # VALU floor of its instruction mix (13 FP64 VALU of 4.6 cycles + v_rsq_f64 of 16
+    # VALU floor of its instruction mix (12 FP64 VALU of 4.6 cycles + v_rsq_f64 of 16
     # cycles per pair and wavefront, measured costs) and the gap between back-to-back
     # launches (1.55 us measured for empty kernels)
     k_s = fp["kernel_us_avg"] * 1e-6
