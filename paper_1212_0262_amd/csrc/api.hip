@@ -47,9 +47,9 @@ bool prec_ok(int model, int prec)
 bool model_ok(int model) { return model == MD_HMF || model == MD_RING || model == MD_GRAV2D; }
 
 // The softening each pair form takes without an overflow, a non-normal number or a
-// negative square-root argument in its terms, for any positions: 2D FP64 adds two
-// terms with one reciprocal of s_a s_b (each s >= eps), which has to stay a normal
-// FP64 number; the FP32 forms round eps to FP32 and divide by it (2D) or raise
+// negative square-root argument in its terms, for any positions: 2D FP64 adds up to
+// four terms with one reciprocal of the product of their s >= eps, which has to
+// stay a normal FP64 number; the FP32 forms round eps to FP32 and divide by it (2D) or raise
 // 2 eps to the -3/2 (the Ring's half-angle form); eq. 9 in FP64 forms
 // u = 1 + eps - cos d, which must stay positive for two particles at the same
 // angle (1 + eps is rounded to 2^-53).  MD_HMF has no softening.

@@ -340,13 +340,14 @@ __host__ __device__ constexpr T sym_pad()
 
 // nblk (1 .. kSymTile / kWave, uniform across the block): the 64-j blocks of the j
 // tile to stream; a ragged tile stops after its last block that holds a particle.
-// SHARE (2D): the lane's i come in twos against the same j, and each two take one
-// reciprocal: with s0, s1 their |r_i - r_j|^2 + eps and R = 1/(s0 s1), the weights
-// are 1/s0 = R s1 and 1/s1 = R s0 (three multiplies in place of a reciprocal; each
-// weight carries about 2 ulp instead of 1).  Needs s0 s1 finite and nonzero (in
-// FP64: particles closer than about 1e77 to each other, eps above 1e-154) and no
-// pad particle among the pair's operands (the pads' s would overflow the
-// product), so blocks that hold pads take SHARE = false.
+// SHARE (2D): the lane's 4 i take one reciprocal against the same j: with s0 .. s3
+// their |r_i - r_j|^2 + eps, P01 = s0 s1, P23 = s2 s3 and R = 1/(P01 P23), the
+// weights are 1/s0 = (R P23) s1, 1/s1 = (R P23) s0, 1/s2 = (R P01) s3 and
+// 1/s3 = (R P01) s2 (nine multiplies and one refined reciprocal in place of four;
+// each weight carries about 5 ulp instead of 1).  Needs s0 s1 s2 s3 a normal FP64
+// number (particles closer than about 1e38 to each other, eps in [1e-75, 1e75],
+// the range md_init takes) and no pad particle among the operands (the pads' s
+// would overflow the product), so blocks that hold pads take SHARE = false.
 template <int MODEL, typename T, typename A, bool SYM, bool SHARE = false, typename Load, typename JSum>
 __device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[kSymIpl], T e, int lane, int nblk,
                                          Load &&load, JSum &&jsum, A (&acc)[MODEL == MD_GRAV2D ? 2 : 1][kSymIpl])
@@ -370,7 +371,6 @@ __device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[k
                 }
             }
             if constexpr (MODEL == MD_GRAV2D && SHARE) {
-                static_assert(kSymIpl % 2 == 0, "the i of a lane pair up");
                 T dx[kSymIpl], dy[kSymIpl], w[kSymIpl];
 #pragma unroll
                 for (int k = 0; k < kSymIpl; ++k) {
@@ -378,12 +378,16 @@ __device__ __forceinline__ void sym_tile(const T (&u0)[kSymIpl], const T (&u1)[k
                     dy[k] = v1 - u1[k];
                     w[k] = fma_(dx[k], dx[k], fma_(dy[k], dy[k], e));
                 }
-#pragma unroll
-                for (int k = 0; k < kSymIpl; k += 2) {
-                    const T r = rcp_(w[k] * w[k + 1]);
-                    const T s0 = w[k];
-                    w[k] = r * w[k + 1];
-                    w[k + 1] = r * s0;
+                static_assert(kSymIpl == 4, "one reciprocal for the lane's 4 i");
+                {
+                    const T p01 = w[0] * w[1], p23 = w[2] * w[3];
+                    const T r = rcp_(p01 * p23);
+                    const T r01 = r * p23, r23 = r * p01;
+                    const T s0 = w[0], s2 = w[2];
+                    w[0] = r01 * w[1];
+                    w[1] = r01 * s0;
+                    w[2] = r23 * w[3];
+                    w[3] = r23 * s2;
                 }
 #pragma unroll
                 for (int k = 0; k < kSymIpl; ++k) {

@@ -30,7 +30,7 @@ SYMMETRIC_AUTO_N_COMP = 15360    # MD_SYMMETRIC_AUTO_N_COMP: the same for 2D wit
 SYMMETRIC_AUTO_N_RING = 13312    # MD_SYMMETRIC_AUTO_N_RING: the same for the Ring with the FP32 forms
 SYMMETRIC_AUTO_N_RING64 = 10240  # MD_SYMMETRIC_AUTO_N_RING64: the same for the Ring with FP64
 # MD_EPS_*: the softening each pair model and precision accepts (md_init)
-EPS_MIN_2D_FP64, EPS_MAX_2D_FP64 = 1e-150, 1e150
+EPS_MIN_2D_FP64, EPS_MAX_2D_FP64 = 1e-75, 1e75
 EPS_MIN_2D_FP32 = 1e-30
 EPS_MIN_RING_FP64 = 1e-12
 EPS_MIN_RING_FP32 = 1e-25
