@@ -50,7 +50,7 @@ __device__ __forceinline__ void hvp_2d(T xi, T yi, T wxi, T wyi, T xj, T yj, T w
 // 1/s_b = s_a / (s_a s_b), three multiplies in place of a reciprocal (FP64: the
 // refined reciprocal is a quarter-rate seed and three FMAs).  Each 1/s carries
 // about 2 ulp instead of 1; s_a s_b stays finite and nonzero for particles closer
-// than about 1e77 and eps above 1e-154.
+// than about 1e77 and the eps md_init takes.
 template <typename T, typename A>
 __device__ __forceinline__ void hvp_2d_two(T xi, T yi, T wxi, T wyi, T xa, T ya, T wxa, T wya, T xb, T yb, T wxb,
                                            T wyb, T eps, A &ax, A &ay)
@@ -220,8 +220,9 @@ __global__ __launch_bounds__(256) void k_hvp_ring(const T *__restrict__ cs, cons
 // pair, i side only.  A wavefront holds 4 i per lane; tile b streams through in 16
 // blocks of 64 j, and at step s lane l meets j = (l + s) mod 64: the j operands
 // (x, y, wx, wy) and the j-side sums move one lane per step through ds_bpermute.
-// The i of a lane come in twos with one reciprocal (hvp_2d_two's scheme: SHARE),
-// except where the tile holds pads, whose s would overflow the product.
+// The 4 i of a lane take one reciprocal (SHARE: the force's scheme, sym_tile in
+// pair_terms.h), except where the tile holds pads, whose s would overflow the
+// product.
 //   x, y, wx, wy: this lane's 4 i;  e: eps;
 //   load(blk, xj, yj, wxj, wyj): this lane's j of 64-j block blk (lane l: j = l);
 //   jsum(blk, m, sj): the j-side sums of the block (sj belongs to j = m of it);
@@ -258,14 +259,16 @@ __device__ __forceinline__ void sym_tile_hvp(const double (&x)[kSymIpl], const d
                 dy[k] = y[k] - yj;
                 inv[k] = fma_(dx[k], dx[k], fma_(dy[k], dy[k], e));
             }
-            if constexpr (SHARE) {
-#pragma unroll
-                for (int k = 0; k < kSymIpl; k += 2) {
-                    const double r = rcp_(inv[k] * inv[k + 1]);
-                    const double s0 = inv[k];
-                    inv[k] = r * inv[k + 1];
-                    inv[k + 1] = r * s0;
-                }
+            if constexpr (SHARE) {  // one reciprocal for the 4 i, as the force's (pair_terms.h)
+                static_assert(kSymIpl == 4, "one reciprocal for the lane's 4 i");
+                const double p01 = inv[0] * inv[1], p23 = inv[2] * inv[3];
+                const double r = rcp_(p01 * p23);
+                const double r01 = r * p23, r23 = r * p01;
+                const double s0 = inv[0], s2 = inv[2];
+                inv[0] = r01 * inv[1];
+                inv[1] = r01 * s0;
+                inv[2] = r23 * inv[3];
+                inv[3] = r23 * s2;
             } else {
 #pragma unroll
                 for (int k = 0; k < kSymIpl; ++k) inv[k] = rcp_(inv[k]);
