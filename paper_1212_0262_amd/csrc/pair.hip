@@ -632,8 +632,13 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
             else ring_term(a0[k], a1[k], x, y, e, acc0[k]);
         }
     };
-    // 2D FP64: the j in twos from the range start, as the staged kernel (grav_j_range)
-    constexpr bool TWO = MODEL == MD_GRAV2D && kPairTwo<T>;
+    // 2D FP64: the j in fours from the start of each jtile, then a last two and a
+    // last one, as the staged kernel (grav_j_range)
+    constexpr bool SHARE = MODEL == MD_GRAV2D && kPairShare<T>;
+    auto term4 = [&](const T *x, const T *y) {
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) pair_2d_four(a0[k], a1[k], x, y, e, acc0[k], acc1[k]);
+    };
     auto term2 = [&](T xa, T ya, T xb, T yb) {
 #pragma unroll
         for (int k = 0; k < IPL; ++k) pair_2d_two(a0[k], a1[k], xa, ya, xb, yb, e, acc0[k], acc1[k]);
@@ -681,17 +686,30 @@ __global__ __launch_bounds__(1024) void k_fused(const T *__restrict__ in, void *
         const T *w0 = win + g * WS + off;
         const T *w1 = win + (L + g) * WS + off;
         if (t + 16 <= len) {
-            if constexpr (TWO) {
+            if constexpr (SHARE) {
 #pragma unroll
-                for (int u = 0; u < 16; u += 2) term2(w0[u], w1[u], w0[u + 1], w1[u + 1]);
+                for (int u = 0; u < 16; u += 4) {
+                    const T xq[4] = {w0[u], w0[u + 1], w0[u + 2], w0[u + 3]};
+                    const T yq[4] = {w1[u], w1[u + 1], w1[u + 2], w1[u + 3]};
+                    term4(xq, yq);
+                }
             } else {
 #pragma unroll
                 for (int u = 0; u < 16; ++u) term(w0[u], w1[u]);
             }
         } else {
             int u = 0;
-            if constexpr (TWO)
-                for (; u + 2 <= len - t; u += 2) term2(w0[u], w1[u], w0[u + 1], w1[u + 1]);
+            if constexpr (SHARE) {
+                for (; u + 4 <= len - t; u += 4) {
+                    const T xq[4] = {w0[u], w0[u + 1], w0[u + 2], w0[u + 3]};
+                    const T yq[4] = {w1[u], w1[u + 1], w1[u + 2], w1[u + 3]};
+                    term4(xq, yq);
+                }
+                if (u + 2 <= len - t) {
+                    term2(w0[u], w1[u], w0[u + 1], w1[u + 1]);
+                    u += 2;
+                }
+            }
             for (; u < len - t; ++u) term(w0[u], w1[u]);
         }
         if (t < len && ((t + 16) % jtile == 0 || t + 16 >= len)) {

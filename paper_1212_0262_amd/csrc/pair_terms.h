@@ -131,15 +131,44 @@ __device__ __forceinline__ void pair_2d_two(T xi, T yi, T xa, T ya, T xb, T yb, 
     ay.add(dyb, wb);
 }
 
-// Whether the 2D terms of operand type T go in twos (pair_2d_two).
+// 2D, four j (a, b, c, d) against the same i with one reciprocal: with P = s_a s_b,
+// Q = s_c s_d and R = 1/(P Q), the weights are 1/s_a = (R Q) s_b, 1/s_b = (R Q) s_a,
+// 1/s_c = (R P) s_d and 1/s_d = (R P) s_c (nine multiplies and one reciprocal in
+// place of four; each weight carries about 5 ulp).  The product of the four s must
+// be a normal number: in FP64, eps in the range md_init takes and particles closer
+// than about 1e38 to each other.  The terms are added in the order a, b, c, d.
+template <typename T, typename A>
+__device__ __forceinline__ void pair_2d_four(T xi, T yi, const T *xj, const T *yj, T eps, A &ax, A &ay)
+{
+    T dx[4], dy[4], s[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dx[k] = xi - xj[k];
+        dy[k] = yi - yj[k];
+        s[k] = fma_(dx[k], dx[k], fma_(dy[k], dy[k], eps));
+    }
+    const T p01 = s[0] * s[1], p23 = s[2] * s[3];
+    const T r = rcp_(p01 * p23);
+    const T r01 = r * p23, r23 = r * p01;
+    const T w[4] = {r01 * s[1], r01 * s[0], r23 * s[3], r23 * s[2]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ax.add(dx[k], w[k]);
+        ay.add(dy[k], w[k]);
+    }
+}
+
+// Whether the 2D terms of operand type T share reciprocals: the j in fours
+// (pair_2d_four), then twos (pair_2d_two), then one by one.
 template <typename T>
-constexpr bool kPairTwo = sizeof(T) == 8;
+constexpr bool kPairShare = sizeof(T) == 8;
 
 // The 2D terms of j in [j0, j1) for each lane's IPL i, j ascending, the
 // accumulators folded every jtile j from j0 (jtile a multiple of 16).  The j
-// operands are wave-uniform (scalar loads).  With kPairTwo<T> the j go in twos
-// (j0 + 2m, j0 + 2m + 1) and an odd last one alone: the pairing every 2D staged,
-// fused and batched kernel shares, so that they agree bit for bit.
+// operands are wave-uniform (scalar loads).  With kPairShare<T> the j of each
+// jtile go in fours from its start (j + 4m), then a last two and a last one as
+// they remain: the grouping every 2D staged, fused and batched kernel shares, so
+// that they agree bit for bit.
 template <typename T, typename A, int IPL>
 __device__ __forceinline__ void grav_j_range(const T *__restrict__ xs, const T *__restrict__ ys, int j0, int j1,
                                              int jtile, T eps, const T (&xi)[IPL], const T (&yi)[IPL],
@@ -149,12 +178,13 @@ __device__ __forceinline__ void grav_j_range(const T *__restrict__ xs, const T *
         const int je = min(j1, jt + jtile);
         int j = jt;
         for (; j + 8 <= je; j += 8) {
-            if constexpr (kPairTwo<T>) {
+            if constexpr (kPairShare<T>) {
 #pragma unroll
-                for (int u = 0; u < 8; u += 2) {
-                    const T xa = xs[j + u], ya = ys[j + u], xb = xs[j + u + 1], yb = ys[j + u + 1];
+                for (int u = 0; u < 8; u += 4) {
+                    const T xq[4] = {xs[j + u], xs[j + u + 1], xs[j + u + 2], xs[j + u + 3]};
+                    const T yq[4] = {ys[j + u], ys[j + u + 1], ys[j + u + 2], ys[j + u + 3]};
 #pragma unroll
-                    for (int k = 0; k < IPL; ++k) pair_2d_two(xi[k], yi[k], xa, ya, xb, yb, eps, ax[k], ay[k]);
+                    for (int k = 0; k < IPL; ++k) pair_2d_four(xi[k], yi[k], xq, yq, eps, ax[k], ay[k]);
                 }
             } else {
 #pragma unroll
@@ -166,11 +196,19 @@ __device__ __forceinline__ void grav_j_range(const T *__restrict__ xs, const T *
                 }
             }
         }
-        if constexpr (kPairTwo<T>) {
-            for (; j + 2 <= je; j += 2) {
+        if constexpr (kPairShare<T>) {
+            if (j + 4 <= je) {
+                const T xq[4] = {xs[j], xs[j + 1], xs[j + 2], xs[j + 3]};
+                const T yq[4] = {ys[j], ys[j + 1], ys[j + 2], ys[j + 3]};
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) pair_2d_four(xi[k], yi[k], xq, yq, eps, ax[k], ay[k]);
+                j += 4;
+            }
+            if (j + 2 <= je) {
                 const T xa = xs[j], ya = ys[j], xb = xs[j + 1], yb = ys[j + 1];
 #pragma unroll
                 for (int k = 0; k < IPL; ++k) pair_2d_two(xi[k], yi[k], xa, ya, xb, yb, eps, ax[k], ay[k]);
+                j += 2;
             }
         }
         for (; j < je; ++j) {
