@@ -111,11 +111,10 @@ size_t md_workspace_bytes(int model, int prec, int64_t n);
  * loses its normal range or takes the square root of a negative number, for any
  * positions.  2D in FP64 adds up to four pair terms with one reciprocal of the
  * product of their |r_i - r_j|^2 + eps, which must stay a normal FP64 number
- * (particles closer than about 1e38 to each other); the FP32
- * forms round eps to FP32 (the Ring's half-angle form raises 2 eps to the -3/2);
- * the Ring in FP64 (eq. 9) forms 1 + eps - cos(ti - tj), which has to stay
- * positive for two particles at the same angle.  No upper bound for the Ring in
- * FP64.
+ * (particles closer than about 1e38 to each other); the FP32 forms round eps to
+ * FP32 (the Ring's half-angle form raises 2 eps to the -3/2); the Ring in FP64
+ * (eq. 9) forms 1 + eps - cos(ti - tj), which has to stay positive for two
+ * particles at the same angle.  No upper bound for the Ring in FP64.
  */
 #define MD_EPS_MIN_2D_FP64 1e-75
 #define MD_EPS_MAX_2D_FP64 1e75
