@@ -68,19 +68,24 @@ def test_batch_force_matches_oracle_per_realization(model, eps, prec):
         check(f"ensemble model={model} prec={prec} N_b={SIZES[b]}", rel_inf(fg[b], fo), force_tol(model, prec, SIZES[b]))
 
 
+@pytest.mark.parametrize("prec", [md.MIXED, md.FP64])
 @pytest.mark.parametrize("model,eps", [(RING, 0.01), (GRAV2D, 1e-3)])
-def test_batch_equals_single_system_bitwise(model, eps):
+def test_batch_equals_single_system_bitwise(model, eps, prec):
     """With one j chunk per realization and the same lanes, a batched realization
-    is the single-system sum in the same order: bit-identical forces."""
-    q, _, off = ensemble(model, [300, 1000, 777], seed=41)
-    ctx = md.md_batch_init(model, md.MIXED, off, eps)
+    is the single-system sum in the same order: bit-identical forces.  The sizes
+    leave 44, 104, 9, 107 and 110 j in the last j-tile of 128, so the 2D FP64
+    grouping of the j in fours (one reciprocal each) ends on a four, on none, on a
+    one, on a two and a one, and on a four and a two."""
+    q, _, off = ensemble(model, [300, 1000, 777, 1003, 1006], seed=41)
+    ctx = md.md_batch_init(model, prec, off, eps)
     md.md_set_tiles(ctx, 1, 4, 1, 128)
+    md.md_set_launch(ctx, md.LAUNCH_STAGED)
     qd = dev(q)
     f = torch.empty_like(qd)
     md.md_force(ctx, qd, f)
     fg = split(host(f), off)
     for b, qb in enumerate(split(q, off)):
-        s = md.md_init(model, md.MIXED, qb.shape[1], eps)
+        s = md.md_init(model, prec, qb.shape[1], eps)
         md.md_set_tiles(s, 1, 4, 1, 128)
         qs = dev(qb)
         fs = torch.empty_like(qs)
