@@ -46,21 +46,27 @@ __device__ __forceinline__ void hvp_2d(T xi, T yi, T wxi, T wyi, T xj, T yj, T w
     hvp_2d_add(dx, dy, rcp_(fma_(dx, dx, fma_(dy, dy, eps))), wxi, wyi, wxj, wyj, ax, ay);
 }
 
-// The terms of two j (a, then b) with one reciprocal: 1/s_a = s_b / (s_a s_b) and
-// 1/s_b = s_a / (s_a s_b), three multiplies in place of a reciprocal (FP64: the
-// refined reciprocal is a quarter-rate seed and three FMAs).  Each 1/s carries
-// about 2 ulp instead of 1; s_a s_b stays finite and nonzero for particles closer
-// than about 1e77 and the eps md_init takes.
+// The terms of four j with one reciprocal, the weights as the force's pair_2d_four
+// (pair_terms.h: nine multiplies and one refined FP64 reciprocal in place of four;
+// the product of the four |r_i - r_j|^2 + eps stays a normal number for the eps
+// md_init takes and particles closer than about 1e38); added in the order of the j.
 template <typename T, typename A>
-__device__ __forceinline__ void hvp_2d_two(T xi, T yi, T wxi, T wyi, T xa, T ya, T wxa, T wya, T xb, T yb, T wxb,
-                                           T wyb, T eps, A &ax, A &ay)
+__device__ __forceinline__ void hvp_2d_four(T xi, T yi, T wxi, T wyi, const T *xj, const T *yj, const T *wxj,
+                                            const T *wyj, T eps, A &ax, A &ay)
 {
-    const T dxa = xi - xa, dya = yi - ya, dxb = xi - xb, dyb = yi - yb;
-    const T sa = fma_(dxa, dxa, fma_(dya, dya, eps));
-    const T sb = fma_(dxb, dxb, fma_(dyb, dyb, eps));
-    const T r = rcp_(sa * sb);
-    hvp_2d_add(dxa, dya, r * sb, wxi, wyi, wxa, wya, ax, ay);
-    hvp_2d_add(dxb, dyb, r * sa, wxi, wyi, wxb, wyb, ax, ay);
+    T dx[4], dy[4], s[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dx[k] = xi - xj[k];
+        dy[k] = yi - yj[k];
+        s[k] = fma_(dx[k], dx[k], fma_(dy[k], dy[k], eps));
+    }
+    const T p01 = s[0] * s[1], p23 = s[2] * s[3];
+    const T r = rcp_(p01 * p23);
+    const T r01 = r * p23, r23 = r * p01;
+    const T inv[4] = {r01 * s[1], r01 * s[0], r23 * s[3], r23 * s[2]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hvp_2d_add(dx[k], dy[k], inv[k], wxi, wyi, wxj[k], wyj[k], ax, ay);
 }
 
 // Ring: adds phi''(d) (w_i - w_j) / pref, d = ti - tj.
@@ -121,16 +127,15 @@ __global__ __launch_bounds__(256) void k_hvp_2d(const T *__restrict__ xs, const 
         int j = jt;
         for (; j + 4 <= je; j += 4) {
             if constexpr (sizeof(T) == 8) {
-                // FP64: one reciprocal for two j (measured FP32: the shared form does
+                // FP64: one reciprocal for four j (measured FP32: a shared form does
                 // not pay, its multiplies costing what the FP32 reciprocal does)
+                const T xq[4] = {xs[j], xs[j + 1], xs[j + 2], xs[j + 3]};
+                const T yq[4] = {ys[j], ys[j + 1], ys[j + 2], ys[j + 3]};
+                const T wxq[4] = {wxs[j], wxs[j + 1], wxs[j + 2], wxs[j + 3]};
+                const T wyq[4] = {wys[j], wys[j + 1], wys[j + 2], wys[j + 3]};
 #pragma unroll
-                for (int u = 0; u < 4; u += 2) {
-                    const T xa = xs[j + u], ya = ys[j + u], wxa = wxs[j + u], wya = wys[j + u];
-                    const T xb = xs[j + u + 1], yb = ys[j + u + 1], wxb = wxs[j + u + 1], wyb = wys[j + u + 1];
-#pragma unroll
-                    for (int k = 0; k < IPL; ++k)
-                        hvp_2d_two(xi[k], yi[k], wxi[k], wyi[k], xa, ya, wxa, wya, xb, yb, wxb, wyb, eps, ax[k], ay[k]);
-                }
+                for (int k = 0; k < IPL; ++k)
+                    hvp_2d_four(xi[k], yi[k], wxi[k], wyi[k], xq, yq, wxq, wyq, eps, ax[k], ay[k]);
             } else {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
