@@ -278,10 +278,11 @@ __device__ __forceinline__ void sym_block(const T *__restrict__ r0, const T *__r
             __syncthreads();
         }
     };
-    // 2D FP64: one reciprocal for two pairs (SHARE), except in a j tile that holds
-    // pads (b is never below a).  Measured at N = 262,144: 16.36 -> 14.76 ms per
-    // force evaluation.  The FP32 forms keep one reciprocal a pair: there the shared
-    // form measured 1.5% slower (7.35 -> 7.45 ms), its three multiplies costing
+    // 2D FP64: one reciprocal for a lane's four i against each j (SHARE), except in
+    // a j tile that holds pads (b is never below a).  Measured at N = 262,144, per
+    // force evaluation: 16.36 -> 14.76 ms with one reciprocal for two i, and 4% less
+    // again with one for four.  The FP32 forms keep one reciprocal a pair: there the
+    // shared form measured 1.5% slower (7.35 -> 7.45 ms), its multiplies costing
     // about what the FP32 reciprocal does
     constexpr bool kShare = MODEL == MD_GRAV2D && sizeof(T) == 8;
     if (!kShare || (b + 1) * TILE > n)
